@@ -1,0 +1,335 @@
+"""Pins of the CPU oracle against facts the paper and the mathematics fix.
+
+Each test names the property it pins; none re-derives a result by calling
+the oracle's own routine a second way.
+"""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_2104_09189_amd import inputs as I
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------------------
+# P-1: exact orientation sign
+
+def _frac_orient(p):
+    ax, ay, bx, by, cx, cy = (Fraction(float(v)) for v in p)
+    d = (ax - cx) * (by - cy) - (ay - cy) * (bx - cx)
+    return (d > 0) - (d < 0)
+
+
+def _adversarial_points(rng, m):
+    """Near-collinear triples: c is a rounded point of the segment a-b, or a
+    lattice point exactly on it, possibly nudged by one ulp."""
+    out = []
+    for _ in range(m):
+        kind = rng.integers(0, 4)
+        if kind == 0:   # rounding of a point on the line
+            a = rng.uniform(-1, 1, 2)
+            b = rng.uniform(-1, 1, 2)
+            t = rng.uniform(-2, 3)
+            c = a + t * (b - a)
+        elif kind == 1:  # exactly collinear dyadic lattice points
+            s = 2.0 ** -int(rng.integers(0, 40))
+            a = rng.integers(-50, 50, 2) * s
+            d = rng.integers(-7, 8, 2) * s
+            a, b, c = a, a + d, a + int(rng.integers(-5, 6)) * d
+        elif kind == 2:  # collinear lattice point nudged by one ulp
+            s = 2.0 ** -int(rng.integers(0, 30))
+            a = rng.integers(-50, 50, 2) * s
+            d = rng.integers(-7, 8, 2) * s
+            b = a + d
+            c = a + int(rng.integers(-5, 6)) * d
+            c = c.copy()
+            i = int(rng.integers(0, 2))
+            c[i] = np.nextafter(c[i], np.inf if rng.integers(0, 2) else -np.inf)
+        else:            # tiny triangles far from the origin
+            base = rng.uniform(-1e6, 1e6, 2)
+            a = base + rng.uniform(-1e-9, 1e-9, 2)
+            b = base + rng.uniform(-1e-9, 1e-9, 2)
+            c = a + rng.uniform(-2, 3) * (b - a)
+        out.append(np.concatenate([a, b, c]))
+    return np.array(out)
+
+
+def test_orient_known_signs(orc):
+    # counter-clockwise, clockwise and collinear reference triples
+    assert orc.orient_sign((0, 0), (1, 0), (0, 1)) == 1
+    assert orc.orient_sign((0, 0), (0, 1), (1, 0)) == -1
+    assert orc.orient_sign((0, 0), (1, 1), (3, 3)) == 0
+    assert orc.orient_sign((0.1, 0.1), (0.3, 0.3), (0.2, 0.2)) == _frac_orient((0.1, 0.1, 0.3, 0.3, 0.2, 0.2))
+    # c just left / right of the x axis
+    assert orc.orient_sign((0, 0), (1, 0), (0.5, 1e-300)) == 1
+    assert orc.orient_sign((0, 0), (1, 0), (0.5, -5e-324)) == -1
+
+
+def test_orient_matches_rationals_random_and_adversarial(orc):
+    rng = np.random.default_rng(11)
+    pts = np.concatenate([rng.uniform(-1, 1, (3000, 6)), _adversarial_points(rng, 6000)])
+    want = np.array([_frac_orient(p) for p in pts], dtype=np.int8)
+    got_f = orc.orient_sign_batch(pts, use_filter=True)
+    got_x = orc.orient_sign_batch(pts, use_filter=False)
+    assert (got_x == want).all()
+    assert (got_f == want).all()
+    # the adversarial set really exercises zeros and near-zeros
+    assert (want == 0).sum() > 500
+
+
+def test_orient_symmetries(orc):
+    rng = np.random.default_rng(12)
+    pts = _adversarial_points(rng, 3000)
+    s = orc.orient_sign_batch(pts)
+    cyc = orc.orient_sign_batch(pts[:, [2, 3, 4, 5, 0, 1]])
+    swp = orc.orient_sign_batch(pts[:, [2, 3, 0, 1, 4, 5]])
+    mir = pts.copy()
+    mir[:, [1, 3, 5]] *= -1.0
+    assert (cyc == s).all()            # cyclic invariance
+    assert (swp == -s).all()           # antisymmetry
+    assert (orc.orient_sign_batch(mir) == -s).all()  # reflection flips
+    assert (orc.orient_sign_batch(pts * 2.0) == s).all()  # power-of-two scaling (exact)
+
+
+def test_orient_agrees_with_numpy_cross_when_well_separated(orc):
+    rng = np.random.default_rng(13)
+    pts = rng.uniform(-1, 1, (20000, 6))
+    a, b, c = pts[:, 0:2], pts[:, 2:4], pts[:, 4:6]
+    cr = (a - c)[:, 0] * (b - c)[:, 1] - (a - c)[:, 1] * (b - c)[:, 0]
+    big = np.abs(cr) > 1e-9
+    assert (orc.orient_sign_batch(pts)[big] == np.sign(cr[big])).all()
+
+
+# ---------------------------------------------------------------------------
+# P-2 / P-3: point location by definition
+
+def _meshes_small():
+    yield I.jittered_grid(33, 1001)
+    yield I.permute_mesh(*I.jittered_grid(17, 7), 8)
+    xy, tri = I.jittered_grid(20, 9)
+    # clockwise input for a third of the triangles
+    tri = tri.copy()
+    tri[::3] = tri[::3][:, [0, 2, 1]]
+    yield xy, tri
+
+
+def test_bucket_search_equals_full_scan(orc):
+    for xy, tri in _meshes_small():
+        rng = np.random.default_rng(tri.shape[0])
+        mid = (xy[tri[:, 0]] + xy[tri[:, 1]]) * 0.5
+        q = np.concatenate([I.random_points(3000, 1), xy, mid, xy[tri].mean(axis=1)])
+        e1, _ = orc.locate(xy, tri, q)
+        e2, _ = orc.locate(xy, tri, q, brute=True)
+        assert (e1 == e2).all()
+        assert (e1[3000:3000 + xy.shape[0]] >= 0).all()  # every vertex is found
+
+
+def test_closed_containment_counts_on_dyadic_grid(orc):
+    # unjittered 2^k grid: vertices, edge points and interior points are exact
+    n = 9
+    xy = I.grid_nodes(n)
+    tri = I.grid_triangles(n)
+    h = 1.0 / (n - 1)
+    # an interior vertex belongs to its 6 incident triangles, a corner to 1 or 2
+    assert len(orc.containers(xy, tri, (4 * h, 4 * h))) == 6
+    assert sorted(orc.containers(xy, tri, (0.0, 0.0))) == [0, 1]
+    assert len(orc.containers(xy, tri, (1.0, 0.0))) == 1
+    # a point inside a diagonal edge: the two triangles of its cell
+    c = sorted(orc.containers(xy, tri, (2.5 * h, 3.5 * h)))
+    cell = (n - 1) * 3 + 2
+    assert c == [2 * cell, 2 * cell + 1]
+    # the smallest id wins
+    e, b = orc.locate(xy, tri, np.array([[2.5 * h, 3.5 * h], [4 * h, 4 * h]]))
+    assert e[0] == 2 * cell
+    assert e[1] == min(orc.containers(xy, tri, (4 * h, 4 * h)))
+    # outside points
+    e, b = orc.locate(xy, tri, np.array([[-1e-17, 0.5], [0.5, np.nextafter(1.0, 2.0)], [np.nan, 0.5], [np.inf, 0]]))
+    assert (e == -1).all() and np.isnan(b).all()
+
+
+def test_structured_direct_location_golden(orc):
+    rows = np.loadtxt(os.path.join(GOLDEN, "structured_direct_location.txt"))
+    xy = I.grid_nodes(5, -0.5, 0.5)
+    tri = I.grid_triangles(5)
+    e, _ = orc.locate(xy, tri, rows[:, :2])
+    assert (e == rows[:, 2].astype(int) - 1).all()
+
+
+def test_structured_direct_location_random(orc):
+    # the paper's closed form on a 64 x 64 Courant grid, points off the edges
+    M = 64
+    dx = 1.0 / M
+    xy = I.grid_nodes(M + 1, -0.5, 0.5)
+    tri = I.grid_triangles(M + 1)
+    rng = np.random.default_rng(14)
+    q = rng.uniform(-0.5, 0.5, (20000, 2))
+    xi, eta = q[:, 0] + 0.5, q[:, 1] + 0.5
+    l = np.floor(xi / dx).astype(int)
+    m = np.floor(eta / dx).astype(int)
+    fx, fy = xi - l * dx, eta - m * dx
+    keep = (np.minimum(fx, fy) > 1e-9) & (np.maximum(fx, fy) < dx - 1e-9) & (np.abs(fx - fy) > 1e-9)
+    paper_1based = np.where(fx < fy, 2 * (M * m + l) + 1, 2 * (M * m + l + 1))
+    e, _ = orc.locate(xy, tri, q[keep])
+    assert keep.sum() > 19000
+    assert (e == paper_1based[keep] - 1).all()
+
+
+# ---------------------------------------------------------------------------
+# P-4: barycentric coordinates
+
+def test_barycentric_identities(orc):
+    xy, tri = I.jittered_grid(33, 1001)
+    q = I.random_points(5000, 3, 0.0, 1.0)
+    e, b = orc.locate(xy, tri, q)
+    ok = e >= 0
+    assert ok.all()
+    assert np.abs(b.sum(axis=1) - 1.0).max() < 4e-16
+    rec = np.einsum("ik,ikd->id", b, xy[tri[e]])
+    assert np.abs(rec - q).max() < 4e-16
+    assert b.min() > -1e-14
+    # at a vertex: exactly a unit vector
+    e, b = orc.locate(xy, tri, xy[:200])
+    assert set(np.unique(b)) <= {0.0, 1.0}
+    assert (b.sum(axis=1) == 1.0).all()
+
+
+# ---------------------------------------------------------------------------
+# P-5: P1 reproduces affine data, P2 reproduces quadratics
+
+def test_p1_affine_and_p2_quadratic_reproduction(orc):
+    xy, tri = I.permute_mesh(*I.jittered_grid(25, 21), 22)
+    q = I.random_points(4000, 4, 0.0, 1.0)
+    e, b = orc.locate(xy, tri, q)
+    v1 = orc.interp(1, tri, e, b, I.linear_data(xy), xy.shape[0])
+    assert np.abs(v1[:, 0] - I.linear_data(q)).max() < 2e-15
+    p2 = orc.P2Dofs(xy, tri)
+    assert p2.edges.shape[0] == xy.shape[0] + tri.shape[0] - 1  # Euler: V - E + F = 1
+    v2 = orc.interp(2, tri, e, b, I.quadratic_data(p2.xy), xy.shape[0], p2.tri_edges)
+    assert np.abs(v2[:, 0] - I.quadratic_data(q)).max() < 1e-14
+    # P1 does not reproduce the quadratic: the pin is not vacuous
+    v1q = orc.interp(1, tri, e, b, I.quadratic_data(xy), xy.shape[0])
+    assert np.abs(v1q[:, 0] - I.quadratic_data(q)).max() > 1e-5
+    # outside value
+    e2 = e.copy()
+    e2[:10] = -1
+    v = orc.interp(1, tri, e2, b, I.linear_data(xy), xy.shape[0], outside_value=-7.0)
+    assert (v[:10, 0] == -7.0).all()
+
+
+def test_p2_edge_numbering(orc):
+    tri = np.array([[0, 1, 2], [2, 1, 3]], dtype=np.int32)
+    p2 = orc.P2Dofs(np.array([[0, 0], [1, 0], [0, 1], [1, 1]], float), tri)
+    # lexicographic (min, max) pairs
+    assert p2.edges.tolist() == [[0, 1], [0, 2], [1, 2], [1, 3], [2, 3]]
+    # edge opposite local vertex k
+    assert p2.tri_edges.tolist() == [[2, 1, 0], [3, 4, 2]]
+
+
+# ---------------------------------------------------------------------------
+# P-6: feet, closed forms for affine fields
+
+def test_feet_closed_forms(orc):
+    rng = np.random.default_rng(15)
+    xy = rng.uniform(0, 1, (500, 2))
+    A = np.array([[0.3, -1.1], [0.7, 0.2]])
+    c = np.array([0.4, 0.6])
+    fld = I.affine(A[0, 0], A[0, 1], A[1, 0], A[1, 1], c[0], c[1])
+    dt = 0.037
+    E = np.eye(2)
+    q_eu = orc.feet(xy, fld, 1.0, dt, I.SCHEME_EULER)
+    q_rk = orc.feet(xy, fld, 1.0, dt, I.SCHEME_RK2)
+    want_eu = c + (xy - c) @ (E - dt * A).T
+    want_rk = c + (xy - c) @ (E - dt * A + 0.5 * dt * dt * A @ A).T
+    assert np.abs(q_eu - want_eu).max() < 1e-15
+    assert np.abs(q_rk - want_rk).max() < 1e-15
+    # solid-body rotation is the affine field with A = omega * [[0,-1],[1,0]]
+    w = 2 * math.pi
+    q_sb = orc.feet(xy, I.solid_body(w, 0.5, 0.5), 0.3, dt, I.SCHEME_RK2)
+    Aw = w * np.array([[0.0, -1.0], [1.0, 0.0]])
+    want = 0.5 + (xy - 0.5) @ (E - dt * Aw + 0.5 * dt * dt * Aw @ Aw).T
+    assert np.abs(q_sb - want).max() < 1e-14
+    # constant field: Euler and midpoint both give x - dt a
+    q_c = orc.feet(xy, I.constant(0.25, -0.5), 0.0, dt, I.SCHEME_RK2)
+    assert np.abs(q_c - (xy - dt * np.array([0.25, -0.5]))).max() < 1e-16
+
+
+def test_field_special_values(orc):
+    # swirl (period T): at (1/2, 1/4) the field is (cos(pi t / T), 0); zero on the boundary
+    for t in (0.0, 0.25, 0.5, 1.0):
+        f = orc.field(I.swirl(1.0), 0.5, 0.25, t)
+        assert abs(f[0] - math.cos(math.pi * t)) < 1e-15 and abs(f[1]) < 1e-15
+        assert np.abs(orc.field(I.swirl(1.0), 0.0, 0.37, t)).max() < 1e-15
+    f = orc.field(I.swirl(2.0), 0.5, 0.25, 1.0)
+    assert abs(f[0] - math.cos(math.pi / 2)) < 1e-15
+    # swirl is divergence free (central differences)
+    e = 1e-6
+    for (x, y) in [(0.3, 0.7), (0.61, 0.2)]:
+        fxp, fxm = orc.field(I.swirl(1.0), x + e, y, 0.1), orc.field(I.swirl(1.0), x - e, y, 0.1)
+        fyp, fym = orc.field(I.swirl(1.0), x, y + e, 0.1), orc.field(I.swirl(1.0), x, y - e, 0.1)
+        assert abs((fxp[0] - fxm[0] + fyp[1] - fym[1]) / (2 * e)) < 1e-7
+    # the rotating field of Section 4: unit norm, angle C0 |x| + C1 t
+    rf = I.paper_rot(8 * math.pi, 2 * math.pi)
+    for (x, y, t) in [(0.1, -0.2, 0.3), (0.0, 0.0, 0.7), (-0.45, 0.4, 0.0)]:
+        f = orc.field(rf, x, y, t)
+        ang = 8 * math.pi * math.hypot(x, y) + 2 * math.pi * t
+        assert abs(f[0] - math.cos(ang)) < 1e-15 and abs(f[1] - math.sin(ang)) < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# P-7 / P-8 / P-9: SL steps with exact answers and invariants
+
+def test_constant_advection_transports_affine_data_exactly(orc):
+    xy, tri = I.jittered_grid(41, 31)
+    a = np.array([0.37, -0.21])
+    dt, steps = 0.02, 6
+    fld = I.constant(*a)
+    v = orc.sl_run(xy, tri, I.linear_data(xy), fld, dt, steps, I.SCHEME_EULER)
+    want = I.linear_data(xy - steps * dt * a)
+    # the outside value enters through the inflow boundary and spreads by at
+    # most dt|a| + (one triangle diameter) per step
+    margin = steps * (dt * np.abs(a).max() + 1.5 / 40)
+    inner = np.all((xy > margin) & (xy < 1 - margin), axis=1)
+    assert inner.sum() > 200
+    assert np.abs(v[inner, 0] - want[inner]).max() < 1e-13
+
+
+def test_grid_shift_is_bit_exact(orc):
+    # feet land exactly on nodes (two zero barycentric coordinates):
+    # one step shifts the data by one column, bit for bit
+    n = 33
+    h = 1.0 / (n - 1)
+    xy = I.grid_nodes(n)
+    tri = I.grid_triangles(n)
+    v0 = I.gaussian_hill(xy, 0.4, 0.5, 0.1)[:, None]
+    v1, q, e, b = orc.sl_step(xy, tri, v0, I.constant(1.0, 0.0), 0.0, h, I.SCHEME_EULER)
+    grid0 = v0[:, 0].reshape(n, n)
+    grid1 = v1[:, 0].reshape(n, n)
+    assert (grid1[:, 1:] == grid0[:, :-1]).all()
+    assert (grid1[:, 0] == 0.0).all()  # feet left of the domain: outside value
+
+
+def test_p1_step_maximum_principle(orc):
+    xy, tri = I.jittered_grid(40, 41)
+    v0 = (I.gaussian_hill(xy, 0.5, 0.75, 0.05) - 0.3)[:, None]
+    v1, q, e, b = orc.sl_step(xy, tri, v0, I.swirl(1.0), 0.0, 0.07, I.SCHEME_RK2,
+                              outside_value=0.0)
+    assert (e >= 0).all()
+    assert v1.min() >= v0.min() - 1e-15 and v1.max() <= v0.max() + 1e-15
+
+
+def test_full_turn_error_decreases_under_refinement(orc):
+    # solid-body rotation returns the initial profile after one turn; the
+    # scheme's error (not a parity quantity) shrinks as the mesh is refined
+    # (mesh, steps) refined together: the error behaves like dt^2 + h^2/dt
+    errs = []
+    for n, steps in ((33, 20), (129, 40), (257, 80)):
+        xy, tri = I.jittered_grid(n, 1001)
+        v = orc.sl_run(xy, tri, I.gaussian_hill(xy)[:, None], I.solid_body(), 1.0 / steps, steps,
+                       I.SCHEME_RK2)
+        errs.append(np.abs(v[:, 0] - I.gaussian_hill(xy)).max())
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 0.2 * errs[0]
