@@ -1,0 +1,228 @@
+/*
+ * slwalk — characteristic-foot location and interpolation on unstructured
+ * triangular meshes, for MI355X (gfx950).
+ *
+ * Method: Cacace & Ferretti, "Efficient implementation of characteristic-
+ * based schemes on unstructured triangular grids", arXiv 2104.09189.
+ *   - semi-Lagrangian step v_i^{n+1} = I[V^n](X^Delta(x_i, t_{n+1}; t_n)),
+ *     eq. (schema_trasp);
+ *   - foot by explicit Euler backward in time, eq. (eulero), or by the
+ *     explicit midpoint rule (the "suitable ODE solver" of Section 3);
+ *   - point location by the barycentric walk of Section 2.2 (stop when all
+ *     barycentric coordinates are >= 0, else cross the edge opposite the
+ *     most negative one), started from the node's own incident triangles as
+ *     in strategy (a) of Section 3, with the incident triangle chosen by the
+ *     direction of the foot; strategy (b) (start from the previous step's
+ *     element) is available as a start mode;
+ *   - P1 interpolation with the barycentric weights (Remark after
+ *     eq. barycoords) and P2 Lagrange interpolation.
+ *
+ * Conventions shared by every call
+ *   - Indices are 0-based.  Triangle ids at this interface are always the
+ *     user's ids (the position in the tri array given to slw_mesh_upload).
+ *   - Degrees of freedom (DOFs): for P1 the nodes; for P2 the nodes followed
+ *     by the edge midpoints, edges numbered in lexicographic order of their
+ *     (min, max) user vertex pair.  DOF-indexed arrays (v_in, v_out, feet,
+ *     elem and steps of slw_locate_feet, start) follow the user's DOF order,
+ *     unless the mesh was uploaded with SLW_INTERNAL_ORDER; then they follow
+ *     the library's internal (Morton) order, obtainable with
+ *     slw_mesh_dof_order.  The internal order avoids two permutation passes
+ *     per call.
+ *   - Pointers without the _h suffix are device pointers (e.g. the
+ *     data_ptr() of a torch tensor on the context's device) and stay owned
+ *     by the caller; _h pointers are host memory.  The library owns only
+ *     what it allocates inside a handle, and frees it in the destroy/free
+ *     call.
+ *   - Coordinates, feet and barycentric coordinates use the mesh's
+ *     coordinate type (double, or float with SLW_COORDS_F32).  Values use
+ *     the vdtype given to each call (SLW_F64 or SLW_F32) and are node-major:
+ *     v[dof * k + field].
+ *   - Every call returns SLW_OK or an error code; slw_last_error() then
+ *     describes the failure (thread-local).  Outputs are unspecified after an
+ *     error.  Kernel launches are asynchronous on the context's stream: the
+ *     caller synchronises before reading outputs on the host.  A call that
+ *     returns statistics (stats_h) synchronises the stream itself.
+ *   - Location results are exact: every stop/move/outside decision uses the
+ *     exact sign of an orientation determinant (filtered floating point,
+ *     then exact expansion arithmetic), so the element returned does not
+ *     depend on the start element, the walk path, the precision mode or the
+ *     launch configuration.  When a point lies on an edge or a vertex (several
+ *     closed triangles contain it), the result is the smallest user triangle
+ *     id among them.  A point contained in no triangle gets elem = -1
+ *     ("outside"), NaN barycentric coordinates and outside_value as value.
+ *   - Exactness domain: mesh coordinates must be finite and either 0 or of
+ *     magnitude in [2^-100, 2^100] (checked at upload); query coordinates
+ *     may be any double (non-finite ones, and points outside the mesh's
+ *     bounding box, are outside).
+ *   - The mesh must be conforming (every edge shared by at most two
+ *     triangles, consistently oriented), free of zero-area triangles, and
+ *     its domain convex (one boundary loop with no reflex corner), so that
+ *     "outside" is decided exactly by a boundary edge.
+ */
+#ifndef SLWALK_H
+#define SLWALK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum slw_status {
+    SLW_OK = 0,
+    SLW_E_ARG = 1,                /* invalid argument (null, size, enum) */
+    SLW_E_MESH_INDEX = 2,         /* triangle vertex index out of range */
+    SLW_E_MESH_DEGENERATE = 3,    /* zero-area triangle or repeated vertex */
+    SLW_E_MESH_NONCONFORMING = 4, /* edge in >2 triangles, or overlapping pair */
+    SLW_E_MESH_NONCONVEX = 5,     /* boundary not one convex loop */
+    SLW_E_MESH_RANGE = 6,         /* coordinate not finite or outside the exactness domain */
+    SLW_E_HIP = 7,                /* HIP runtime error (message has the HIP error string) */
+    SLW_E_NOMEM = 8,              /* device or host allocation failed */
+    SLW_E_UNSUPPORTED = 9,        /* valid request that this build does not handle */
+    SLW_E_WALK = 10               /* a walk exceeded the hard step limit */
+} slw_status;
+
+typedef struct slw_ctx slw_ctx;
+typedef struct slw_mesh slw_mesh;
+
+/* dtype codes */
+enum { SLW_F64 = 0, SLW_F32 = 1 };
+/* foot schemes: eq. (eulero); explicit midpoint */
+enum { SLW_EULER = 0, SLW_RK2 = 1 };
+/* start modes of slw_locate_feet / slw_step */
+enum {
+    SLW_START_STEERED = 0, /* strategy (a): the DOF's incident triangle facing the foot */
+    SLW_START_GIVEN = 1,   /* start[dof] = user triangle id */
+    SLW_START_PREV = 2,    /* strategy (b): the element found for this DOF by the previous
+                              SLW_START_PREV/STEERED call on this mesh (steered on the first) */
+    SLW_START_FIXED = 3    /* every walk starts at user triangle start[0] (the paper's
+                              fixed-start baseline, Section 2.2 complexity) */
+};
+/* slw_mesh_upload flags */
+#define SLW_COORDS_F32 0x1u     /* store coordinates as float (FP32 walk, FP64/exact fallback) */
+#define SLW_P2 0x2u             /* build P2 edge DOFs */
+#define SLW_NO_REORDER 0x4u     /* keep the user's node/triangle order internally */
+#define SLW_INTERNAL_ORDER 0x8u /* DOF-indexed arrays at this interface use the internal order */
+/* slw_locate_feet flags */
+#define SLW_FEET_IN 0x1u        /* feet are an input (not computed from the field) */
+
+/* Advecting field f(x, t).  kind / parameters p[0..7]:
+ *   0 constant:     f = (p0, p1)
+ *   1 solid body:   f = p0 * (-(y - p2), x - p1)
+ *   2 swirl:        f = cos(pi t / p0) (sin^2(pi x) sin(2 pi y), -sin^2(pi y) sin(2 pi x))
+ *   3 rotating field of Section 4: f = (cos a, sin a), a = p0 |x - (p2, p3)| + p1 t
+ *   4 affine:       f = [[p0, p1], [p2, p3]] (x - (p4, p5)) + (p6, p7)            */
+typedef struct slw_field {
+    int32_t kind;
+    int32_t reserved;
+    double p[8];
+} slw_field;
+
+/* Per-call statistics (device counters copied back when stats_h != NULL). */
+typedef struct slw_stats {
+    int64_t feet;           /* feet located */
+    int64_t outside;        /* feet with no containing triangle (incl. non-finite) */
+    int64_t walk_steps;     /* element changes summed over feet (Section 2.2 walk steps) */
+    int64_t max_steps;      /* longest walk */
+    int64_t exact_tests;    /* orientation signs decided by exact arithmetic */
+    int64_t fp64_tests;     /* FP32 meshes: signs decided by the FP64 stage */
+    int64_t fallback_walks; /* walks that reached the step cap and finished randomised */
+    int64_t edge_ties;      /* feet on an edge shared by two triangles */
+    int64_t vertex_ties;    /* feet on a mesh vertex */
+    int64_t reserved[7];
+} slw_stats;
+
+typedef struct slw_mesh_info {
+    int64_t n_nodes, n_tris, n_edges, n_dofs; /* n_edges, n_dofs: P2 only (else 0, n_nodes) */
+    int64_t device_bytes;                     /* device memory held by the handle */
+    int32_t coords_f32, p2, reordered, internal_order;
+    double bbox[4];                           /* xmin, ymin, xmax, ymax */
+} slw_mesh_info;
+
+const char *slw_status_string(slw_status s);
+/* Message for the last failing call on this thread ("" if none). */
+const char *slw_last_error(void);
+
+/* Context: one device and one stream (hipStream_t as void*, NULL = the null
+ * stream).  The stream is borrowed, never destroyed by the library. */
+slw_status slw_ctx_create(int device, void *hip_stream, slw_ctx **out);
+slw_status slw_ctx_set_stream(slw_ctx *ctx, void *hip_stream);
+void slw_ctx_destroy(slw_ctx *ctx);
+
+/* Mesh upload: validates the triangulation (host arrays xy_h n x 2,
+ * tri_h nt x 3), flips clockwise triangles to counter-clockwise (the
+ * barycentric coordinates returned still follow the user's vertex order),
+ * builds the neighbour lists of Section 3 (neighbour k across the edge
+ * opposite vertex k, -1 on the boundary), the incident-triangle lists of
+ * every DOF with their edge directions (start selection), the P2 edge DOFs,
+ * and a Morton order of nodes and triangles (unless SLW_NO_REORDER), and
+ * copies the result to the device.  Synchronous. */
+slw_status slw_mesh_upload(slw_ctx *ctx, const double *xy_h, int64_t n_nodes, const int32_t *tri_h,
+                           int64_t n_tris, uint32_t flags, slw_mesh **out);
+/* The host half of slw_mesh_upload alone: the same validation and
+ * preprocessing, no device and no allocation that outlives the call.
+ * info_h (nullable) receives the sizes the upload would produce. */
+slw_status slw_mesh_check(const double *xy_h, int64_t n_nodes, const int32_t *tri_h, int64_t n_tris,
+                          uint32_t flags, slw_mesh_info *info_h);
+slw_status slw_mesh_free(slw_mesh *mesh);
+slw_status slw_mesh_get_info(const slw_mesh *mesh, slw_mesh_info *out_h);
+/* DOF coordinates (n_dofs x 2 doubles, host) in the DOF order of this
+ * interface (user order, or internal with SLW_INTERNAL_ORDER). */
+slw_status slw_mesh_dof_coords(const slw_mesh *mesh, double *xy_h);
+/* internal position -> user DOF id (n_dofs ints, host). */
+slw_status slw_mesh_dof_order(const slw_mesh *mesh, int32_t *user_of_internal_h);
+/* Step cap after which a walk switches to the randomised remembering walk
+ * (default 4096), and the hard limit that fails with SLW_E_WALK
+ * (default 1 << 22).  Either value <= 0 keeps the current one. */
+slw_status slw_mesh_set_walk_limits(slw_mesh *mesh, int32_t step_cap, int32_t hard_limit);
+
+/* General point location, the analogue of the paper's [I, B] =
+ * pointLocationBW(TBW, Q, s): m query points q (m x 2, mesh coordinate type)
+ * -> elem (m ints, user triangle ids, -1 outside), bary (m x 3 in the user's
+ * vertex order of elem, nullable), steps (m ints, element changes, nullable).
+ * start (nullable, m user triangle ids) gives each walk's first triangle;
+ * when NULL the walk starts from a bucket grid of start triangles. */
+slw_status slw_locate(slw_mesh *mesh, const void *q, int64_t m, const int32_t *start, int32_t *elem,
+                      void *bary, int32_t *steps);
+
+/* Feet of all DOFs at t_np1 with step dt (scheme SLW_EULER / SLW_RK2),
+ * located by walks started per start_mode.  feet (n_dofs x 2, nullable)
+ * receives the feet; with SLW_FEET_IN in flags it is read instead of
+ * computed (field may then be NULL).  elem, bary, steps as in slw_locate
+ * (bary and steps nullable; elem nullable too).  start is read for GIVEN
+ * (n_dofs ids) and FIXED (one id). */
+slw_status slw_locate_feet(slw_mesh *mesh, const slw_field *field, double t_np1, double dt, int scheme,
+                           int start_mode, const int32_t *start, uint32_t flags, void *feet,
+                           int32_t *elem, void *bary, int32_t *steps, slw_stats *stats_h);
+
+/* Interpolation I[V](x) at m located points (elem, bary from slw_locate or
+ * slw_locate_feet): order 1 (P1) or 2 (P2, needs an SLW_P2 mesh).  v_in is
+ * n_dofs x k, v_out m x k, both of vdtype.  elem -1 gives outside_value. */
+slw_status slw_interpolate(slw_mesh *mesh, int order, const int32_t *elem, const void *bary, int64_t m,
+                           const void *v_in, int vdtype, int k, void *v_out, double outside_value);
+
+/* One semi-Lagrangian step (Algorithm 2, one pass of its time loop), fused
+ * in one kernel: foot at t_n + dt, start selection, walk, tie rule, weights,
+ * and k values per DOF: v_out[i] = I[v_in](foot_i), outside_value for feet
+ * outside the domain.  start_mode as in slw_locate_feet (GIVEN/FIXED read
+ * start).  v_in and v_out must not overlap. */
+slw_status slw_step(slw_mesh *mesh, const slw_field *field, double t_n, double dt, int scheme, int order,
+                    int start_mode, const int32_t *start, const void *v_in, int vdtype, int k,
+                    void *v_out, double outside_value, slw_stats *stats_h);
+
+/* Permute a DOF-indexed array (n_dofs rows of row_bytes) between the user
+ * order and the internal order (to_internal != 0: user -> internal). */
+slw_status slw_permute_rows(slw_mesh *mesh, const void *src, void *dst, int64_t row_bytes, int to_internal);
+
+/* The library's orientation predicate evaluated on the host, for testing:
+ * out_h[i] = sign of orient(a, b, c) for the triple pts_h[6i .. 6i+5] =
+ * (ax, ay, bx, by, cx, cy).  mode 0: FP64 filter then exact stage (what a
+ * double mesh's walk uses); 1: exact stage alone; 2: the float pipeline on
+ * the inputs rounded to float (what a float mesh's walk uses).  Exact on
+ * the exactness domain above. */
+slw_status slw_orient_sign_host(const double *pts_h, int64_t m, int8_t *out_h, int mode);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

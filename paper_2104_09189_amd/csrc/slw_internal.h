@@ -1,0 +1,126 @@
+// Internal data layout of the library (device side and handles).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/slwalk.h"
+
+namespace slw {
+
+// Triangle record read by every walk step: the three vertex coordinates
+// (stored redundantly per triangle so that one walk step is a single
+// dependent load), the three neighbours (neighbour k across the edge opposite
+// vertex k, -1 on the boundary) and the user id.  64 bytes for double.
+struct alignas(64) GeoRec64 {
+    double2 p[3];
+    int32_t nb[3];
+    int32_t uid;
+};
+// 48 bytes for float coordinates.
+struct alignas(16) GeoRec32 {
+    float2 p[3];
+    int32_t nb[3];
+    int32_t uid;
+    int32_t pad[2];
+};
+static_assert(sizeof(GeoRec64) == 64, "GeoRec64 layout");
+static_assert(sizeof(GeoRec32) == 48, "GeoRec32 layout");
+
+// Topology record: internal vertex DOF ids (v) in the user's vertex order up
+// to the counter-clockwise flip; flags bit 0 = vertices 1 and 2 were swapped.
+struct alignas(16) TopRec {
+    int32_t v[3];
+    int32_t flags;
+};
+
+// Star entry of a DOF: an incident triangle and the pseudo-angle (in [0, 4))
+// of the direction where its angular sector at the DOF begins.  A DOF's
+// entries are sorted by angle; the sector of entry s runs from its angle to
+// the next entry's angle (counter-clockwise).
+struct alignas(8) StarEnt {
+    float ang;
+    int32_t tri;
+};
+
+struct DevMesh {
+    int64_t n_nodes = 0, n_tris = 0, n_edges = 0, n_dofs = 0;
+    int coords_f32 = 0, p2 = 0, reordered = 0, internal_order = 0;
+    double bbox[4] = {0, 0, 0, 0};
+    // device arrays (internal order)
+    void *geo = nullptr;          // GeoRec64[n_tris] or GeoRec32[n_tris]
+    TopRec *top = nullptr;        // [n_tris]
+    int4 *tedge = nullptr;        // [n_tris] P2: internal DOF ids of edge opposite k
+    void *dof_xy = nullptr;       // double2/float2 [n_dofs]
+    int32_t *star_ptr = nullptr;  // [n_dofs + 1]
+    StarEnt *star = nullptr;      // [star_ptr[n_dofs]]
+    int32_t *vmin = nullptr;      // [n_nodes] internal tri with the smallest user id around the node
+    int32_t *dof_user = nullptr;  // [n_dofs] internal -> user DOF id
+    int32_t *dof_int = nullptr;   // [n_dofs] user -> internal DOF id
+    int32_t *tri_int = nullptr;   // [n_tris] user -> internal triangle id
+    int32_t *prev_elem = nullptr; // [n_dofs] internal tri of the last location (strategy b)
+    int32_t *jump = nullptr;      // [jump_g * jump_g] bucket grid of start triangles (internal)
+    int jump_g = 1;
+    int has_prev = 0;
+    // host copies kept for queries about the mesh
+    std::vector<double> dof_xy_user_h;   // n_dofs x 2, user order
+    std::vector<int32_t> dof_user_h;     // internal -> user
+    int64_t device_bytes = 0;
+    int32_t step_cap = 4096;
+    int32_t hard_limit = 1 << 22;
+};
+
+// Device counters accumulated by the kernels (all int64, see slw_stats).
+struct DevStats {
+    unsigned long long feet, outside, walk_steps, max_steps, exact_tests, fp64_tests, fallback_walks,
+        edge_ties, vertex_ties, hard_fail, pad[6];
+};
+
+}  // namespace slw
+
+struct slw_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    slw::DevStats *stats = nullptr;  // device counters
+    void *work = nullptr;            // grow-only workspace for permutations
+    size_t work_bytes = 0;
+};
+
+struct slw_mesh {
+    slw_ctx *ctx = nullptr;
+    slw::DevMesh m;
+};
+
+namespace slw {
+slw_status set_error(slw_status s, const std::string &msg);
+slw_status hip_check(hipError_t e, const char *what);
+slw_status ensure_work(slw_ctx *ctx, size_t bytes);
+
+// mesh construction (slw_mesh.cpp)
+slw_status build_mesh(slw_ctx *ctx, const double *xy, int64_t n, const int32_t *tri, int64_t nt, uint32_t flags,
+                      DevMesh &out, bool to_device);
+void free_mesh(DevMesh &m);
+
+// launchers (slw_kernels.hip)
+struct FieldDev {
+    int kind;
+    double p[8];
+};
+hipError_t launch_locate(const DevMesh &m, hipStream_t st, const void *q, int64_t m_pts, const int32_t *start,
+                         int32_t *elem, void *bary, int32_t *steps, DevStats *stats);
+hipError_t launch_locate_feet(const DevMesh &m, hipStream_t st, const FieldDev *f, double t_np1, double dt,
+                              int scheme, int start_mode, const int32_t *start, bool feet_in, void *feet,
+                              int32_t *elem, void *bary, int32_t *steps, DevStats *stats);
+hipError_t launch_interp(const DevMesh &m, hipStream_t st, int order, const int32_t *elem, const void *bary,
+                         int64_t m_pts, const void *v_in, int vdtype, int k, void *v_out, double outside,
+                         bool user_order);
+hipError_t launch_step(const DevMesh &m, hipStream_t st, const FieldDev &f, double t_n, double dt, int scheme,
+                       int order, int start_mode, const int32_t *start, const void *v_in, int vdtype, int k,
+                       void *v_out, double outside, bool write_prev, const int32_t *out_map, DevStats *stats);
+hipError_t launch_zero_stats(hipStream_t st, DevStats *p);
+hipError_t launch_permute_rows(hipStream_t st, const void *src, void *dst, int64_t rows, int64_t row_bytes,
+                               const int32_t *map, int scatter);
+}  // namespace slw

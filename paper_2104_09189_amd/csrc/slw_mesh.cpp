@@ -1,0 +1,532 @@
+// Mesh upload: validation, adjacency, start tables, Morton order, device copy.
+//
+// The structures follow Section 3 of the paper (node list, triangle list,
+// neighbour list with neighbour k across the edge opposite vertex k, and a
+// per-node start list), laid out for the GPU walk:
+//   - nodes and triangles are renumbered along a Morton (Z-order) curve of
+//     their position (triangles by centroid), so that neighbouring feet read
+//     neighbouring records;
+//   - each triangle record carries its vertex coordinates and neighbours, so
+//     one walk step is one 64-byte load (48 bytes for float coordinates);
+//   - each DOF keeps its incident triangles sorted by the direction of the
+//     sector they occupy at the DOF, so a walk can start in the triangle that
+//     faces its foot.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "slw_internal.h"
+#include "slw_predicates.h"
+
+namespace slw {
+
+namespace {
+
+// Monotone stand-in for the polar angle of (dx, dy): 0 along +x, increasing
+// counter-clockwise, in [0, 4).
+double pseudo_angle(double dx, double dy)
+{
+    double s = std::fabs(dx) + std::fabs(dy);
+    if (s == 0.0)
+        return 0.0;
+    double r = dx / s;
+    return dy >= 0.0 ? 1.0 - r : 3.0 + r;
+}
+
+uint64_t spread21(uint64_t v)
+{
+    v &= 0x1fffff;
+    v = (v | (v << 32)) & 0x1f00000000ffffULL;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffULL;
+    v = (v | (v << 8)) & 0x100f00f00f00f00fULL;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ULL;
+    v = (v | (v << 2)) & 0x1249249249249249ULL;
+    return v;
+}
+
+struct MortonFrame {
+    double x0, y0, scale;
+    uint64_t key(double x, double y) const
+    {
+        double fx = (x - x0) * scale, fy = (y - y0) * scale;
+        uint64_t qx = (uint64_t)std::min(std::max(fx, 0.0), 2097151.0);
+        uint64_t qy = (uint64_t)std::min(std::max(fy, 0.0), 2097151.0);
+        return spread21(qx) | (spread21(qy) << 1);
+    }
+};
+
+// order[i] = user id of the i-th element in key order (stable on ties)
+std::vector<int32_t> key_order(const std::vector<uint64_t> &keys)
+{
+    std::vector<int32_t> ord(keys.size());
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return keys[a] < keys[b]; });
+    return ord;
+}
+
+template <typename T>
+slw_status upload(const std::vector<T> &h, T **d, int64_t &bytes)
+{
+    size_t nb = std::max<size_t>(h.size(), 1) * sizeof(T);
+    hipError_t e = hipMalloc((void **)d, nb);
+    if (e != hipSuccess)
+        return set_error(SLW_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    bytes += (int64_t)nb;
+    if (!h.empty()) {
+        e = hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+        if (e != hipSuccess)
+            return hip_check(e, "hipMemcpy (mesh upload)");
+    }
+    return SLW_OK;
+}
+
+bool coord_ok(double v)
+{
+    if (!std::isfinite(v))
+        return false;
+    double a = std::fabs(v);
+    return a == 0.0 || (a >= kTinyCoord && a <= kHugeCoord);
+}
+
+}  // namespace
+
+void free_mesh(DevMesh &m)
+{
+    void *ptrs[] = {m.geo, m.top, m.tedge, m.dof_xy, m.star_ptr, m.star, m.vmin, m.dof_user,
+                    m.dof_int, m.tri_int, m.prev_elem, m.jump};
+    for (void *p : ptrs)
+        if (p)
+            (void)hipFree(p);
+    m = DevMesh();
+}
+
+slw_status build_mesh(slw_ctx *ctx, const double *xy, int64_t n, const int32_t *tri, int64_t nt, uint32_t flags,
+                      DevMesh &out, bool to_device)
+{
+    (void)ctx;
+    if (!xy || !tri || n < 3 || nt < 1)
+        return set_error(SLW_E_ARG, "mesh needs >= 3 nodes and >= 1 triangle and non-null arrays");
+    if (n > (int64_t)1 << 30 || nt > (int64_t)1 << 29)
+        return set_error(SLW_E_ARG, "mesh too large for 32-bit ids");
+    const bool f32 = flags & SLW_COORDS_F32, p2 = flags & SLW_P2, reorder = !(flags & SLW_NO_REORDER);
+
+    // coordinates: in the exactness domain of the predicates (after rounding
+    // to float for float meshes)
+    std::vector<double> X(2 * n);
+    for (int64_t i = 0; i < 2 * n; ++i) {
+        double v = f32 ? (double)(float)xy[i] : xy[i];
+        if (!coord_ok(xy[i]) || !coord_ok(v))
+            return set_error(SLW_E_MESH_RANGE, "node " + std::to_string(i / 2) +
+                                                   ": coordinate not finite, or nonzero with magnitude outside [2^-100, 2^100]");
+        X[i] = v;
+    }
+    double bb[4] = {X[0], X[1], X[0], X[1]};
+    for (int64_t i = 0; i < n; ++i) {
+        bb[0] = std::min(bb[0], X[2 * i]);
+        bb[1] = std::min(bb[1], X[2 * i + 1]);
+        bb[2] = std::max(bb[2], X[2 * i]);
+        bb[3] = std::max(bb[3], X[2 * i + 1]);
+    }
+
+    // triangles: range, distinct vertices, exact orientation, flip to CCW
+    std::vector<int32_t> T(3 * nt);
+    std::vector<int32_t> flip(nt, 0);
+    std::vector<char> used(n, 0);
+    for (int64_t t = 0; t < nt; ++t) {
+        int32_t a = tri[3 * t], b = tri[3 * t + 1], c = tri[3 * t + 2];
+        if (a < 0 || b < 0 || c < 0 || a >= n || b >= n || c >= n)
+            return set_error(SLW_E_MESH_INDEX, "triangle " + std::to_string(t) + ": vertex index out of range");
+        if (a == b || b == c || a == c)
+            return set_error(SLW_E_MESH_DEGENERATE, "triangle " + std::to_string(t) + ": repeated vertex");
+        int s = orient_sign64(X[2 * a], X[2 * a + 1], X[2 * b], X[2 * b + 1], X[2 * c], X[2 * c + 1]);
+        if (s == 0)
+            return set_error(SLW_E_MESH_DEGENERATE, "triangle " + std::to_string(t) + ": zero area");
+        if (s < 0) {
+            std::swap(b, c);
+            flip[t] = 1;
+        }
+        T[3 * t] = a;
+        T[3 * t + 1] = b;
+        T[3 * t + 2] = c;
+        used[a] = used[b] = used[c] = 1;
+    }
+    for (int64_t i = 0; i < n; ++i)
+        if (!used[i])
+            return set_error(SLW_E_MESH_DEGENERATE, "node " + std::to_string(i) + " is in no triangle");
+
+    // edges: directed a->b opposite local vertex k (CCW, interior on the left)
+    struct HalfEdge {
+        uint64_t key;
+        int32_t t;
+        int32_t k;
+    };
+    std::vector<HalfEdge> he(3 * nt);
+    for (int64_t t = 0; t < nt; ++t)
+        for (int k = 0; k < 3; ++k) {
+            uint32_t a = (uint32_t)T[3 * t + (k + 1) % 3], b = (uint32_t)T[3 * t + (k + 2) % 3];
+            uint64_t key = ((uint64_t)std::min(a, b) << 32) | std::max(a, b);
+            he[3 * t + k] = {key, (int32_t)t, k};
+        }
+    std::sort(he.begin(), he.end(), [](const HalfEdge &x, const HalfEdge &y) {
+        return x.key != y.key ? x.key < y.key : (x.t != y.t ? x.t < y.t : x.k < y.k);
+    });
+    std::vector<int32_t> NB(3 * nt, -1);
+    std::vector<int32_t> tri_edge_user(p2 ? 3 * nt : 0);
+    std::vector<uint64_t> edge_keys;
+    std::vector<int32_t> edge_left, edge_right;  // user triangles left / right of min->max
+    std::vector<int32_t> bnext(n, -1);
+    int64_t n_bnd = 0;
+    for (size_t i = 0; i < he.size();) {
+        size_t j = i;
+        while (j < he.size() && he[j].key == he[i].key)
+            ++j;
+        if (j - i > 2)
+            return set_error(SLW_E_MESH_NONCONFORMING, "an edge is shared by more than two triangles");
+        const HalfEdge &e0 = he[i];
+        uint32_t lo = (uint32_t)(e0.key >> 32), hi = (uint32_t)(e0.key & 0xffffffffu);
+        auto from_of = [&](const HalfEdge &e) { return T[3 * (int64_t)e.t + (e.k + 1) % 3]; };
+        int32_t left = -1, right = -1;
+        if (j - i == 2) {
+            const HalfEdge &e1 = he[i + 1];
+            if (from_of(e0) == from_of(e1))
+                return set_error(SLW_E_MESH_NONCONFORMING,
+                                 "triangles " + std::to_string(e0.t) + " and " + std::to_string(e1.t) +
+                                     " overlap across a shared edge");
+            NB[3 * (int64_t)e0.t + e0.k] = e1.t;
+            NB[3 * (int64_t)e1.t + e1.k] = e0.t;
+            left = from_of(e0) == (int32_t)lo ? e0.t : e1.t;
+            right = left == e0.t ? e1.t : e0.t;
+        } else {
+            int32_t a = from_of(e0), b = (int32_t)(a == (int32_t)lo ? hi : lo);
+            if (bnext[a] >= 0)
+                return set_error(SLW_E_MESH_NONCONVEX, "boundary passes twice through node " + std::to_string(a));
+            bnext[a] = b;
+            ++n_bnd;
+            if (a == (int32_t)lo)
+                left = e0.t;
+            else
+                right = e0.t;
+        }
+        if (p2) {
+            int32_t eid = (int32_t)edge_keys.size();
+            edge_keys.push_back(e0.key);
+            edge_left.push_back(left);
+            edge_right.push_back(right);
+            for (size_t q = i; q < j; ++q)
+                tri_edge_user[3 * (int64_t)he[q].t + he[q].k] = eid;
+        }
+        i = j;
+    }
+    // a disk (V - E + F = 1) whose single boundary loop turns left everywhere
+    int64_t n_edge_total = 0;
+    {
+        int64_t ne = 0;
+        for (size_t i = 0; i < he.size(); ++i)
+            if (i == 0 || he[i].key != he[i - 1].key)
+                ++ne;
+        n_edge_total = ne;
+    }
+    if (n - n_edge_total + nt != 1)
+        return set_error(SLW_E_MESH_NONCONVEX, "the mesh is not a single disk (V - E + F != 1)");
+    {
+        int32_t start = -1;
+        for (int64_t i = 0; i < n && start < 0; ++i)
+            if (bnext[i] >= 0)
+                start = (int32_t)i;
+        int64_t cnt = 0;
+        int32_t a = start;
+        do {
+            int32_t b = bnext[a];
+            if (b < 0)
+                return set_error(SLW_E_MESH_NONCONVEX, "open boundary");
+            int32_t c = bnext[b];
+            if (c < 0)
+                return set_error(SLW_E_MESH_NONCONVEX, "open boundary");
+            if (orient_sign64(X[2 * a], X[2 * a + 1], X[2 * b], X[2 * b + 1], X[2 * c], X[2 * c + 1]) < 0)
+                return set_error(SLW_E_MESH_NONCONVEX, "reflex boundary corner at node " + std::to_string(b));
+            a = b;
+            if (++cnt > n_bnd)
+                break;
+        } while (a != start);
+        if (cnt != n_bnd)
+            return set_error(SLW_E_MESH_NONCONVEX, "the boundary is not a single loop");
+    }
+
+    // ---------------- orders ----------------
+    double span = std::max(bb[2] - bb[0], bb[3] - bb[1]);
+    MortonFrame mf{bb[0], bb[1], span > 0 ? 2097151.0 / span : 1.0};
+    std::vector<int32_t> node_u(n), tri_u(nt);  // internal -> user
+    std::iota(node_u.begin(), node_u.end(), 0);
+    std::iota(tri_u.begin(), tri_u.end(), 0);
+    const int64_t ne = p2 ? (int64_t)edge_keys.size() : 0;
+    std::vector<int32_t> edge_u(ne);
+    std::iota(edge_u.begin(), edge_u.end(), 0);
+    if (reorder) {
+        std::vector<uint64_t> k(n);
+        for (int64_t i = 0; i < n; ++i)
+            k[i] = mf.key(X[2 * i], X[2 * i + 1]);
+        node_u = key_order(k);
+        std::vector<uint64_t> kt(nt);
+        for (int64_t t = 0; t < nt; ++t) {
+            double cx = (X[2 * T[3 * t]] + X[2 * T[3 * t + 1]] + X[2 * T[3 * t + 2]]) / 3.0;
+            double cy = (X[2 * T[3 * t] + 1] + X[2 * T[3 * t + 1] + 1] + X[2 * T[3 * t + 2] + 1]) / 3.0;
+            kt[t] = mf.key(cx, cy);
+        }
+        tri_u = key_order(kt);
+        if (p2) {
+            std::vector<uint64_t> ke(ne);
+            for (int64_t e = 0; e < ne; ++e) {
+                int64_t a = (int64_t)(edge_keys[e] >> 32), b = (int64_t)(edge_keys[e] & 0xffffffffu);
+                ke[e] = mf.key(0.5 * (X[2 * a] + X[2 * b]), 0.5 * (X[2 * a + 1] + X[2 * b + 1]));
+            }
+            edge_u = key_order(ke);
+        }
+    }
+    std::vector<int32_t> node_i(n), tri_i(nt), edge_i(ne);  // user -> internal
+    for (int64_t i = 0; i < n; ++i)
+        node_i[node_u[i]] = (int32_t)i;
+    for (int64_t t = 0; t < nt; ++t)
+        tri_i[tri_u[t]] = (int32_t)t;
+    for (int64_t e = 0; e < ne; ++e)
+        edge_i[edge_u[e]] = (int32_t)e;
+    const int64_t ndof = n + ne;
+
+    // ---------------- device records ----------------
+    std::vector<GeoRec64> geo64(f32 ? 0 : nt);
+    std::vector<GeoRec32> geo32(f32 ? nt : 0);
+    std::vector<TopRec> top(nt);
+    std::vector<int4> tedge(p2 ? nt : 0);
+    for (int64_t ti = 0; ti < nt; ++ti) {
+        int64_t t = tri_u[ti];
+        TopRec tr;
+        tr.flags = flip[t];
+        for (int k = 0; k < 3; ++k)
+            tr.v[k] = node_i[T[3 * t + k]];
+        top[ti] = tr;
+        int32_t nbi[3];
+        for (int k = 0; k < 3; ++k)
+            nbi[k] = NB[3 * t + k] < 0 ? -1 : tri_i[NB[3 * t + k]];
+        if (f32) {
+            GeoRec32 g;
+            std::memset(&g, 0, sizeof g);
+            for (int k = 0; k < 3; ++k) {
+                g.p[k] = make_float2((float)X[2 * T[3 * t + k]], (float)X[2 * T[3 * t + k] + 1]);
+                g.nb[k] = nbi[k];
+            }
+            g.uid = (int32_t)t;
+            geo32[ti] = g;
+        } else {
+            GeoRec64 g;
+            std::memset(&g, 0, sizeof g);
+            for (int k = 0; k < 3; ++k) {
+                g.p[k] = make_double2(X[2 * T[3 * t + k]], X[2 * T[3 * t + k] + 1]);
+                g.nb[k] = nbi[k];
+            }
+            g.uid = (int32_t)t;
+            geo64[ti] = g;
+        }
+        if (p2)
+            tedge[ti] = make_int4((int32_t)(n + edge_i[tri_edge_user[3 * t]]),
+                                  (int32_t)(n + edge_i[tri_edge_user[3 * t + 1]]),
+                                  (int32_t)(n + edge_i[tri_edge_user[3 * t + 2]]), 0);
+    }
+
+    // DOF coordinates (user order on the host, internal order on the device);
+    // edge midpoints are (a + b) * 0.5 in double
+    std::vector<double> dof_user_xy(2 * ndof);
+    for (int64_t i = 0; i < n; ++i) {
+        dof_user_xy[2 * i] = X[2 * i];
+        dof_user_xy[2 * i + 1] = X[2 * i + 1];
+    }
+    for (int64_t e = 0; e < ne; ++e) {
+        int64_t a = (int64_t)(edge_keys[e] >> 32), b = (int64_t)(edge_keys[e] & 0xffffffffu);
+        dof_user_xy[2 * (n + e)] = (xy[2 * a] + xy[2 * b]) * 0.5;
+        dof_user_xy[2 * (n + e) + 1] = (xy[2 * a + 1] + xy[2 * b + 1]) * 0.5;
+        if (f32) {
+            dof_user_xy[2 * (n + e)] = (double)(float)dof_user_xy[2 * (n + e)];
+            dof_user_xy[2 * (n + e) + 1] = (double)(float)dof_user_xy[2 * (n + e) + 1];
+        }
+    }
+    std::vector<int32_t> dof_u(ndof), dof_i(ndof);
+    for (int64_t i = 0; i < n; ++i)
+        dof_u[i] = node_u[i];
+    for (int64_t e = 0; e < ne; ++e)
+        dof_u[n + e] = (int32_t)(n + edge_u[e]);
+    for (int64_t d = 0; d < ndof; ++d)
+        dof_i[dof_u[d]] = (int32_t)d;
+
+    // stars: incident triangles of every node with the pseudo-angle of the
+    // edge that begins their sector; two half-planes for an edge DOF
+    std::vector<int32_t> sptr(ndof + 1, 0);
+    for (int64_t ti = 0; ti < nt; ++ti)
+        for (int k = 0; k < 3; ++k)
+            sptr[top[ti].v[k] + 1]++;
+    for (int64_t e = 0; e < ne; ++e) {
+        int64_t eu = edge_u[e];
+        sptr[n + e + 1] = (edge_left[eu] >= 0) + (edge_right[eu] >= 0);
+    }
+    for (int64_t d = 0; d < ndof; ++d)
+        sptr[d + 1] += sptr[d];
+    std::vector<StarEnt> star(sptr[ndof]);
+    {
+        std::vector<int32_t> fill(sptr.begin(), sptr.end() - 1);
+        auto dxy = [&](int64_t user_node, int64_t user_node_from) {
+            return std::make_pair(X[2 * user_node] - X[2 * user_node_from],
+                                  X[2 * user_node + 1] - X[2 * user_node_from + 1]);
+        };
+        for (int64_t ti = 0; ti < nt; ++ti) {
+            int64_t t = tri_u[ti];
+            for (int r = 0; r < 3; ++r) {
+                int64_t v = T[3 * t + r], nx = T[3 * t + (r + 1) % 3];
+                auto d = dxy(nx, v);
+                star[fill[node_i[v]]++] = StarEnt{(float)pseudo_angle(d.first, d.second), (int32_t)ti};
+            }
+        }
+        for (int64_t e = 0; e < ne; ++e) {
+            int64_t eu = edge_u[e];
+            int64_t a = (int64_t)(edge_keys[eu] >> 32), b = (int64_t)(edge_keys[eu] & 0xffffffffu);
+            auto d = dxy(b, a);
+            if (edge_left[eu] >= 0)
+                star[fill[n + e]++] = StarEnt{(float)pseudo_angle(d.first, d.second), tri_i[edge_left[eu]]};
+            if (edge_right[eu] >= 0)
+                star[fill[n + e]++] = StarEnt{(float)pseudo_angle(-d.first, -d.second), tri_i[edge_right[eu]]};
+        }
+        for (int64_t d = 0; d < ndof; ++d)
+            std::sort(star.begin() + sptr[d], star.begin() + sptr[d + 1],
+                      [](const StarEnt &x, const StarEnt &y) { return x.ang < y.ang; });
+    }
+    // smallest user triangle id around each node (vertex tie rule)
+    std::vector<int32_t> vmin(n);
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t best = -1;
+        for (int32_t s = sptr[i]; s < sptr[i + 1]; ++s)
+            if (best < 0 || tri_u[star[s].tri] < tri_u[best])
+                best = star[s].tri;
+        vmin[i] = best;
+    }
+    // bucket grid of start triangles for point queries without a start:
+    // each cell takes the node closest to its centre (nearest filled cell
+    // for empty cells) and that node's first incident triangle
+    int g = (int)std::max(1.0, std::ceil(std::sqrt((double)n / 16.0)));
+    g = std::min(g, 2048);
+    std::vector<int32_t> jump((size_t)g * g, -1);
+    {
+        std::vector<double> best((size_t)g * g, 1e300);
+        double w = span > 0 ? span / g : 1.0;
+        for (int64_t i = 0; i < n; ++i) {
+            int cx = (int)std::min<double>(g - 1, std::max(0.0, std::floor((X[2 * i] - bb[0]) / w)));
+            int cy = (int)std::min<double>(g - 1, std::max(0.0, std::floor((X[2 * i + 1] - bb[1]) / w)));
+            double ox = bb[0] + (cx + 0.5) * w - X[2 * i], oy = bb[1] + (cy + 0.5) * w - X[2 * i + 1];
+            double d2 = ox * ox + oy * oy;
+            size_t c = (size_t)cy * g + cx;
+            if (d2 < best[c]) {
+                best[c] = d2;
+                jump[c] = star[sptr[node_i[i]]].tri;
+            }
+        }
+        std::deque<size_t> qu;
+        for (size_t c = 0; c < jump.size(); ++c)
+            if (jump[c] >= 0)
+                qu.push_back(c);
+        while (!qu.empty()) {
+            size_t c = qu.front();
+            qu.pop_front();
+            int cx = (int)(c % g), cy = (int)(c / g);
+            const int dx[4] = {1, -1, 0, 0}, dy[4] = {0, 0, 1, -1};
+            for (int s = 0; s < 4; ++s) {
+                int nx = cx + dx[s], ny = cy + dy[s];
+                if (nx < 0 || ny < 0 || nx >= g || ny >= g)
+                    continue;
+                size_t nc = (size_t)ny * g + nx;
+                if (jump[nc] < 0) {
+                    jump[nc] = jump[c];
+                    qu.push_back(nc);
+                }
+            }
+        }
+    }
+
+    // ---------------- copy to the device ----------------
+    DevMesh m;
+    if (!to_device) {
+        out.n_nodes = n;
+        out.n_tris = nt;
+        out.n_edges = ne;
+        out.n_dofs = ndof;
+        out.coords_f32 = f32;
+        out.p2 = p2;
+        out.reordered = reorder;
+        out.internal_order = (flags & SLW_INTERNAL_ORDER) ? 1 : 0;
+        for (int i = 0; i < 4; ++i)
+            out.bbox[i] = bb[i];
+        return SLW_OK;
+    }
+    m.n_nodes = n;
+    m.n_tris = nt;
+    m.n_edges = ne;
+    m.n_dofs = ndof;
+    m.coords_f32 = f32;
+    m.p2 = p2;
+    m.reordered = reorder;
+    m.internal_order = (flags & SLW_INTERNAL_ORDER) ? 1 : 0;
+    for (int i = 0; i < 4; ++i)
+        m.bbox[i] = bb[i];
+    m.jump_g = g;
+    slw_status st = SLW_OK;
+    int64_t bytes = 0;
+#define UP(vec, ptr)                                   \
+    do {                                               \
+        st = upload(vec, &(ptr), bytes);               \
+        if (st != SLW_OK) {                            \
+            free_mesh(m);                              \
+            return st;                                 \
+        }                                              \
+    } while (0)
+    if (f32) {
+        GeoRec32 *g32 = nullptr;
+        UP(geo32, g32);
+        m.geo = g32;
+        std::vector<float2> dxy(ndof);
+        for (int64_t d = 0; d < ndof; ++d)
+            dxy[d] = make_float2((float)dof_user_xy[2 * dof_u[d]], (float)dof_user_xy[2 * dof_u[d] + 1]);
+        float2 *p = nullptr;
+        UP(dxy, p);
+        m.dof_xy = p;
+    } else {
+        GeoRec64 *g64 = nullptr;
+        UP(geo64, g64);
+        m.geo = g64;
+        std::vector<double2> dxy(ndof);
+        for (int64_t d = 0; d < ndof; ++d)
+            dxy[d] = make_double2(dof_user_xy[2 * dof_u[d]], dof_user_xy[2 * dof_u[d] + 1]);
+        double2 *p = nullptr;
+        UP(dxy, p);
+        m.dof_xy = p;
+    }
+    UP(top, m.top);
+    if (p2)
+        UP(tedge, m.tedge);
+    UP(sptr, m.star_ptr);
+    UP(star, m.star);
+    UP(vmin, m.vmin);
+    UP(dof_u, m.dof_user);
+    UP(dof_i, m.dof_int);
+    UP(tri_i, m.tri_int);
+    std::vector<int32_t> prev(ndof, -1);
+    UP(prev, m.prev_elem);
+    UP(jump, m.jump);
+#undef UP
+    m.device_bytes = bytes;
+    m.dof_xy_user_h = std::move(dof_user_xy);
+    m.dof_user_h = std::move(dof_u);
+    out = std::move(m);
+    return SLW_OK;
+}
+
+}  // namespace slw

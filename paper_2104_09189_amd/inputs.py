@@ -160,7 +160,12 @@ def graded_grid(n: int, A: float = 0.4, ratio: float = 100.0):
     # keep the boundary exact
     bnd = rho == 1.0
     xy[bnd] = s[bnd]
-    return xy, grid_triangles(n)
+    tri = grid_triangles(n)
+    a, b, cc = xy[tri[:, 0]], xy[tri[:, 1]], xy[tri[:, 2]]
+    area2 = (b[:, 0] - a[:, 0]) * (cc[:, 1] - a[:, 1]) - (b[:, 1] - a[:, 1]) * (cc[:, 0] - a[:, 0])
+    if not (area2 > 0).all():
+        raise ValueError(f"graded grid folds at n={n} (needs n >= 81)")
+    return xy, tri
 
 
 def permute_mesh(xy: np.ndarray, tri: np.ndarray, seed: int):

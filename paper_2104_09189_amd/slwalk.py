@@ -1,0 +1,408 @@
+"""Python binding of the slwalk C-ABI (include/slwalk.h).
+
+Argument marshalling only: every step of the path runs in the HIP library
+(libslwalk.so, built in-tree).  PyTorch supplies device memory and the
+stream; tensors passed to a call must live on the context's device, be
+contiguous and have the dtype the call expects.  There is no CPU fallback:
+if the library is missing this module raises on import.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from pathlib import Path
+
+import numpy as np
+
+_PKG = Path(__file__).resolve().parent
+LIB_PATH = _PKG / "libslwalk.so"
+
+if not LIB_PATH.exists():
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2104_09189_amd.build` "
+                      "(or __graft_entry__.build()); there is no fallback implementation")
+
+# torch first: it brings the HIP runtime (soname libamdhip64.so.7) that the
+# library then binds to, so device pointers and streams are shared by one
+# runtime in the process
+import torch as _torch_mod  # noqa: E402,F401
+
+_lib = ctypes.CDLL(str(LIB_PATH))
+
+SLW_OK = 0
+SLW_F64, SLW_F32 = 0, 1
+SLW_EULER, SLW_RK2 = 0, 1
+START_STEERED, START_GIVEN, START_PREV, START_FIXED = 0, 1, 2, 3
+COORDS_F32, P2, NO_REORDER, INTERNAL_ORDER = 0x1, 0x2, 0x4, 0x8
+FEET_IN = 0x1
+
+STATUS = {0: "SLW_OK", 1: "SLW_E_ARG", 2: "SLW_E_MESH_INDEX", 3: "SLW_E_MESH_DEGENERATE",
+          4: "SLW_E_MESH_NONCONFORMING", 5: "SLW_E_MESH_NONCONVEX", 6: "SLW_E_MESH_RANGE", 7: "SLW_E_HIP",
+          8: "SLW_E_NOMEM", 9: "SLW_E_UNSUPPORTED", 10: "SLW_E_WALK"}
+
+
+class SlwError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        self.name = STATUS.get(code, str(code))
+        msg = _lib.slw_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {self.name}: {msg}")
+
+
+class slw_field(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("p", ctypes.c_double * 8)]
+
+
+class slw_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "feet", "outside", "walk_steps", "max_steps", "exact_tests", "fp64_tests", "fallback_walks",
+        "edge_ties", "vertex_ties")] + [("reserved", ctypes.c_int64 * 7)]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_ if n != "reserved"}
+
+
+class slw_mesh_info(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int64), ("n_tris", ctypes.c_int64), ("n_edges", ctypes.c_int64),
+                ("n_dofs", ctypes.c_int64), ("device_bytes", ctypes.c_int64), ("coords_f32", ctypes.c_int32),
+                ("p2", ctypes.c_int32), ("reordered", ctypes.c_int32), ("internal_order", ctypes.c_int32),
+                ("bbox", ctypes.c_double * 4)]
+
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_dbl = ctypes.c_double
+_u32 = ctypes.c_uint32
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_sig("slw_status_string", ctypes.c_char_p, [ctypes.c_int])
+_sig("slw_last_error", ctypes.c_char_p, [])
+_sig("slw_ctx_create", ctypes.c_int, [ctypes.c_int, _vp, ctypes.POINTER(_vp)])
+_sig("slw_ctx_set_stream", ctypes.c_int, [_vp, _vp])
+_sig("slw_ctx_destroy", None, [_vp])
+_sig("slw_mesh_upload", ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _u32, ctypes.POINTER(_vp)])
+_sig("slw_mesh_check", ctypes.c_int, [_vp, _i64, _vp, _i64, _u32, ctypes.POINTER(slw_mesh_info)])
+_sig("slw_mesh_free", ctypes.c_int, [_vp])
+_sig("slw_mesh_get_info", ctypes.c_int, [_vp, ctypes.POINTER(slw_mesh_info)])
+_sig("slw_mesh_dof_coords", ctypes.c_int, [_vp, _vp])
+_sig("slw_mesh_dof_order", ctypes.c_int, [_vp, _vp])
+_sig("slw_mesh_set_walk_limits", ctypes.c_int, [_vp, _i32, _i32])
+_sig("slw_locate", ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, _vp, _vp])
+_sig("slw_locate_feet", ctypes.c_int, [_vp, ctypes.POINTER(slw_field), _dbl, _dbl, ctypes.c_int, ctypes.c_int, _vp,
+                                       _u32, _vp, _vp, _vp, _vp, ctypes.POINTER(slw_stats)])
+_sig("slw_interpolate", ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _i64, _vp, ctypes.c_int, ctypes.c_int, _vp,
+                                       _dbl])
+_sig("slw_step", ctypes.c_int, [_vp, ctypes.POINTER(slw_field), _dbl, _dbl, ctypes.c_int, ctypes.c_int,
+                                ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _dbl,
+                                ctypes.POINTER(slw_stats)])
+_sig("slw_permute_rows", ctypes.c_int, [_vp, _vp, _vp, _i64, ctypes.c_int])
+_sig("slw_orient_sign_host", ctypes.c_int, [_vp, _i64, _vp, ctypes.c_int])
+
+EXPORTED = ["slw_status_string", "slw_last_error", "slw_ctx_create", "slw_ctx_set_stream", "slw_ctx_destroy",
+            "slw_mesh_upload", "slw_mesh_check", "slw_mesh_free", "slw_mesh_get_info", "slw_mesh_dof_coords", "slw_mesh_dof_order",
+            "slw_mesh_set_walk_limits", "slw_locate", "slw_locate_feet", "slw_interpolate", "slw_step",
+            "slw_permute_rows", "slw_orient_sign_host"]
+
+
+def _check(rc: int, where: str):
+    if rc != SLW_OK:
+        raise SlwError(rc, where)
+
+
+def make_field(fld) -> slw_field:
+    """slw_field from an object with .kind and .params8() (the workload
+    generator's Field) or a (kind, params) pair."""
+    f = slw_field()
+    if hasattr(fld, "params8"):
+        kind, p = fld.kind, fld.params8()
+    else:
+        kind, p = fld
+    f.kind = int(kind)
+    for i, v in enumerate(np.asarray(p, dtype=np.float64).ravel()[:8]):
+        f.p[i] = float(v)
+    return f
+
+
+# ---------------------------------------------------------------------------
+# thin wrappers with the C names
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t, dtype=None, device=None, name="tensor", optional=False):
+    if t is None:
+        if optional:
+            return None
+        raise ValueError(f"{name} is required")
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if device is not None and (t.device.type != "cuda" or t.device.index != device):
+        raise ValueError(f"{name} must be on cuda:{device}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+import atexit  # noqa: E402
+import weakref  # noqa: E402
+
+_live_meshes = weakref.WeakSet()
+_live_ctxs = weakref.WeakSet()
+
+
+@atexit.register
+def _release_all():
+    # free every handle before interpreter teardown unloads the HIP runtime
+    for m in list(_live_meshes):
+        m.free()
+    for c in list(_live_ctxs):
+        c.close()
+
+
+class Context:
+    """slw_ctx_create / slw_ctx_destroy; the stream defaults to torch's current one."""
+
+    def __init__(self, device: int = 0, stream=None):
+        torch = _torch()
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _check(_lib.slw_ctx_create(device, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)), "slw_ctx_create")
+        self.h = h
+        self.meshes = weakref.WeakSet()
+        _live_ctxs.add(self)
+
+    def set_stream(self, stream):
+        self.stream = stream
+        _check(_lib.slw_ctx_set_stream(self.h, ctypes.c_void_p(stream.cuda_stream)), "slw_ctx_set_stream")
+
+    def close(self):
+        if getattr(self, "h", None):
+            for m in list(self.meshes):
+                m.free()
+            _lib.slw_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mesh:
+    """slw_mesh_upload and the calls on a mesh handle."""
+
+    def __init__(self, ctx: Context, xy, tri, flags: int = 0):
+        xy = np.ascontiguousarray(xy, dtype=np.float64)
+        tri = np.ascontiguousarray(tri, dtype=np.int32)
+        if xy.ndim != 2 or xy.shape[1] != 2 or tri.ndim != 2 or tri.shape[1] != 3:
+            raise ValueError("xy must be n x 2 and tri nt x 3")
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        _check(_lib.slw_mesh_upload(ctx.h, xy.ctypes.data_as(_vp), xy.shape[0], tri.ctypes.data_as(_vp),
+                                    tri.shape[0], flags, ctypes.byref(h)), "slw_mesh_upload")
+        self.h = h
+        ctx.meshes.add(self)
+        _live_meshes.add(self)
+        info = slw_mesh_info()
+        _check(_lib.slw_mesh_get_info(h, ctypes.byref(info)), "slw_mesh_get_info")
+        self.n_nodes, self.n_tris = info.n_nodes, info.n_tris
+        self.n_edges, self.n_dofs = info.n_edges, info.n_dofs
+        self.device_bytes = info.device_bytes
+        self.coords_f32 = bool(info.coords_f32)
+        self.p2 = bool(info.p2)
+        self.internal_order = bool(info.internal_order)
+        self.bbox = tuple(info.bbox)
+        self.cdtype = _torch().float32 if self.coords_f32 else _torch().float64
+
+    # -- mesh queries
+    def dof_coords(self) -> np.ndarray:
+        out = np.empty((self.n_dofs, 2), dtype=np.float64)
+        _check(_lib.slw_mesh_dof_coords(self.h, out.ctypes.data_as(_vp)), "slw_mesh_dof_coords")
+        return out
+
+    def dof_order(self) -> np.ndarray:
+        out = np.empty(self.n_dofs, dtype=np.int32)
+        _check(_lib.slw_mesh_dof_order(self.h, out.ctypes.data_as(_vp)), "slw_mesh_dof_order")
+        return out
+
+    def set_walk_limits(self, step_cap: int = 0, hard_limit: int = 0):
+        _check(_lib.slw_mesh_set_walk_limits(self.h, step_cap, hard_limit), "slw_mesh_set_walk_limits")
+
+    def free(self):
+        if getattr(self, "h", None) and getattr(self.ctx, "h", None):
+            _lib.slw_mesh_free(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    # -- calls
+    def locate(self, q, start=None, elem=None, bary=None, steps=None, want_bary=True, want_steps=False):
+        torch = _torch()
+        dev = self.ctx.device
+        m = q.shape[0]
+        if elem is None:
+            elem = torch.empty(m, dtype=torch.int32, device=f"cuda:{dev}")
+        if bary is None and want_bary:
+            bary = torch.empty((m, 3), dtype=self.cdtype, device=f"cuda:{dev}")
+        if steps is None and want_steps:
+            steps = torch.empty(m, dtype=torch.int32, device=f"cuda:{dev}")
+        if q.ndim != 2 or q.shape[1] != 2:
+            raise ValueError("q must be m x 2")
+        _check(_lib.slw_locate(self.h, _ptr(q, self.cdtype, dev, "q"), m,
+                               _ptr(start, torch.int32, dev, "start", True), _ptr(elem, torch.int32, dev, "elem"),
+                               _ptr(bary, self.cdtype, dev, "bary", True), _ptr(steps, torch.int32, dev, "steps", True)),
+               "slw_locate")
+        return elem, bary, steps
+
+    def locate_feet(self, field=None, t_np1=0.0, dt=0.0, scheme=SLW_EULER, start_mode=START_STEERED, start=None,
+                    feet=None, feet_in=False, want_feet=False, want_bary=True, want_steps=False, want_elem=True,
+                    stats=False):
+        torch = _torch()
+        dev = self.ctx.device
+        n = self.n_dofs
+        if feet is not None and tuple(feet.shape) != (n, 2):
+            raise ValueError("feet must be n_dofs x 2")
+        if start is not None and start_mode == START_GIVEN and start.shape[0] != n:
+            raise ValueError("start must hold one triangle id per DOF")
+        if feet is None and want_feet:
+            feet = torch.empty((n, 2), dtype=self.cdtype, device=f"cuda:{dev}")
+        elem = torch.empty(n, dtype=torch.int32, device=f"cuda:{dev}") if want_elem else None
+        bary = torch.empty((n, 3), dtype=self.cdtype, device=f"cuda:{dev}") if want_bary else None
+        steps = torch.empty(n, dtype=torch.int32, device=f"cuda:{dev}") if want_steps else None
+        st = slw_stats() if stats else None
+        fp = ctypes.byref(make_field(field)) if field is not None else None
+        _check(_lib.slw_locate_feet(self.h, fp, float(t_np1), float(dt), int(scheme), int(start_mode),
+                                    _ptr(start, torch.int32, dev, "start", True), FEET_IN if feet_in else 0,
+                                    _ptr(feet, self.cdtype, dev, "feet", True), _ptr(elem, torch.int32, dev, "elem", True),
+                                    _ptr(bary, self.cdtype, dev, "bary", True),
+                                    _ptr(steps, torch.int32, dev, "steps", True),
+                                    ctypes.byref(st) if st is not None else None), "slw_locate_feet")
+        return {"feet": feet, "elem": elem, "bary": bary, "steps": steps,
+                "stats": st.as_dict() if st is not None else None}
+
+    def interpolate(self, order, elem, bary, v_in, v_out=None, outside_value=0.0):
+        torch = _torch()
+        dev = self.ctx.device
+        vdtype = _vdtype(v_in)
+        k = 1 if v_in.ndim == 1 else v_in.shape[1]
+        m = elem.shape[0]
+        rows = self.n_nodes if order == 1 else self.n_dofs
+        if v_in.shape[0] < rows:
+            raise ValueError(f"v_in needs {rows} rows for order {order}")
+        if bary.shape != (m, 3):
+            raise ValueError("bary must be m x 3")
+        if v_out is None:
+            v_out = torch.empty((m, k), dtype=v_in.dtype, device=f"cuda:{dev}")
+        _check(_lib.slw_interpolate(self.h, int(order), _ptr(elem, torch.int32, dev, "elem"),
+                                    _ptr(bary, self.cdtype, dev, "bary"), m, _ptr(v_in, v_in.dtype, dev, "v_in"),
+                                    vdtype, k, _ptr(v_out, v_in.dtype, dev, "v_out"), float(outside_value)),
+               "slw_interpolate")
+        return v_out
+
+    def step(self, field, t_n, dt, scheme, v_in, v_out=None, order=1, start_mode=START_STEERED, start=None,
+             outside_value=0.0, stats=False):
+        torch = _torch()
+        dev = self.ctx.device
+        vdtype = _vdtype(v_in)
+        k = 1 if v_in.ndim == 1 else v_in.shape[1]
+        rows = self.n_nodes if order == 1 else self.n_dofs
+        if v_in.shape[0] != rows:
+            raise ValueError(f"v_in must have {rows} rows")
+        if v_out is None:
+            v_out = torch.empty_like(v_in)
+        if v_out.shape != v_in.shape:
+            raise ValueError("v_out must have the shape of v_in")
+        st = slw_stats() if stats else None
+        _check(_lib.slw_step(self.h, ctypes.byref(make_field(field)), float(t_n), float(dt), int(scheme), int(order),
+                             int(start_mode), _ptr(start, torch.int32, dev, "start", True),
+                             _ptr(v_in, v_in.dtype, dev, "v_in"), vdtype, k, _ptr(v_out, v_in.dtype, dev, "v_out"),
+                             float(outside_value), ctypes.byref(st) if st is not None else None), "slw_step")
+        return (v_out, st.as_dict()) if stats else v_out
+
+    def permute_rows(self, src, dst=None, to_internal=True):
+        torch = _torch()
+        dev = self.ctx.device
+        if dst is None:
+            dst = torch.empty_like(src)
+        row_bytes = src.element_size() * (1 if src.ndim == 1 else int(np.prod(src.shape[1:])))
+        if src.shape[0] != self.n_dofs:
+            raise ValueError("src must have n_dofs rows")
+        _check(_lib.slw_permute_rows(self.h, _ptr(src, None, dev, "src"), _ptr(dst, None, dev, "dst"), row_bytes,
+                                     1 if to_internal else 0), "slw_permute_rows")
+        return dst
+
+
+def _vdtype(t):
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return SLW_F64
+    if t.dtype == torch.float32:
+        return SLW_F32
+    raise TypeError("values must be float64 or float32")
+
+
+def slw_mesh_check(xy, tri, flags: int = 0) -> dict:
+    """Host-side validation of a mesh (no device needed); raises SlwError."""
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    info = slw_mesh_info()
+    _check(_lib.slw_mesh_check(xy.ctypes.data_as(_vp), xy.shape[0], tri.ctypes.data_as(_vp), tri.shape[0], flags,
+                               ctypes.byref(info)), "slw_mesh_check")
+    return {"n_nodes": info.n_nodes, "n_tris": info.n_tris, "n_edges": info.n_edges, "n_dofs": info.n_dofs,
+            "bbox": tuple(info.bbox)}
+
+
+def slw_orient_sign_host(pts, mode: int = 0) -> np.ndarray:
+    """The library's orientation predicate on the host (mode 0 FP64 + exact,
+    1 exact stage only, 2 float pipeline)."""
+    pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 6)
+    out = np.empty(pts.shape[0], dtype=np.int8)
+    _check(_lib.slw_orient_sign_host(pts.ctypes.data_as(_vp), pts.shape[0], out.ctypes.data_as(_vp), int(mode)),
+           "slw_orient_sign_host")
+    return out
+
+
+# C-name aliases (same semantics as the header)
+slw_ctx_create = Context
+slw_mesh_upload = Mesh
+
+
+def slw_locate(mesh: Mesh, *a, **kw):
+    return mesh.locate(*a, **kw)
+
+
+def slw_locate_feet(mesh: Mesh, *a, **kw):
+    return mesh.locate_feet(*a, **kw)
+
+
+def slw_interpolate(mesh: Mesh, *a, **kw):
+    return mesh.interpolate(*a, **kw)
+
+
+def slw_step(mesh: Mesh, *a, **kw):
+    return mesh.step(*a, **kw)
+
+
+def slw_permute_rows(mesh: Mesh, *a, **kw):
+    return mesh.permute_rows(*a, **kw)

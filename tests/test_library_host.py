@@ -1,0 +1,150 @@
+"""CPU-side tests of the HIP library: it loads, exports every entry point the
+header declares, and its host-side mesh validation accepts valid meshes and
+rejects invalid ones with the documented status codes.  No kernel runs."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2104_09189_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2104_09189_amd import slwalk
+    return slwalk
+
+
+def test_library_exports_every_declared_symbol(S):
+    hdr = open(os.path.join(ROOT, "include", "slwalk.h")).read()
+    declared = set(re.findall(r"\b(slw_[a-z0-9_]+)\s*\(", hdr))
+    assert len(declared) >= 15
+    lib = ctypes.CDLL(str(S.LIB_PATH))
+    missing = [n for n in sorted(declared) if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(S.EXPORTED) == declared
+
+
+def test_status_strings(S):
+    for code in range(11):
+        assert S._lib.slw_status_string(code).decode()
+
+
+def test_valid_meshes_pass(S):
+    xy, tri = I.jittered_grid(33, 1001)
+    info = S.slw_mesh_check(xy, tri, S.P2)
+    assert info["n_nodes"] == 1089 and info["n_tris"] == 2048
+    assert info["n_edges"] == 1089 + 2048 - 1
+    assert info["n_dofs"] == 1089 + info["n_edges"]
+    xy, tri = I.permute_mesh(*I.graded_grid(81), 3)
+    assert S.slw_mesh_check(xy, tri)["n_tris"] == 2 * 80 * 80
+    # clockwise triangles are accepted (flipped internally)
+    tri2 = tri.copy()
+    tri2[::2] = tri2[::2][:, [0, 2, 1]]
+    S.slw_mesh_check(xy, tri2)
+
+
+def _code(S, xy, tri, flags=0):
+    try:
+        S.slw_mesh_check(xy, tri, flags)
+    except S.SlwError as e:
+        return e.name
+    return "SLW_OK"
+
+
+def test_invalid_meshes_are_rejected(S):
+    xy, tri = I.jittered_grid(6, 3)
+    t = tri.copy()
+    t[4, 1] = 999
+    assert _code(S, xy, t) == "SLW_E_MESH_INDEX"
+    t = tri.copy()
+    t[4, 1] = t[4, 0]
+    assert _code(S, xy, t) == "SLW_E_MESH_DEGENERATE"
+    # zero-area triangle: three collinear nodes
+    x2 = xy.copy()
+    a, b, c = tri[7]
+    x2[c] = 0.5 * (x2[a] + x2[b])
+    assert _code(S, x2, tri) in ("SLW_E_MESH_DEGENERATE", "SLW_E_MESH_NONCONFORMING", "SLW_E_MESH_NONCONVEX")
+    # an unused node
+    x3 = np.concatenate([xy, [[0.5, 0.5]]])
+    assert _code(S, x3, tri) == "SLW_E_MESH_DEGENERATE"
+    # a triangle listed twice: an edge in more than two triangles
+    assert _code(S, xy, np.concatenate([tri, tri[:1]])) == "SLW_E_MESH_NONCONFORMING"
+    # a hole (one interior triangle removed): not a convex disk
+    n = 6
+    hole = (n - 1) * 2 + 2
+    assert _code(S, xy, np.delete(tri, [2 * hole], axis=0)) == "SLW_E_MESH_NONCONVEX"
+    # a reflex corner: remove one corner cell's triangle
+    assert _code(S, xy, np.delete(tri, [1], axis=0)) == "SLW_E_MESH_NONCONVEX"
+    # coordinates outside the exactness domain
+    x4 = xy.copy()
+    x4[0, 0] = np.nan
+    assert _code(S, x4, tri) == "SLW_E_MESH_RANGE"
+    x4 = xy.copy()
+    x4[8, 0] = 1e-200
+    assert _code(S, x4, tri) == "SLW_E_MESH_RANGE"
+    assert _code(S, xy, tri, 0x100) == "SLW_E_ARG"
+    assert _code(S, xy[:2], tri[:0]) == "SLW_E_ARG"
+
+
+def test_context_on_a_missing_device_is_an_error(S):
+    h = ctypes.c_void_p()
+    rc = S._lib.slw_ctx_create(99, None, ctypes.byref(h))
+    assert rc in (1, 7) and not h.value   # SLW_E_ARG, or SLW_E_HIP without a device
+    assert S._lib.slw_ctx_create(0, None, None) == 1
+
+
+def _predicate_cases(rng, m):
+    """Triples (a, b) in the mesh exactness domain and any query c: random,
+    near-collinear (rounded points of the line a-b, one-ulp nudges of exact
+    lattice points), and queries with tiny or subnormal coordinates."""
+    out = []
+    for _ in range(m):
+        kind = int(rng.integers(0, 5))
+        a = rng.uniform(-1, 1, 2)
+        b = rng.uniform(-1, 1, 2)
+        if kind == 0:
+            c = rng.uniform(-1, 1, 2)
+        elif kind == 1:
+            c = a + rng.uniform(-2, 3) * (b - a)
+        elif kind == 2:
+            s = 2.0 ** -int(rng.integers(0, 60))
+            a = rng.integers(-50, 50, 2) * s
+            d = rng.integers(-7, 8, 2) * s
+            b = a + d
+            c = (a + int(rng.integers(-5, 6)) * d).astype(float)
+            i = int(rng.integers(0, 2))
+            c[i] = np.nextafter(c[i], np.inf if rng.integers(0, 2) else -np.inf)
+        elif kind == 3:
+            # a vertical or horizontal edge through 0 and a query at a tiny offset
+            t = rng.uniform(0.1, 0.9)
+            a = np.array([0.0, rng.uniform(0.0, 0.4)])
+            b = np.array([0.0, rng.uniform(0.6, 1.0)])
+            tiny = float(rng.choice([5e-324, -5e-324, 1e-310, -1e-300, 1e-200, -2.0 ** -1000]))
+            c = np.array([tiny, t])
+            if rng.integers(0, 2):
+                a, b, c = a[::-1].copy(), b[::-1].copy(), c[::-1].copy()
+        else:
+            # large coordinates at the top of the domain
+            base = rng.uniform(-2.0 ** 90, 2.0 ** 90, 2)
+            a = base + rng.uniform(-1e10, 1e10, 2)
+            b = base + rng.uniform(-1e10, 1e10, 2)
+            c = a + rng.uniform(-2, 3) * (b - a)
+        out.append(np.concatenate([a, b, c]))
+    return np.array(out)
+
+
+def test_library_predicate_matches_oracle_exact_sign(S, orc):
+    rng = np.random.default_rng(77)
+    pts = _predicate_cases(rng, 40000)
+    want = orc.orient_sign_batch(pts, use_filter=False)
+    assert (S.slw_orient_sign_host(pts, 0) == want).all()
+    assert (S.slw_orient_sign_host(pts, 1) == want).all()
+    assert (want == 0).sum() > 1000 and (want != 0).sum() > 10000
+    # float pipeline: exact on the inputs rounded to float
+    p32 = pts.astype(np.float32).astype(np.float64)
+    assert (S.slw_orient_sign_host(pts, 2) == orc.orient_sign_batch(p32, use_filter=False)).all()
