@@ -94,7 +94,7 @@ enum {
     SLW_START_STEERED = 0, /* strategy (a): the DOF's incident triangle facing the foot */
     SLW_START_GIVEN = 1,   /* start[dof] = user triangle id */
     SLW_START_PREV = 2,    /* strategy (b): the element found for this DOF by the previous
-                              SLW_START_PREV/STEERED call on this mesh (steered on the first) */
+                              SLW_START_PREV call on this mesh (steered when there is none) */
     SLW_START_FIXED = 3    /* every walk starts at user triangle start[0] (the paper's
                               fixed-start baseline, Section 2.2 complexity) */
 };

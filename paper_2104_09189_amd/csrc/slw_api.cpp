@@ -403,7 +403,7 @@ slw_status slw_step(slw_mesh *mesh, const slw_field *field, double t_n, double d
         vin_int = ctx->work;
         out_map = m.dof_user;
     }
-    const bool write_prev = start_mode == SLW_START_PREV || start_mode == SLW_START_STEERED;
+    const bool write_prev = start_mode == SLW_START_PREV;
     FieldDev fd = to_dev(field);
     st = hip_check(launch_step(m, ctx->stream, fd, t_n, dt, scheme, order, start_mode, start, vin_int, vdtype, k,
                                v_out, outside_value, write_prev, out_map, stats_h ? ctx->stats : nullptr),

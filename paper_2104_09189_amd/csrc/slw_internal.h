@@ -108,7 +108,13 @@ void free_mesh(DevMesh &m);
 struct FieldDev {
     int kind;
     double p[8];
+    // time-dependent factors of the two evaluation times of a step, computed
+    // on the host: [0] at t_{n+1}, [1] at t_{n+1} - dt/2 (midpoint stage).
+    // swirl: cos(pi t / p0); rotating field: p1 t.
+    double g[2];
 };
+// fill FieldDev::g for evaluation times t_np1 and t_np1 - dt/2
+void field_time_factors(FieldDev &f, double t_np1, double dt);
 hipError_t launch_locate(const DevMesh &m, hipStream_t st, const void *q, int64_t m_pts, const int32_t *start,
                          int32_t *elem, void *bary, int32_t *steps, DevStats *stats);
 hipError_t launch_locate_feet(const DevMesh &m, hipStream_t st, const FieldDev *f, double t_np1, double dt,

@@ -10,6 +10,8 @@
 // depend on where the walk started.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "slw_internal.h"
 #include "slw_predicates.h"
 
@@ -37,10 +39,14 @@ struct CT<true> {
 // ---------------------------------------------------------------------------
 // advecting fields (kinds as in slw_field) and feet
 
+__device__ inline void sincospi_r(double x, double &s, double &c) { sincospi(x, &s, &c); }
+__device__ inline void sincospi_r(float x, float &s, float &c) { sincospif(x, &s, &c); }
+
+// f at (x, y) and evaluation time `which` (0: t_{n+1}, 1: t_{n+1} - dt/2);
+// the time factors were evaluated once on the host
 template <typename R>
-__device__ inline void field_eval(const FieldDev &f, R x, R y, R t, R &fx, R &fy)
+__device__ inline void field_eval(const FieldDev &f, int which, R x, R y, R &fx, R &fy)
 {
-    const R pi = (R)3.14159265358979323846;
     const R p0 = (R)f.p[0], p1 = (R)f.p[1], p2 = (R)f.p[2], p3 = (R)f.p[3];
     switch (f.kind) {
     case 0:
@@ -52,15 +58,18 @@ __device__ inline void field_eval(const FieldDev &f, R x, R y, R t, R &fx, R &fy
         fy = p0 * (x - p1);
         break;
     case 2: {
-        R g = cos(pi * t / p0);
-        R sx = sin(pi * x), sy = sin(pi * y);
-        fx = g * sx * sx * sin((R)2 * pi * y);
-        fy = -g * sy * sy * sin((R)2 * pi * x);
+        // sin(2 pi y) = 2 sin(pi y) cos(pi y): one sincospi per coordinate
+        const R g = (R)f.g[which];
+        R sx, cx, sy, cy;
+        sincospi_r(x, sx, cx);
+        sincospi_r(y, sy, cy);
+        fx = g * sx * sx * ((R)2 * sy * cy);
+        fy = -g * sy * sy * ((R)2 * sx * cx);
         break;
     }
     case 3: {
         R dx = x - p2, dy = y - p3;
-        R a = p0 * sqrt(dx * dx + dy * dy) + p1 * t;
+        R a = p0 * sqrt(dx * dx + dy * dy) + (R)f.g[which];
         fx = cos(a);
         fy = sin(a);
         break;
@@ -79,13 +88,13 @@ __device__ inline void field_eval(const FieldDev &f, R x, R y, R t, R &fx, R &fy
 // eq. (eulero): q = x - dt f(x, t_{n+1}); midpoint: x* = x - dt/2 f(x, t_{n+1}),
 // q = x - dt f(x*, t_{n+1} - dt/2)
 template <typename R>
-__device__ inline void foot_of(const FieldDev &f, int scheme, R x, R y, R t_np1, R dt, R &qx, R &qy)
+__device__ inline void foot_of(const FieldDev &f, int scheme, R x, R y, R dt, R &qx, R &qy)
 {
     R fx, fy;
-    field_eval<R>(f, x, y, t_np1, fx, fy);
+    field_eval<R>(f, 0, x, y, fx, fy);
     if (scheme == SLW_RK2) {
         R xs = x - (R)0.5 * dt * fx, ys = y - (R)0.5 * dt * fy;
-        field_eval<R>(f, xs, ys, t_np1 - (R)0.5 * dt, fx, fy);
+        field_eval<R>(f, 1, xs, ys, fx, fy);
     }
     qx = x - dt * fx;
     qy = y - dt * fy;
@@ -541,7 +550,7 @@ __global__ void __launch_bounds__(kBlock)
             qx = feet[api].x;
             qy = feet[api].y;
         } else {
-            foot_of<R>(f, scheme, x.x, x.y, (R)t_np1, (R)dt, qx, qy);
+            foot_of<R>(f, scheme, x.x, x.y, (R)dt, qx, qy);
             if (feet) {
                 R2 o;
                 o.x = qx;
@@ -558,7 +567,7 @@ __global__ void __launch_bounds__(kBlock)
             int32_t j0 = start_for<F32>(mv, d, api, mode, start, (float)(qx - x.x), (float)(qy - x.y));
             w = walk<F32>(wp, j0, qx, qy, (uint32_t)d * 2654435761u, ls.c);
         }
-        if (mode == SLW_START_PREV || mode == SLW_START_STEERED)
+        if (mode == SLW_START_PREV)
             mv.prev[d] = w.elem;
         if (st)
             ls.add(w);
@@ -691,23 +700,62 @@ __global__ void __launch_bounds__(kBlock)
     }
 }
 
-// The fused step: foot -> start -> walk -> tie rule -> weights -> values.
-template <bool F32, typename V>
+template <typename VV>
+__device__ inline VV vv_zero();
+template <>
+__device__ inline float4 vv_zero<float4>() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+template <>
+__device__ inline double2 vv_zero<double2>() { return make_double2(0.0, 0.0); }
+__device__ inline void vv_fma(float w, const float4 r, float4 &acc)
+{
+    acc.x = fmaf(w, r.x, acc.x);
+    acc.y = fmaf(w, r.y, acc.y);
+    acc.z = fmaf(w, r.z, acc.z);
+    acc.w = fmaf(w, r.w, acc.w);
+}
+__device__ inline void vv_fma(double w, const double2 r, double2 &acc)
+{
+    acc.x = fma(w, r.x, acc.x);
+    acc.y = fma(w, r.y, acc.y);
+}
+
+// Workgroups are dispatched to the 8 XCDs round-robin (block b runs on XCD
+// b mod 8).  Give each XCD one contiguous range of tiles instead, so that the
+// Morton-ordered tiles one XCD processes are spatially compact and the
+// triangle records and value rows they share stay in that XCD's L2.
+__device__ inline int64_t xcd_tile(int64_t b, int64_t nb)
+{
+    constexpr int64_t kXcd = 8;
+    const int64_t q = nb / kXcd, r = nb % kXcd;
+    const int64_t x = b % kXcd, local = b / kXcd;
+    return x < r ? x * (q + 1) + local : r * (q + 1) + (x - r) * q + local;
+}
+
+// The fused step, one workgroup per tile of kBlock consecutive (Morton) DOFs.
+// Phase 1, one lane per foot: foot -> start -> walk -> tie rule -> weights;
+// the located element's value rows and weights go to LDS.  Phase 2, the
+// workgroup interpolates the tile's values cooperatively: work item
+// (foot, chunk of VW fields), consecutive lanes on consecutive chunks, so
+// the row gathers read whole row segments and the stores are contiguous.
+template <bool F32, typename V, int NA>
 __global__ void __launch_bounds__(kBlock)
-    k_step(MeshView mv, FieldDev f, double t_np1, double dt, int scheme, int order, int mode,
-           const int32_t *__restrict__ start, const V *__restrict__ vin, int k, V *__restrict__ vout, double outside,
-           int write_prev, const int32_t *__restrict__ out_map, int64_t n_iter, DevStats *st)
+    k_step(MeshView mv, FieldDev f, double dt, int scheme, int mode, const int32_t *__restrict__ start,
+           const V *__restrict__ vin, int k, V *__restrict__ vout, double outside, int write_prev,
+           const int32_t *__restrict__ out_map, int64_t n_iter, DevStats *st)
 {
     using R = typename CT<F32>::R;
     using R2 = typename CT<F32>::R2;
+    __shared__ int32_t s_row[NA][kBlock];
+    __shared__ V s_w[NA][kBlock];
+    const int64_t base = xcd_tile(blockIdx.x, gridDim.x) * kBlock;
+    const int tid = threadIdx.x;
+    const int64_t d = base + tid;
     LaneStats ls;
-    const WalkParams wp = walk_params(mv);
-    const R2 *X = (const R2 *)mv.dof_xy;
-    for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < n_iter;
-         d += (int64_t)gridDim.x * blockDim.x) {
-        const R2 x = X[d];
+    if (d < n_iter) {
+        const WalkParams wp = walk_params(mv);
+        const R2 x = ((const R2 *)mv.dof_xy)[d];
         R qx, qy;
-        foot_of<R>(f, scheme, x.x, x.y, (R)t_np1, (R)dt, qx, qy);
+        foot_of<R>(f, scheme, x.x, x.y, (R)dt, qx, qy);
         WalkResult<R> w;
         w.elem = -1;
         w.uid = -1;
@@ -715,18 +763,82 @@ __global__ void __launch_bounds__(kBlock)
         w.flags = 0;
         if (in_box<R>(qx, qy, mv.bb)) {
             const int64_t api = (mode == SLW_START_GIVEN && !mv.internal_order) ? mv.dof_user[d] : d;
-            int32_t j0 = start_for<F32>(mv, d, api, mode, start, (float)(qx - x.x), (float)(qy - x.y));
+            const int32_t j0 = start_for<F32>(mv, d, api, mode, start, (float)(qx - x.x), (float)(qy - x.y));
             w = walk<F32>(wp, j0, qx, qy, (uint32_t)d * 2654435761u, ls.c);
         }
         if (write_prev)
             mv.prev[d] = w.elem;
         if (st)
             ls.add(w);
-        const int64_t o = out_map ? out_map[d] : d;
-        interp_point<R, V>(mv, order, w.elem, w.th, vin, k, nullptr, (V)outside, vout + o * (int64_t)k);
+        if (w.elem >= 0) {
+            const TopRec t = mv.top[w.elem];
+            if constexpr (NA == 3) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    s_row[a][tid] = t.v[a];
+                    s_w[a][tid] = (V)w.th[a];
+                }
+            } else {
+                const int4 te = mv.tedge[w.elem];
+                const int32_t ev[3] = {te.x, te.y, te.z};
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const int b = (a + 1) % 3, c = (a + 2) % 3;
+                    s_row[a][tid] = t.v[a];
+                    s_row[3 + a][tid] = ev[a];
+                    s_w[a][tid] = (V)(w.th[a] * ((R)2 * w.th[a] - (R)1));
+                    s_w[3 + a][tid] = (V)((R)4 * w.th[b] * w.th[c]);
+                }
+            }
+        } else {
+            s_row[0][tid] = -1;
+        }
     }
     if (st)
         flush_stats(ls, st);
+    __syncthreads();
+
+    const int nf = (int)min<int64_t>(kBlock, n_iter - base);
+    constexpr int VW = sizeof(V) == 4 ? 4 : 2;  // fields per 16-byte chunk
+    const bool aligned = ((reinterpret_cast<uintptr_t>(vin) | reinterpret_cast<uintptr_t>(vout)) & 15) == 0;
+    if (aligned && k % VW == 0) {
+        using VV = typename std::conditional<sizeof(V) == 4, float4, double2>::type;
+        const int chunks = k / VW;
+        for (int it = tid; it < nf * chunks; it += kBlock) {
+            const int fl = it / chunks, c = it - fl * chunks;
+            const int64_t o = out_map ? out_map[base + fl] : base + fl;
+            VV *dst = (VV *)(vout + o * (int64_t)k) + c;
+            const int32_t r0 = s_row[0][fl];
+            if (r0 < 0) {
+                VV z;
+                if constexpr (VW == 4)
+                    z = make_float4((float)outside, (float)outside, (float)outside, (float)outside);
+                else
+                    z = make_double2(outside, outside);
+                *dst = z;
+                continue;
+            }
+            VV acc = vv_zero<VV>();
+#pragma unroll
+            for (int a = 0; a < NA; ++a)
+                vv_fma(s_w[a][fl], *((const VV *)(vin + (int64_t)s_row[a][fl] * k) + c), acc);
+            *dst = acc;
+        }
+    } else {
+        for (int it = tid; it < nf * k; it += kBlock) {
+            const int fl = it / k, c = it - fl * k;
+            const int64_t o = out_map ? out_map[base + fl] : base + fl;
+            const int32_t r0 = s_row[0][fl];
+            V acc = (V)outside;
+            if (r0 >= 0) {
+                acc = (V)0;
+#pragma unroll
+                for (int a = 0; a < NA; ++a)
+                    acc = fma(s_w[a][fl], vin[(int64_t)s_row[a][fl] * k + c], acc);
+            }
+            vout[o * (int64_t)k + c] = acc;
+        }
+    }
 }
 
 __global__ void k_permute_rows(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst, int64_t rows,
@@ -782,7 +894,8 @@ hipError_t launch_locate_feet(const DevMesh &m, hipStream_t st, const FieldDev *
                               void *bary, int32_t *steps, DevStats *stats)
 {
     MeshView mv = view_of(m);
-    FieldDev fd = f ? *f : FieldDev{0, {0, 0, 0, 0, 0, 0, 0, 0}};
+    FieldDev fd = f ? *f : FieldDev{0, {0, 0, 0, 0, 0, 0, 0, 0}, {0, 0}};
+    field_time_factors(fd, t_np1, dt);
     if (m.coords_f32)
         hipLaunchKernelGGL(k_locate_feet<true>, dim3(grid_for(m.n_dofs)), dim3(kBlock), 0, st, mv, fd, t_np1, dt,
                            scheme, mode, start, (int)feet_in, (float2 *)feet, elem, (float *)bary, steps, stats);
@@ -822,34 +935,52 @@ hipError_t launch_interp(const DevMesh &m, hipStream_t st, int order, const int3
     return hipGetLastError();
 }
 
-hipError_t launch_step(const DevMesh &m, hipStream_t st, const FieldDev &f, double t_n, double dt, int scheme,
+hipError_t launch_step(const DevMesh &m, hipStream_t st, const FieldDev &f0, double t_n, double dt, int scheme,
                        int order, int mode, const int32_t *start, const void *v_in, int vdtype, int k, void *v_out,
                        double outside, bool write_prev, const int32_t *out_map, DevStats *stats)
 {
     MeshView mv = view_of(m);
+    FieldDev f = f0;
+    field_time_factors(f, t_n + dt, dt);
     const int64_t n_iter = order == 1 ? m.n_nodes : m.n_dofs;
-    const int g = grid_for(n_iter);
-    const double t_np1 = t_n + dt;
+    const int64_t tiles = (n_iter + kBlock - 1) / kBlock;
+    if (tiles == 0)
+        return hipSuccess;
+    if (tiles > (int64_t)INT32_MAX)
+        return hipErrorInvalidValue;
+    const dim3 g((unsigned)tiles), b(kBlock);
+#define SLW_STEP(F32, V, NA)                                                                                   \
+    hipLaunchKernelGGL((k_step<F32, V, NA>), g, b, 0, st, mv, f, dt, scheme, mode, start, (const V *)v_in, k, \
+                       (V *)v_out, outside, (int)write_prev, out_map, n_iter, stats)
     if (m.coords_f32) {
-        if (vdtype == SLW_F32)
-            hipLaunchKernelGGL((k_step<true, float>), dim3(g), dim3(kBlock), 0, st, mv, f, t_np1, dt, scheme, order,
-                               mode, start, (const float *)v_in, k, (float *)v_out, outside, (int)write_prev,
-                               out_map, n_iter, stats);
-        else
-            hipLaunchKernelGGL((k_step<true, double>), dim3(g), dim3(kBlock), 0, st, mv, f, t_np1, dt, scheme,
-                               order, mode, start, (const double *)v_in, k, (double *)v_out, outside,
-                               (int)write_prev, out_map, n_iter, stats);
+        if (vdtype == SLW_F32) {
+            if (order == 1) SLW_STEP(true, float, 3); else SLW_STEP(true, float, 6);
+        } else {
+            if (order == 1) SLW_STEP(true, double, 3); else SLW_STEP(true, double, 6);
+        }
     } else {
-        if (vdtype == SLW_F32)
-            hipLaunchKernelGGL((k_step<false, float>), dim3(g), dim3(kBlock), 0, st, mv, f, t_np1, dt, scheme,
-                               order, mode, start, (const float *)v_in, k, (float *)v_out, outside,
-                               (int)write_prev, out_map, n_iter, stats);
-        else
-            hipLaunchKernelGGL((k_step<false, double>), dim3(g), dim3(kBlock), 0, st, mv, f, t_np1, dt, scheme,
-                               order, mode, start, (const double *)v_in, k, (double *)v_out, outside,
-                               (int)write_prev, out_map, n_iter, stats);
+        if (vdtype == SLW_F32) {
+            if (order == 1) SLW_STEP(false, float, 3); else SLW_STEP(false, float, 6);
+        } else {
+            if (order == 1) SLW_STEP(false, double, 3); else SLW_STEP(false, double, 6);
+        }
     }
+#undef SLW_STEP
     return hipGetLastError();
+}
+
+void field_time_factors(FieldDev &f, double t_np1, double dt)
+{
+    const double pi = 3.14159265358979323846;
+    const double t[2] = {t_np1, t_np1 - 0.5 * dt};
+    for (int i = 0; i < 2; ++i) {
+        if (f.kind == 2)
+            f.g[i] = cos(pi * t[i] / f.p[0]);
+        else if (f.kind == 3)
+            f.g[i] = f.p[1] * t[i];
+        else
+            f.g[i] = 0.0;
+    }
 }
 
 hipError_t launch_zero_stats(hipStream_t st, DevStats *p)
