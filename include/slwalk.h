@@ -222,6 +222,16 @@ slw_status slw_permute_rows(slw_mesh *mesh, const void *src, void *dst, int64_t 
  * the exactness domain above. */
 slw_status slw_orient_sign_host(const double *pts_h, int64_t m, int8_t *out_h, int mode);
 
+/* The walk's float filter evaluated on the host, for testing its error
+ * bound: for the triple pts_h[6i .. 6i+5] = (ax, ay, bx, by, qx, qy), the
+ * coordinates are rounded to float the way a mesh stores them (minus the
+ * centre (cx, cy), for a mesh whose largest |coordinate - centre| is cmax;
+ * with f32 != 0 the coordinates themselves, as for a float mesh) and out_h[i]
+ * is the filter's certified sign of orient(a, b, q), or 2 when it defers to
+ * the exact stages. */
+slw_status slw_float_filter_host(const double *pts_h, int64_t m, double cx, double cy, double cmax, int f32,
+                                 int8_t *out_h);
+
 #ifdef __cplusplus
 }
 #endif

@@ -337,7 +337,6 @@ slw_status slw_locate_feet(slw_mesh *mesh, const slw_field *field, double t_np1,
                    "slw_locate_feet");
     if (st != SLW_OK)
         return st;
-    mesh->m.has_prev = 1;
     return end_stats(ctx, stats_h);
 }
 
@@ -410,7 +409,6 @@ slw_status slw_step(slw_mesh *mesh, const slw_field *field, double t_n, double d
                    "slw_step");
     if (st != SLW_OK)
         return st;
-    mesh->m.has_prev = 1;
     return end_stats(ctx, stats_h);
 }
 
@@ -428,6 +426,24 @@ slw_status slw_orient_sign_host(const double *pts_h, int64_t m, int8_t *out_h, i
         else
             s = orient_sign32((float)p[0], (float)p[1], (float)p[2], (float)p[3], (float)p[4], (float)p[5]);
         out_h[i] = (int8_t)s;
+    }
+    return SLW_OK;
+}
+
+slw_status slw_float_filter_host(const double *pts_h, int64_t m, double cx, double cy, double cmax, int f32,
+                                 int8_t *out_h)
+{
+    if (m < 0 || (m > 0 && (!pts_h || !out_h)) || !(cmax >= 0.0))
+        return set_error(SLW_E_ARG, "slw_float_filter_host: bad arguments");
+    const FilterConst fc = filter_constants(f32 != 0, f32 ? 0.0 : cx, f32 ? 0.0 : cy, cmax);
+    for (int64_t i = 0; i < m; ++i) {
+        const double *p = pts_h + 6 * i;
+        float r[6];
+        for (int j = 0; j < 6; ++j)
+            r[j] = f32 ? (float)p[j] : (float)(p[j] - ((j & 1) ? fc.cy : fc.cx));
+        float det;
+        const int s = filter_sign_f32(r[0] - r[4], r[1] - r[5], r[2] - r[4], r[3] - r[5], fc.c1, fc.c2, fc.c3, det);
+        out_h[i] = (int8_t)(s != 0 ? s : 2);
     }
     return SLW_OK;
 }

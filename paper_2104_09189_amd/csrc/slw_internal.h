@@ -11,52 +11,38 @@
 
 namespace slw {
 
-// Triangle record read by every walk step: the three vertex coordinates
-// (stored redundantly per triangle so that one walk step is a single
-// dependent load), the three neighbours (neighbour k across the edge opposite
-// vertex k, -1 on the boundary) and the user id.  64 bytes for double.
-struct alignas(64) GeoRec64 {
-    double2 p[3];
-    int32_t nb[3];
-    int32_t uid;
-};
-// 48 bytes for float coordinates.
-struct alignas(16) GeoRec32 {
+// Triangle record read by every walk step (48 bytes, three 16-byte loads):
+// vertex coordinates as float (for double meshes: relative to the centre of
+// the bounding box, rounded; for float meshes: the coordinates themselves),
+// the neighbours (neighbour k across the edge opposite vertex k, -1 on the
+// boundary) and the internal ids of the three vertices.  Walk decisions are
+// taken on the float coordinates only when a certified error bound allows
+// it; otherwise the exact coordinates are read through the vertex ids.
+struct alignas(16) GeoRec {
     float2 p[3];
     int32_t nb[3];
-    int32_t uid;
-    int32_t pad[2];
-};
-static_assert(sizeof(GeoRec64) == 64, "GeoRec64 layout");
-static_assert(sizeof(GeoRec32) == 48, "GeoRec32 layout");
-
-// Topology record: internal vertex DOF ids (v) in the user's vertex order up
-// to the counter-clockwise flip; flags bit 0 = vertices 1 and 2 were swapped.
-struct alignas(16) TopRec {
     int32_t v[3];
-    int32_t flags;
 };
+static_assert(sizeof(GeoRec) == 48, "GeoRec layout");
 
-// Star entry of a DOF: an incident triangle and the pseudo-angle (in [0, 4))
-// of the direction where its angular sector at the DOF begins.  A DOF's
-// entries are sorted by angle; the sector of entry s runs from its angle to
-// the next entry's angle (counter-clockwise).
-struct alignas(8) StarEnt {
-    float ang;
-    int32_t tri;
+// Coefficients of the float filter's error bound (see the walk kernel):
+// |det_float - det| <= c1 (|l| + |r|) + c2 (|ax|+|ay|+|bx|+|by|) + c3.
+struct FilterConst {
+    float c1, c2, c3;
+    double cx, cy;  // centre subtracted from coordinates before rounding to float
 };
 
 struct DevMesh {
     int64_t n_nodes = 0, n_tris = 0, n_edges = 0, n_dofs = 0;
     int coords_f32 = 0, p2 = 0, reordered = 0, internal_order = 0;
     double bbox[4] = {0, 0, 0, 0};
+    FilterConst fc = {0, 0, 0, 0, 0};
     // device arrays (internal order)
-    void *geo = nullptr;          // GeoRec64[n_tris] or GeoRec32[n_tris]
-    TopRec *top = nullptr;        // [n_tris]
-    int4 *tedge = nullptr;        // [n_tris] P2: internal DOF ids of edge opposite k
-    void *dof_xy = nullptr;       // double2/float2 [n_dofs]
-    int32_t *star_ptr = nullptr;  // [n_dofs + 1]
-    StarEnt *star = nullptr;      // [star_ptr[n_dofs]]
+    GeoRec *geo = nullptr;        // [n_tris]
+    int32_t *tri_uf = nullptr;    // [n_tris] user id | (1 << 31 if vertices 1, 2 were swapped to make it CCW)
+    int4 *tedge = nullptr;        // [n_tris] P2: internal DOF ids of the edge opposite vertex k
+    void *dof_xy = nullptr;       // double2/float2 [n_dofs], exact coordinates
+    int4 *qstart = nullptr;       // [n_dofs] incident triangle facing each diagonal direction
     int32_t *vmin = nullptr;      // [n_nodes] internal tri with the smallest user id around the node
     int32_t *dof_user = nullptr;  // [n_dofs] internal -> user DOF id
     int32_t *dof_int = nullptr;   // [n_dofs] user -> internal DOF id
@@ -64,10 +50,9 @@ struct DevMesh {
     int32_t *prev_elem = nullptr; // [n_dofs] internal tri of the last location (strategy b)
     int32_t *jump = nullptr;      // [jump_g * jump_g] bucket grid of start triangles (internal)
     int jump_g = 1;
-    int has_prev = 0;
     // host copies kept for queries about the mesh
-    std::vector<double> dof_xy_user_h;   // n_dofs x 2, user order
-    std::vector<int32_t> dof_user_h;     // internal -> user
+    std::vector<double> dof_xy_user_h;  // n_dofs x 2, user order
+    std::vector<int32_t> dof_user_h;    // internal -> user
     int64_t device_bytes = 0;
     int32_t step_cap = 4096;
     int32_t hard_limit = 1 << 22;
@@ -103,6 +88,9 @@ slw_status ensure_work(slw_ctx *ctx, size_t bytes);
 slw_status build_mesh(slw_ctx *ctx, const double *xy, int64_t n, const int32_t *tri, int64_t nt, uint32_t flags,
                       DevMesh &out, bool to_device);
 void free_mesh(DevMesh &m);
+// coefficients of the walk's float filter for a mesh whose float coordinates
+// are fl32(x - (cx, cy)) with |x - c| <= cmax (f32: coordinates already float)
+FilterConst filter_constants(bool f32, double cx, double cy, double cmax);
 
 // launchers (slw_kernels.hip)
 struct FieldDev {
@@ -115,6 +103,7 @@ struct FieldDev {
 };
 // fill FieldDev::g for evaluation times t_np1 and t_np1 - dt/2
 void field_time_factors(FieldDev &f, double t_np1, double dt);
+
 hipError_t launch_locate(const DevMesh &m, hipStream_t st, const void *q, int64_t m_pts, const int32_t *start,
                          int32_t *elem, void *bary, int32_t *steps, DevStats *stats);
 hipError_t launch_locate_feet(const DevMesh &m, hipStream_t st, const FieldDev *f, double t_np1, double dt,

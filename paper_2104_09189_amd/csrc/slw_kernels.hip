@@ -1,13 +1,14 @@
 // Device kernels: feet, start selection, barycentric walk, tie rule,
 // interpolation, and the fused semi-Lagrangian step.
 //
-// One lane handles one foot.  A walk step reads one triangle record (vertex
-// coordinates + neighbours, 64 B in double, 48 B in float), computes the three
-// edge orientations of the foot, and either stops (all signs >= 0: the
-// barycentric coordinates of Section 2.2 are all non-negative) or crosses the
-// edge with the most negative coordinate.  Signs are exact (filtered FP32 /
-// FP64, then exact expansion arithmetic), so the triangle found does not
-// depend on where the walk started.
+// One lane handles one foot.  A walk step reads one 48-byte triangle record
+// (float coordinates, neighbours, vertex ids), computes the three edge
+// orientations of the foot, and either stops (all signs >= 0: the barycentric
+// coordinates of Section 2.2 are all non-negative) or crosses the edge with
+// the most negative coordinate.  Every sign is exact: a float filter with a
+// certified error bound decides almost all of them; the rest are decided on
+// the exact coordinates (FP64 filter, then exact expansion arithmetic).  The
+// triangle found therefore does not depend on where the walk started.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -20,6 +21,8 @@ namespace slw {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kWave = 64;
+constexpr int32_t kUidMask = 0x7fffffff;
 
 template <bool F32>
 struct CT;
@@ -27,13 +30,11 @@ template <>
 struct CT<false> {
     using R = double;
     using R2 = double2;
-    using Geo = GeoRec64;
 };
 template <>
 struct CT<true> {
     using R = float;
     using R2 = float2;
-    using Geo = GeoRec32;
 };
 
 // ---------------------------------------------------------------------------
@@ -101,114 +102,151 @@ __device__ inline void foot_of(const FieldDev &f, int scheme, R x, R y, R dt, R 
 }
 
 // ---------------------------------------------------------------------------
-// start selection
+// mesh view passed to every kernel
 
-__device__ inline float pseudo_angle_f(float dx, float dy)
-{
-    float s = fabsf(dx) + fabsf(dy);
-    if (s == 0.0f)
-        return 0.0f;
-    float r = dx / s;
-    return dy >= 0.0f ? 1.0f - r : 3.0f + r;
-}
+struct MeshView {
+    const GeoRec *geo;
+    const int32_t *tri_uf;
+    const int4 *tedge;
+    const void *dof_xy;
+    const int4 *qstart;
+    const int32_t *vmin;
+    const int32_t *dof_user;
+    const int32_t *tri_int;
+    int32_t *prev;
+    const int32_t *jump;
+    int jump_g;
+    int internal_order;
+    int64_t n_dofs;
+    int64_t n_tris;
+    double bb[4];
+    FilterConst fc;
+    int32_t step_cap, hard_limit;
+};
 
-// The incident triangle of DOF d whose angular sector contains the direction
-// of the foot (strategy (a) of Section 3 with the element facing the foot).
-__device__ inline int32_t steer(const int32_t *__restrict__ sptr, const StarEnt *__restrict__ star, int64_t d,
-                                float dx, float dy)
+MeshView view_of(const DevMesh &m)
 {
-    int32_t s0 = sptr[d], s1 = sptr[d + 1];
-    float th = pseudo_angle_f(dx, dy);
-    int32_t sel = s1 - 1;
-    for (int32_t s = s0; s < s1; ++s)
-        if (star[s].ang <= th)
-            sel = s;
-    return star[sel].tri;
+    MeshView v;
+    v.geo = m.geo;
+    v.tri_uf = m.tri_uf;
+    v.tedge = m.tedge;
+    v.dof_xy = m.dof_xy;
+    v.qstart = m.qstart;
+    v.vmin = m.vmin;
+    v.dof_user = m.dof_user;
+    v.tri_int = m.tri_int;
+    v.prev = m.prev_elem;
+    v.jump = m.jump;
+    v.jump_g = m.jump_g;
+    v.internal_order = m.internal_order;
+    v.n_dofs = m.n_dofs;
+    v.n_tris = m.n_tris;
+    for (int i = 0; i < 4; ++i)
+        v.bb[i] = m.bbox[i];
+    v.fc = m.fc;
+    v.step_cap = m.step_cap;
+    v.hard_limit = m.hard_limit;
+    return v;
 }
 
 // ---------------------------------------------------------------------------
-// exact edge signs of a triangle record for a point
+// start selection: strategy (a) of Section 3 (the walk starts at the DOF),
+// in the incident triangle that faces the diagonal direction of the foot's
+// quadrant
+
+__device__ inline int32_t quadrant_start(const int4 qs, float dx, float dy)
+{
+    return dx >= 0.0f ? (dy >= 0.0f ? qs.x : qs.w) : (dy >= 0.0f ? qs.y : qs.z);
+}
+
+template <bool F32>
+__device__ inline int32_t start_for(const MeshView &mv, int64_t d, int64_t api, int mode,
+                                    const int32_t *__restrict__ start, float dx, float dy)
+{
+    // caller-given ids outside [0, n_tris) fall back to the steered start
+    if (mode == SLW_START_GIVEN || mode == SLW_START_FIXED) {
+        const int32_t u = start[mode == SLW_START_GIVEN ? api : 0];
+        if (u >= 0 && u < mv.n_tris)
+            return mv.tri_int[u];
+    }
+    if (mode == SLW_START_PREV) {
+        const int32_t pe = mv.prev[d];
+        if (pe >= 0)
+            return pe;
+    }
+    return quadrant_start(mv.qstart[d], dx, dy);
+}
+
+// ---------------------------------------------------------------------------
+// exact signs
 
 struct Counters {
     uint32_t exact = 0, fp64 = 0;
 };
 
-__device__ inline void edge_signs64(const double2 p[3], double qx, double qy, double o[3], int s[3], Counters &c)
+// sign of orient(a, b, q) on the exact coordinates (FP64 filter, then
+// exact), for the rare tests the float filter cannot certify; the exact
+// coordinates of a double mesh are read through the vertex ids va, vb
+template <bool F32>
+__device__ __noinline__ int slow_sign(const void *dof_xy, float2 pa, float2 pb, int32_t va, int32_t vb,
+                                      typename CT<F32>::R qx, typename CT<F32>::R qy)
 {
-    double dx[3], dy[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        dx[k] = p[k].x - qx;
-        dy[k] = p[k].y - qy;
+    double ax, ay, bx, by;
+    if constexpr (F32) {
+        ax = pa.x;
+        ay = pa.y;
+        bx = pb.x;
+        by = pb.y;
+    } else {
+        const double2 *X = (const double2 *)dof_xy;
+        const double2 A = X[va], B = X[vb];
+        ax = A.x;
+        ay = A.y;
+        bx = B.x;
+        by = B.y;
     }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const int a = (k + 1) % 3, b = (k + 2) % 3;
-        bool certain;
-        const double det = filter64(dx[a] * dy[b], dy[a] * dx[b], certain);
-        o[k] = det;
-        if (certain)
-            s[k] = sign_of(det);
-        else {
-            s[k] = orient_exact_sign(p[a].x, p[a].y, p[b].x, p[b].y, qx, qy);
-            ++c.exact;
-        }
-    }
+    bool certain;
+    const double d = orient_fp64(ax, ay, bx, by, (double)qx, (double)qy, certain);
+    if (certain)
+        return sign_of(d);
+    return 2 * orient_exact_sign(ax, ay, bx, by, (double)qx, (double)qy);  // x2: tells the caller it was exact
 }
 
-__device__ inline void edge_signs32(const float2 p[3], float qx, float qy, float o[3], int s[3], Counters &c)
+// Signs of the three edge orientations o_k = orient(x_{k+1}, x_{k+2}, q) of
+// record r: the float filter on the rounded inputs (filter_sign_f32) decides
+// when its bound allows, the exact coordinates otherwise.  o[] keeps the
+// float values, used to pick among negative edges (any negative edge is a
+// valid move).
+template <bool F32>
+__device__ inline void edge_signs(const MeshView &mv, const GeoRec &r, float qfx, float qfy,
+                                  typename CT<F32>::R qx, typename CT<F32>::R qy, float o[3], int s[3], Counters &c)
 {
     float dx[3], dy[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        dx[k] = p[k].x - qx;
-        dy[k] = p[k].y - qy;
+        dx[k] = r.p[k].x - qfx;
+        dy[k] = r.p[k].y - qfy;
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const int a = (k + 1) % 3, b = (k + 2) % 3;
-        bool certain;
-        const float det = filter32(dx[a] * dy[b], dy[a] * dx[b], certain);
-        o[k] = det;
-        if (certain)
-            s[k] = (det > 0.0f) - (det < 0.0f);
-        else {
-            double d64 = orient_fp64((double)p[a].x, (double)p[a].y, (double)p[b].x, (double)p[b].y, (double)qx,
-                                     (double)qy, certain);
-            ++c.fp64;
-            if (certain)
-                s[k] = sign_of(d64);
-            else {
-                s[k] = orient_exact_sign((double)p[a].x, (double)p[a].y, (double)p[b].x, (double)p[b].y,
-                                         (double)qx, (double)qy);
-                ++c.exact;
+        s[k] = filter_sign_f32(dx[a], dy[a], dx[b], dy[b], mv.fc.c1, mv.fc.c2, mv.fc.c3, o[k]);
+    }
+    if ((s[0] == 0) | (s[1] == 0) | (s[2] == 0)) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (s[k] == 0) {
+                const int a = (k + 1) % 3, b = (k + 2) % 3;
+                const int sg = slow_sign<F32>(mv.dof_xy, r.p[a], r.p[b], r.v[a], r.v[b], qx, qy);
+                ++c.fp64;
+                c.exact += (sg == 2 || sg == -2 || sg == 0);
+                s[k] = sg > 0 ? 1 : (sg < 0 ? -1 : 0);
             }
         }
     }
 }
 
-template <bool F32>
-__device__ inline void load_geo(const typename CT<F32>::Geo *__restrict__ geo, int32_t j,
-                                typename CT<F32>::R2 p[3], int32_t nb[3], int32_t &uid)
-{
-    const typename CT<F32>::Geo g = geo[j];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        p[k] = g.p[k];
-        nb[k] = g.nb[k];
-    }
-    uid = g.uid;
-}
-
-template <bool F32>
-__device__ inline void edge_signs(const typename CT<F32>::R2 p[3], typename CT<F32>::R qx, typename CT<F32>::R qy,
-                                  typename CT<F32>::R o[3], int s[3], Counters &c)
-{
-    if constexpr (F32)
-        edge_signs32(p, qx, qy, o, s, c);
-    else
-        edge_signs64(p, qx, qy, o, s, c);
-}
+__device__ inline int32_t sel3(int k, int32_t a, int32_t b, int32_t c) { return k == 0 ? a : (k == 1 ? b : c); }
 
 __device__ inline uint32_t hash32(uint32_t x)
 {
@@ -223,101 +261,120 @@ __device__ inline uint32_t hash32(uint32_t x)
 template <typename R>
 struct WalkResult {
     int32_t elem;   // internal triangle id, -1 outside
-    int32_t uid;    // user id of elem
     int32_t steps;  // element changes
     int32_t flags;  // bit0 fallback walk, bit1 hard limit, bit2 edge tie, bit3 vertex tie
-    R th[3];        // barycentric coordinates in the internal vertex order of elem
+    int32_t v[3];   // internal vertex DOF ids of elem
+    R th[3];        // barycentric coordinates in the internal (counter-clockwise) vertex order of elem
 };
 
-struct WalkParams {
-    const void *geo;
-    const TopRec *top;
-    const int32_t *vmin;
-    int32_t step_cap;
-    int32_t hard_limit;
-};
+template <typename R>
+__device__ inline WalkResult<R> outside_result(int32_t steps, int32_t flags)
+{
+    WalkResult<R> w;
+    w.elem = -1;
+    w.steps = steps;
+    w.flags = flags;
+    w.v[0] = w.v[1] = w.v[2] = -1;
+    w.th[0] = w.th[1] = w.th[2] = (R)0;
+    return w;
+}
 
-// Barycentric walk of Section 2.2 from triangle j to the foot (qx, qy), then
-// the tie rule (smallest user id among the closed containers).
+// Barycentric walk of Section 2.2 from triangle j to the foot q, then the tie
+// rule (smallest user id among the closed containers), then the weights on
+// the exact coordinates.
 template <bool F32>
-__device__ WalkResult<typename CT<F32>::R> walk(const WalkParams &wp, int32_t j, typename CT<F32>::R qx,
+__device__ WalkResult<typename CT<F32>::R> walk(const MeshView &mv, int32_t j, typename CT<F32>::R qx,
                                                  typename CT<F32>::R qy, uint32_t seed, Counters &c)
 {
     using R = typename CT<F32>::R;
-    using R2 = typename CT<F32>::R2;
-    using Geo = typename CT<F32>::Geo;
-    const Geo *geo = (const Geo *)wp.geo;
-    WalkResult<R> res;
-    res.steps = 0;
-    res.flags = 0;
-    R2 p[3];
-    int32_t nb[3], uid;
-    R o[3];
+    const float qfx = F32 ? (float)qx : (float)((double)qx - mv.fc.cx);
+    const float qfy = F32 ? (float)qy : (float)((double)qy - mv.fc.cy);
+    GeoRec r;
+    float o[3];
     int s[3];
+    int32_t steps = 0, flags = 0;
     for (;;) {
-        load_geo<F32>(geo, j, p, nb, uid);
-        edge_signs<F32>(p, qx, qy, o, s, c);
+        r = mv.geo[j];
+        edge_signs<F32>(mv, r, qfx, qfy, qx, qy, o, s, c);
         const bool n0 = s[0] < 0, n1 = s[1] < 0, n2 = s[2] < 0;
         if (!(n0 | n1 | n2))
             break;
         // a negative side on the boundary: the foot is outside the (convex) domain
-        if ((n0 && nb[0] < 0) || (n1 && nb[1] < 0) || (n2 && nb[2] < 0)) {
-            res.elem = -1;
-            res.uid = -1;
-            return res;
-        }
-        if (res.steps >= wp.hard_limit) {
-            res.flags |= 2;
-            res.elem = -1;
-            res.uid = -1;
-            return res;
-        }
+        if ((n0 && r.nb[0] < 0) || (n1 && r.nb[1] < 0) || (n2 && r.nb[2] < 0))
+            return outside_result<R>(steps, flags);
+        if (steps >= mv.hard_limit)
+            return outside_result<R>(steps, flags | 3);
         int k;
-        if (res.steps < wp.step_cap) {
+        if (steps < mv.step_cap) {
             // most negative barycentric coordinate, lowest index on ties
-            k = n0 ? 0 : (n1 ? 1 : 2);
-            if (n1 && o[1] < o[k])
-                k = 1;
-            if (n2 && o[2] < o[k])
-                k = 2;
+            // (selects rather than indexing, so the record stays in registers)
+            const float m0 = n0 ? o[0] : INFINITY, m1 = n1 ? o[1] : INFINITY, m2 = n2 ? o[2] : INFINITY;
+            k = (m1 < m0) ? ((m2 < m1) ? 2 : 1) : ((m2 < m0) ? 2 : 0);
         } else {
             // randomised visibility walk: a uniformly chosen separating edge
             // (terminates with probability 1 on any triangulation)
-            res.flags |= 1;
+            flags |= 1;
             const int cnt = (int)n0 + (int)n1 + (int)n2;
-            int pick = (int)(hash32(seed ^ hash32((uint32_t)res.steps)) % (uint32_t)cnt);
-            k = -1;
-            for (int q = 0; q < 3; ++q)
-                if (s[q] < 0 && pick-- == 0)
-                    k = q;
+            const int pick = (int)(hash32(seed ^ hash32((uint32_t)steps)) % (uint32_t)cnt);
+            // the pick-th negative edge
+            const int first = n0 ? 0 : (n1 ? 1 : 2);
+            const int second = (n0 && n1) ? 1 : 2;
+            k = pick == 0 ? first : (pick == 1 ? second : 2);
         }
-        j = nb[k];
-        ++res.steps;
+        j = sel3(k, r.nb[0], r.nb[1], r.nb[2]);
+        ++steps;
     }
     // tie rule on the closed containers
     const int z = (s[0] == 0) + (s[1] == 0) + (s[2] == 0);
     int32_t e = j;
     if (z == 1) {
         const int k = s[0] == 0 ? 0 : (s[1] == 0 ? 1 : 2);
-        res.flags |= 4;
-        if (nb[k] >= 0 && geo[nb[k]].uid < uid)
-            e = nb[k];
+        const int32_t nbk = sel3(k, r.nb[0], r.nb[1], r.nb[2]);
+        flags |= 4;
+        if (nbk >= 0 && (mv.tri_uf[nbk] & kUidMask) < (mv.tri_uf[j] & kUidMask))
+            e = nbk;
     } else if (z == 2) {
         const int cidx = s[0] != 0 ? 0 : (s[1] != 0 ? 1 : 2);
-        res.flags |= 8;
-        e = wp.vmin[wp.top[j].v[cidx]];
+        flags |= 8;
+        e = mv.vmin[sel3(cidx, r.v[0], r.v[1], r.v[2])];
     }
-    if (e != j) {
-        load_geo<F32>(geo, e, p, nb, uid);
-        edge_signs<F32>(p, qx, qy, o, s, c);
+    if (e != j)
+        r = mv.geo[e];
+    WalkResult<R> w;
+    w.elem = e;
+    w.steps = steps;
+    w.flags = flags;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        w.v[k] = r.v[k];
+    // weights on the exact coordinates: theta_k = o_k / (o_0 + o_1 + o_2)
+    R ex[3], ey[3];
+    if constexpr (F32) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            ex[k] = r.p[k].x - qx;
+            ey[k] = r.p[k].y - qy;
+        }
+    } else {
+        const double2 *X = (const double2 *)mv.dof_xy;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double2 p = X[r.v[k]];
+            ex[k] = p.x - qx;
+            ey[k] = p.y - qy;
+        }
     }
-    const R sum = o[0] + o[1] + o[2];
-    res.th[0] = o[0] / sum;
-    res.th[1] = o[1] / sum;
-    res.th[2] = o[2] / sum;
-    res.elem = e;
-    res.uid = uid;
-    return res;
+    R oo[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int a = (k + 1) % 3, b = (k + 2) % 3;
+        oo[k] = ex[a] * ey[b] - ey[a] * ex[b];
+    }
+    const R sum = oo[0] + oo[1] + oo[2];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        w.th[k] = oo[k] / sum;
+    return w;
 }
 
 // ---------------------------------------------------------------------------
@@ -357,6 +414,7 @@ struct LaneStats {
     }
 };
 
+// called by every lane of the wavefront
 __device__ inline void flush_stats(const LaneStats &ls, DevStats *st)
 {
     unsigned long long v[10] = {ls.feet, ls.outside, ls.steps, ls.max_steps, ls.c.exact, ls.c.fp64, ls.fallback,
@@ -378,75 +436,30 @@ __device__ inline void flush_stats(const LaneStats &ls, DevStats *st)
 }
 
 // queries outside the mesh's bounding box (or not finite) are outside
-// without a walk
+// without a walk; written so that NaN compares false
 template <typename R>
 __device__ inline bool in_box(R qx, R qy, const double bb[4])
 {
-    // written so that NaN compares false and lands outside
     return (double)qx >= bb[0] && (double)qx <= bb[2] && (double)qy >= bb[1] && (double)qy <= bb[3];
 }
 
-struct MeshView {
-    const void *geo;
-    const TopRec *top;
-    const int4 *tedge;
-    const void *dof_xy;
-    const int32_t *sptr;
-    const StarEnt *star;
-    const int32_t *vmin;
-    const int32_t *dof_user;
-    const int32_t *tri_int;
-    int32_t *prev;
-    const int32_t *jump;
-    int jump_g;
-    int64_t n_dofs;
-    int64_t n_tris;
-    double bb[4];
-    int32_t step_cap, hard_limit;
-    int internal_order;
-};
-
-MeshView view_of(const DevMesh &m)
+// Workgroups are dispatched to the 8 XCDs round-robin (block b runs on XCD
+// b mod 8).  Give each XCD one contiguous range of tiles instead, so that the
+// Morton-ordered tiles one XCD processes are spatially compact and the
+// triangle records and value rows they share stay in that XCD's L2.
+__device__ inline int64_t xcd_tile(int64_t b, int64_t nb)
 {
-    MeshView v;
-    v.geo = m.geo;
-    v.top = m.top;
-    v.tedge = m.tedge;
-    v.dof_xy = m.dof_xy;
-    v.sptr = m.star_ptr;
-    v.star = m.star;
-    v.vmin = m.vmin;
-    v.dof_user = m.dof_user;
-    v.tri_int = m.tri_int;
-    v.prev = m.prev_elem;
-    v.jump = m.jump;
-    v.jump_g = m.jump_g;
-    v.n_dofs = m.n_dofs;
-    v.n_tris = m.n_tris;
-    for (int i = 0; i < 4; ++i)
-        v.bb[i] = m.bbox[i];
-    v.step_cap = m.step_cap;
-    v.hard_limit = m.hard_limit;
-    v.internal_order = m.internal_order;
-    return v;
-}
-
-__device__ inline WalkParams walk_params(const MeshView &mv)
-{
-    WalkParams wp;
-    wp.geo = mv.geo;
-    wp.top = mv.top;
-    wp.vmin = mv.vmin;
-    wp.step_cap = mv.step_cap;
-    wp.hard_limit = mv.hard_limit;
-    return wp;
+    constexpr int64_t kXcd = 8;
+    const int64_t q = nb / kXcd, r = nb % kXcd;
+    const int64_t x = b % kXcd, local = b / kXcd;
+    return x < r ? x * (q + 1) + local : r * (q + 1) + (x - r) * q + local;
 }
 
 template <typename R>
-__device__ inline void user_bary(const TopRec &t, const R th[3], R out[3])
+__device__ inline void user_bary(int32_t uf, const R th[3], R out[3])
 {
     out[0] = th[0];
-    if (t.flags & 1) {
+    if (uf < 0) {  // vertices 1 and 2 were swapped at upload
         out[1] = th[2];
         out[2] = th[1];
     } else {
@@ -466,14 +479,10 @@ __global__ void __launch_bounds__(kBlock) k_locate(MeshView mv, const typename C
 {
     using R = typename CT<F32>::R;
     LaneStats ls;
-    const WalkParams wp = walk_params(mv);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (i < m) {
         R qx = q[i].x, qy = q[i].y;
-        WalkResult<R> w;
-        w.elem = -1;
-        w.uid = -1;
-        w.steps = 0;
-        w.flags = 0;
+        WalkResult<R> w = outside_result<R>(0, 0);
         if (in_box<R>(qx, qy, mv.bb)) {
             int32_t j0;
             const int32_t su = start ? start[i] : -1;
@@ -482,21 +491,22 @@ __global__ void __launch_bounds__(kBlock) k_locate(MeshView mv, const typename C
             } else {
                 const double wx = (mv.bb[2] - mv.bb[0]), wy = (mv.bb[3] - mv.bb[1]);
                 const double span = wx > wy ? wx : wy;
-                const double w = span > 0 ? span / mv.jump_g : 1.0;
-                int cx = (int)floor(((double)qx - mv.bb[0]) / w), cy = (int)floor(((double)qy - mv.bb[1]) / w);
+                const double cw = span > 0 ? span / mv.jump_g : 1.0;
+                int cx = (int)floor(((double)qx - mv.bb[0]) / cw), cy = (int)floor(((double)qy - mv.bb[1]) / cw);
                 cx = cx < 0 ? 0 : (cx >= mv.jump_g ? mv.jump_g - 1 : cx);
                 cy = cy < 0 ? 0 : (cy >= mv.jump_g ? mv.jump_g - 1 : cy);
                 j0 = mv.jump[(int64_t)cy * mv.jump_g + cx];
             }
-            w = walk<F32>(wp, j0, qx, qy, (uint32_t)i * 2654435761u, ls.c);
+            w = walk<F32>(mv, j0, qx, qy, (uint32_t)i * 2654435761u, ls.c);
         }
         if (st)
             ls.add(w);
-        elem[i] = w.uid;
+        const int32_t uf = w.elem >= 0 ? mv.tri_uf[w.elem] : -1;
+        elem[i] = w.elem >= 0 ? (uf & kUidMask) : -1;
         if (bary) {
             if (w.elem >= 0) {
                 R ub[3];
-                user_bary<R>(mv.top[w.elem], w.th, ub);
+                user_bary<R>(uf, w.th, ub);
                 bary[3 * i] = ub[0];
                 bary[3 * i + 1] = ub[1];
                 bary[3 * i + 2] = ub[2];
@@ -512,39 +522,18 @@ __global__ void __launch_bounds__(kBlock) k_locate(MeshView mv, const typename C
 }
 
 template <bool F32>
-__device__ inline int32_t start_for(const MeshView &mv, int64_t d, int64_t api, int mode,
-                                    const int32_t *__restrict__ start, float dx, float dy)
-{
-    // caller-given ids outside [0, n_tris) fall back to the steered start
-    if (mode == SLW_START_GIVEN || mode == SLW_START_FIXED) {
-        const int32_t u = start[mode == SLW_START_GIVEN ? api : 0];
-        if (u >= 0 && u < mv.n_tris)
-            return mv.tri_int[u];
-    }
-    if (mode == SLW_START_PREV) {
-        int32_t pe = mv.prev[d];
-        if (pe >= 0)
-            return pe;
-    }
-    return steer(mv.sptr, mv.star, d, dx, dy);
-}
-
-template <bool F32>
 __global__ void __launch_bounds__(kBlock)
-    k_locate_feet(MeshView mv, FieldDev f, double t_np1, double dt, int scheme, int mode,
-                  const int32_t *__restrict__ start, int feet_in, typename CT<F32>::R2 *__restrict__ feet,
-                  int32_t *__restrict__ elem, typename CT<F32>::R *__restrict__ bary, int32_t *__restrict__ steps,
-                  DevStats *st)
+    k_locate_feet(MeshView mv, FieldDev f, double dt, int scheme, int mode, const int32_t *__restrict__ start,
+                  int feet_in, typename CT<F32>::R2 *__restrict__ feet, int32_t *__restrict__ elem,
+                  typename CT<F32>::R *__restrict__ bary, int32_t *__restrict__ steps, DevStats *st)
 {
     using R = typename CT<F32>::R;
     using R2 = typename CT<F32>::R2;
     LaneStats ls;
-    const WalkParams wp = walk_params(mv);
-    const R2 *X = (const R2 *)mv.dof_xy;
-    for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < mv.n_dofs;
-         d += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t d = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (d < mv.n_dofs) {
         const int64_t api = mv.internal_order ? d : mv.dof_user[d];
-        const R2 x = X[d];
+        const R2 x = ((const R2 *)mv.dof_xy)[d];
         R qx, qy;
         if (feet_in) {
             qx = feet[api].x;
@@ -558,25 +547,22 @@ __global__ void __launch_bounds__(kBlock)
                 feet[api] = o;
             }
         }
-        WalkResult<R> w;
-        w.elem = -1;
-        w.uid = -1;
-        w.steps = 0;
-        w.flags = 0;
+        WalkResult<R> w = outside_result<R>(0, 0);
         if (in_box<R>(qx, qy, mv.bb)) {
-            int32_t j0 = start_for<F32>(mv, d, api, mode, start, (float)(qx - x.x), (float)(qy - x.y));
-            w = walk<F32>(wp, j0, qx, qy, (uint32_t)d * 2654435761u, ls.c);
+            const int32_t j0 = start_for<F32>(mv, d, api, mode, start, (float)(qx - x.x), (float)(qy - x.y));
+            w = walk<F32>(mv, j0, qx, qy, (uint32_t)d * 2654435761u, ls.c);
         }
         if (mode == SLW_START_PREV)
             mv.prev[d] = w.elem;
         if (st)
             ls.add(w);
+        const int32_t uf = w.elem >= 0 ? mv.tri_uf[w.elem] : -1;
         if (elem)
-            elem[api] = w.uid;
+            elem[api] = w.elem >= 0 ? (uf & kUidMask) : -1;
         if (bary) {
             if (w.elem >= 0) {
                 R ub[3];
-                user_bary<R>(mv.top[w.elem], w.th, ub);
+                user_bary<R>(uf, w.th, ub);
                 bary[3 * api] = ub[0];
                 bary[3 * api + 1] = ub[1];
                 bary[3 * api + 2] = ub[2];
@@ -591,114 +577,8 @@ __global__ void __launch_bounds__(kBlock)
         flush_stats(ls, st);
 }
 
-// weighted sum of rows: out[f] = sum_a w[a] * V[row_a * k + f]
-template <typename V, int NA>
-__device__ inline void combine_rows(const V *__restrict__ vin, const int64_t rows[NA], const V w[NA], int k,
-                                    V *__restrict__ out)
-{
-    const bool aligned = ((reinterpret_cast<uintptr_t>(vin) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
-    if constexpr (sizeof(V) == 4) {
-        if ((k & 3) == 0 && aligned) {
-            for (int f = 0; f < k; f += 4) {
-                float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-                for (int a = 0; a < NA; ++a) {
-                    const float4 r = *(const float4 *)(vin + rows[a] * k + f);
-                    acc.x = fmaf(w[a], r.x, acc.x);
-                    acc.y = fmaf(w[a], r.y, acc.y);
-                    acc.z = fmaf(w[a], r.z, acc.z);
-                    acc.w = fmaf(w[a], r.w, acc.w);
-                }
-                *(float4 *)(out + f) = acc;
-            }
-            return;
-        }
-    } else {
-        if ((k & 1) == 0 && aligned) {
-            for (int f = 0; f < k; f += 2) {
-                double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
-                for (int a = 0; a < NA; ++a) {
-                    const double2 r = *(const double2 *)(vin + rows[a] * k + f);
-                    acc.x = fma(w[a], r.x, acc.x);
-                    acc.y = fma(w[a], r.y, acc.y);
-                }
-                *(double2 *)(out + f) = acc;
-            }
-            return;
-        }
-    }
-    for (int f = 0; f < k; ++f) {
-        V acc = (V)0;
-#pragma unroll
-        for (int a = 0; a < NA; ++a)
-            acc = fma(w[a], vin[rows[a] * k + f], acc);
-        out[f] = acc;
-    }
-}
-
-// P1 / P2 values at a located point from internal element e and internal-order
-// barycentric coordinates th; rows are internal DOF ids, mapped through
-// row_map when the value array is in the user's order.
-template <typename R, typename V>
-__device__ inline void interp_point(const MeshView &mv, int order, int32_t e, const R th[3],
-                                    const V *__restrict__ vin, int k, const int32_t *__restrict__ row_map,
-                                    V outside, V *__restrict__ out)
-{
-    if (e < 0) {
-        for (int f = 0; f < k; ++f)
-            out[f] = outside;
-        return;
-    }
-    const TopRec t = mv.top[e];
-    if (order == 1) {
-        int64_t rows[3];
-        V w[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            rows[a] = row_map ? row_map[t.v[a]] : t.v[a];
-            w[a] = (V)th[a];
-        }
-        combine_rows<V, 3>(vin, rows, w, k, out);
-    } else {
-        const int4 te = mv.tedge[e];
-        const int32_t ev[3] = {te.x, te.y, te.z};
-        int64_t rows[6];
-        V w[6];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const int b = (a + 1) % 3, c = (a + 2) % 3;
-            rows[a] = row_map ? row_map[t.v[a]] : t.v[a];
-            rows[3 + a] = row_map ? row_map[ev[a]] : ev[a];
-            w[a] = (V)(th[a] * ((R)2 * th[a] - (R)1));
-            w[3 + a] = (V)((R)4 * th[b] * th[c]);
-        }
-        combine_rows<V, 6>(vin, rows, w, k, out);
-    }
-}
-
-template <bool F32, typename V>
-__global__ void __launch_bounds__(kBlock)
-    k_interp(MeshView mv, int order, const int32_t *__restrict__ elem, const typename CT<F32>::R *__restrict__ bary,
-             int64_t m, const V *__restrict__ vin, int k, V *__restrict__ vout, double outside, int user_rows)
-{
-    using R = typename CT<F32>::R;
-    const int32_t *row_map = user_rows ? mv.dof_user : nullptr;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t u = elem[i];
-        // ids outside [0, n_tris) are treated as outside
-        int32_t e = (u >= 0 && u < mv.n_tris) ? mv.tri_int[u] : -1;
-        R th[3] = {0, 0, 0};
-        if (e >= 0) {
-            // user vertex order -> internal order
-            const TopRec t = mv.top[e];
-            th[0] = bary[3 * i];
-            th[1] = (t.flags & 1) ? bary[3 * i + 2] : bary[3 * i + 1];
-            th[2] = (t.flags & 1) ? bary[3 * i + 1] : bary[3 * i + 2];
-        }
-        interp_point<R, V>(mv, order, e, th, vin, k, row_map, (V)outside, vout + i * (int64_t)k);
-    }
-}
+// ---------------------------------------------------------------------------
+// interpolation helpers
 
 template <typename VV>
 __device__ inline VV vv_zero();
@@ -706,6 +586,8 @@ template <>
 __device__ inline float4 vv_zero<float4>() { return make_float4(0.f, 0.f, 0.f, 0.f); }
 template <>
 __device__ inline double2 vv_zero<double2>() { return make_double2(0.0, 0.0); }
+__device__ inline float4 vv_fill(float v) { return make_float4(v, v, v, v); }
+__device__ inline double2 vv_fill(double v) { return make_double2(v, v); }
 __device__ inline void vv_fma(float w, const float4 r, float4 &acc)
 {
     acc.x = fmaf(w, r.x, acc.x);
@@ -719,24 +601,137 @@ __device__ inline void vv_fma(double w, const double2 r, double2 &acc)
     acc.y = fma(w, r.y, acc.y);
 }
 
-// Workgroups are dispatched to the 8 XCDs round-robin (block b runs on XCD
-// b mod 8).  Give each XCD one contiguous range of tiles instead, so that the
-// Morton-ordered tiles one XCD processes are spatially compact and the
-// triangle records and value rows they share stay in that XCD's L2.
-__device__ inline int64_t xcd_tile(int64_t b, int64_t nb)
+// Lagrange weights and value rows of a located point: P1 (NA = 3), the
+// barycentric coordinates; P2 (NA = 6), theta_a (2 theta_a - 1) at the
+// vertices and 4 theta_b theta_c at the midpoint of the edge opposite a.
+template <typename R, typename V, int NA>
+__device__ inline void lagrange(const MeshView &mv, int32_t e, const int32_t v[3], const R th[3], int32_t row[NA],
+                                V wgt[NA])
 {
-    constexpr int64_t kXcd = 8;
-    const int64_t q = nb / kXcd, r = nb % kXcd;
-    const int64_t x = b % kXcd, local = b / kXcd;
-    return x < r ? x * (q + 1) + local : r * (q + 1) + (x - r) * q + local;
+    if constexpr (NA == 3) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            row[a] = v[a];
+            wgt[a] = (V)th[a];
+        }
+    } else {
+        const int4 te = mv.tedge[e];
+        const int32_t ev[3] = {te.x, te.y, te.z};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int b = (a + 1) % 3, c = (a + 2) % 3;
+            row[a] = v[a];
+            row[3 + a] = ev[a];
+            wgt[a] = (V)(th[a] * ((R)2 * th[a] - (R)1));
+            wgt[3 + a] = (V)((R)4 * th[b] * th[c]);
+        }
+    }
 }
 
-// The fused step, one workgroup per tile of kBlock consecutive (Morton) DOFs.
-// Phase 1, one lane per foot: foot -> start -> walk -> tie rule -> weights;
-// the located element's value rows and weights go to LDS.  Phase 2, the
-// workgroup interpolates the tile's values cooperatively: work item
-// (foot, chunk of VW fields), consecutive lanes on consecutive chunks, so
-// the row gathers read whole row segments and the stores are contiguous.
+// Values of the 64 points of a wavefront, computed cooperatively: lane L of
+// pass p handles item p * 64 + L = (point f, chunk c of VW fields), reading
+// point f's rows and weights from lane f with cross-lane shuffles.  The
+// chunks of consecutive lanes are contiguous in memory (gathers read whole
+// row segments, stores are contiguous).  row[0] < 0 marks an outside point.
+// Every lane of the wavefront calls it (the shuffles need all of them).
+template <typename V, int NA>
+__device__ inline void wave_interp(const int32_t row[NA], const V wgt[NA], int nf, const V *__restrict__ vin, int k,
+                                   V *__restrict__ vout, const int32_t *__restrict__ out_map, int64_t base, V outside)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    constexpr int VW = sizeof(V) == 4 ? 4 : 2;
+    using VV = typename std::conditional<sizeof(V) == 4, float4, double2>::type;
+    const bool vec = (k % VW == 0) &&
+                     (((reinterpret_cast<uintptr_t>(vin) | reinterpret_cast<uintptr_t>(vout)) & 15) == 0);
+    const int chunks = vec ? k / VW : k;
+    const int total = nf * chunks;
+    // chunks is uniform; a power of two (the common k = 1, 4, 16 ...) divides by shifting
+    const bool pow2 = (chunks & (chunks - 1)) == 0;
+    const int sh = __builtin_ctz((unsigned)chunks);
+    for (int p0 = 0; p0 < total; p0 += kWave) {
+        const int it = p0 + lane;
+        const int q = pow2 ? (it >> sh) : it / chunks;
+        const int fl = it < total ? q : 0;
+        const int c = it - fl * chunks;
+        int32_t rr[NA];
+        V ww[NA];
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+            rr[a] = __shfl(row[a], fl, kWave);
+            ww[a] = __shfl(wgt[a], fl, kWave);
+        }
+        if (it < total) {
+            const int64_t o = out_map ? (int64_t)out_map[base + fl] : base + fl;
+            if (vec) {
+                VV acc = vv_zero<VV>();
+                if (rr[0] < 0) {
+                    acc = vv_fill(outside);
+                } else {
+#pragma unroll
+                    for (int a = 0; a < NA; ++a)
+                        vv_fma(ww[a], *((const VV *)(vin + (int64_t)rr[a] * k) + c), acc);
+                }
+                *((VV *)(vout + o * (int64_t)k) + c) = acc;
+            } else {
+                V acc = outside;
+                if (rr[0] >= 0) {
+                    acc = (V)0;
+#pragma unroll
+                    for (int a = 0; a < NA; ++a)
+                        acc = fma(ww[a], vin[(int64_t)rr[a] * k + c], acc);
+                }
+                vout[o * (int64_t)k + c] = acc;
+            }
+        }
+    }
+}
+
+template <bool F32, typename V, int NA>
+__global__ void __launch_bounds__(kBlock)
+    k_interp(MeshView mv, const int32_t *__restrict__ elem, const typename CT<F32>::R *__restrict__ bary, int64_t m,
+             const V *__restrict__ vin, int k, V *__restrict__ vout, double outside, int user_rows)
+{
+    using R = typename CT<F32>::R;
+    const int64_t base = xcd_tile(blockIdx.x, gridDim.x) * kBlock + (threadIdx.x & ~(kWave - 1));
+    const int64_t i = base + (threadIdx.x & (kWave - 1));
+    int32_t row[NA];
+    V wgt[NA];
+    row[0] = -1;
+#pragma unroll
+    for (int a = 1; a < NA; ++a)
+        row[a] = 0;
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+        wgt[a] = (V)0;
+    if (i < m) {
+        const int32_t u = elem[i];
+        // ids outside [0, n_tris) are treated as outside
+        const int32_t e = (u >= 0 && u < mv.n_tris) ? mv.tri_int[u] : -1;
+        if (e >= 0) {
+            const GeoRec r = mv.geo[e];
+            const bool flip = mv.tri_uf[e] < 0;
+            // user vertex order -> internal order
+            R th[3];
+            th[0] = bary[3 * i];
+            th[1] = flip ? bary[3 * i + 2] : bary[3 * i + 1];
+            th[2] = flip ? bary[3 * i + 1] : bary[3 * i + 2];
+            lagrange<R, V, NA>(mv, e, r.v, th, row, wgt);
+            if (user_rows) {
+#pragma unroll
+                for (int a = 0; a < NA; ++a)
+                    row[a] = mv.dof_user[row[a]];
+            }
+        }
+    }
+    if (base >= m)
+        return;
+    const int nf = (int)min<int64_t>(kWave, m - base);
+    wave_interp<V, NA>(row, wgt, nf, vin, k, vout, nullptr, base, (V)outside);
+}
+
+// The fused step (Algorithm 2, one pass of its loop): one lane per foot for
+// foot -> start -> walk -> tie rule -> weights; then the wavefront computes
+// its 64 feet's values cooperatively.
 template <bool F32, typename V, int NA>
 __global__ void __launch_bounds__(kBlock)
     k_step(MeshView mv, FieldDev f, double dt, int scheme, int mode, const int32_t *__restrict__ start,
@@ -745,100 +740,41 @@ __global__ void __launch_bounds__(kBlock)
 {
     using R = typename CT<F32>::R;
     using R2 = typename CT<F32>::R2;
-    __shared__ int32_t s_row[NA][kBlock];
-    __shared__ V s_w[NA][kBlock];
-    const int64_t base = xcd_tile(blockIdx.x, gridDim.x) * kBlock;
-    const int tid = threadIdx.x;
-    const int64_t d = base + tid;
+    const int64_t base = xcd_tile(blockIdx.x, gridDim.x) * kBlock + (threadIdx.x & ~(kWave - 1));
+    const int64_t d = base + (threadIdx.x & (kWave - 1));
     LaneStats ls;
+    int32_t row[NA];
+    V wgt[NA];
+    row[0] = -1;
+#pragma unroll
+    for (int a = 1; a < NA; ++a)
+        row[a] = 0;
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+        wgt[a] = (V)0;
     if (d < n_iter) {
-        const WalkParams wp = walk_params(mv);
         const R2 x = ((const R2 *)mv.dof_xy)[d];
         R qx, qy;
         foot_of<R>(f, scheme, x.x, x.y, (R)dt, qx, qy);
-        WalkResult<R> w;
-        w.elem = -1;
-        w.uid = -1;
-        w.steps = 0;
-        w.flags = 0;
+        WalkResult<R> w = outside_result<R>(0, 0);
         if (in_box<R>(qx, qy, mv.bb)) {
             const int64_t api = (mode == SLW_START_GIVEN && !mv.internal_order) ? mv.dof_user[d] : d;
             const int32_t j0 = start_for<F32>(mv, d, api, mode, start, (float)(qx - x.x), (float)(qy - x.y));
-            w = walk<F32>(wp, j0, qx, qy, (uint32_t)d * 2654435761u, ls.c);
+            w = walk<F32>(mv, j0, qx, qy, (uint32_t)d * 2654435761u, ls.c);
         }
         if (write_prev)
             mv.prev[d] = w.elem;
         if (st)
             ls.add(w);
-        if (w.elem >= 0) {
-            const TopRec t = mv.top[w.elem];
-            if constexpr (NA == 3) {
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    s_row[a][tid] = t.v[a];
-                    s_w[a][tid] = (V)w.th[a];
-                }
-            } else {
-                const int4 te = mv.tedge[w.elem];
-                const int32_t ev[3] = {te.x, te.y, te.z};
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const int b = (a + 1) % 3, c = (a + 2) % 3;
-                    s_row[a][tid] = t.v[a];
-                    s_row[3 + a][tid] = ev[a];
-                    s_w[a][tid] = (V)(w.th[a] * ((R)2 * w.th[a] - (R)1));
-                    s_w[3 + a][tid] = (V)((R)4 * w.th[b] * w.th[c]);
-                }
-            }
-        } else {
-            s_row[0][tid] = -1;
-        }
+        if (w.elem >= 0)
+            lagrange<R, V, NA>(mv, w.elem, w.v, w.th, row, wgt);
     }
     if (st)
         flush_stats(ls, st);
-    __syncthreads();
-
-    const int nf = (int)min<int64_t>(kBlock, n_iter - base);
-    constexpr int VW = sizeof(V) == 4 ? 4 : 2;  // fields per 16-byte chunk
-    const bool aligned = ((reinterpret_cast<uintptr_t>(vin) | reinterpret_cast<uintptr_t>(vout)) & 15) == 0;
-    if (aligned && k % VW == 0) {
-        using VV = typename std::conditional<sizeof(V) == 4, float4, double2>::type;
-        const int chunks = k / VW;
-        for (int it = tid; it < nf * chunks; it += kBlock) {
-            const int fl = it / chunks, c = it - fl * chunks;
-            const int64_t o = out_map ? out_map[base + fl] : base + fl;
-            VV *dst = (VV *)(vout + o * (int64_t)k) + c;
-            const int32_t r0 = s_row[0][fl];
-            if (r0 < 0) {
-                VV z;
-                if constexpr (VW == 4)
-                    z = make_float4((float)outside, (float)outside, (float)outside, (float)outside);
-                else
-                    z = make_double2(outside, outside);
-                *dst = z;
-                continue;
-            }
-            VV acc = vv_zero<VV>();
-#pragma unroll
-            for (int a = 0; a < NA; ++a)
-                vv_fma(s_w[a][fl], *((const VV *)(vin + (int64_t)s_row[a][fl] * k) + c), acc);
-            *dst = acc;
-        }
-    } else {
-        for (int it = tid; it < nf * k; it += kBlock) {
-            const int fl = it / k, c = it - fl * k;
-            const int64_t o = out_map ? out_map[base + fl] : base + fl;
-            const int32_t r0 = s_row[0][fl];
-            V acc = (V)outside;
-            if (r0 >= 0) {
-                acc = (V)0;
-#pragma unroll
-                for (int a = 0; a < NA; ++a)
-                    acc = fma(s_w[a][fl], vin[(int64_t)s_row[a][fl] * k + c], acc);
-            }
-            vout[o * (int64_t)k + c] = acc;
-        }
-    }
+    if (base >= n_iter)
+        return;
+    const int nf = (int)min<int64_t>(kWave, n_iter - base);
+    wave_interp<V, NA>(row, wgt, nf, vin, k, vout, out_map, base, (V)outside);
 }
 
 __global__ void k_permute_rows(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst, int64_t rows,
@@ -862,30 +798,47 @@ __global__ void k_zero_u64(unsigned long long *p, int n)
         p[i] = 0ull;
 }
 
-inline int grid_for(int64_t n)
+// number of kBlock tiles covering n items (one workgroup per tile)
+inline bool tiles_for(int64_t n, unsigned &g)
 {
-    int64_t g = (n + kBlock - 1) / kBlock;
-    if (g < 1)
-        g = 1;
-    if (g > (int64_t)1 << 20)
-        g = (int64_t)1 << 20;
-    return (int)g;
+    const int64_t t = (n + kBlock - 1) / kBlock;
+    if (t > (int64_t)INT32_MAX)
+        return false;
+    g = (unsigned)(t < 1 ? 1 : t);
+    return true;
 }
 
 }  // namespace
+
+void field_time_factors(FieldDev &f, double t_np1, double dt)
+{
+    const double pi = 3.14159265358979323846;
+    const double t[2] = {t_np1, t_np1 - 0.5 * dt};
+    for (int i = 0; i < 2; ++i) {
+        if (f.kind == 2)
+            f.g[i] = cos(pi * t[i] / f.p[0]);
+        else if (f.kind == 3)
+            f.g[i] = f.p[1] * t[i];
+        else
+            f.g[i] = 0.0;
+    }
+}
 
 hipError_t launch_locate(const DevMesh &m, hipStream_t st, const void *q, int64_t mp, const int32_t *start,
                          int32_t *elem, void *bary, int32_t *steps, DevStats *stats)
 {
     if (mp == 0)
         return hipSuccess;
+    unsigned g;
+    if (!tiles_for(mp, g))
+        return hipErrorInvalidValue;
     MeshView mv = view_of(m);
     if (m.coords_f32)
-        hipLaunchKernelGGL(k_locate<true>, dim3(grid_for(mp)), dim3(kBlock), 0, st, mv, (const float2 *)q, mp, start,
-                           elem, (float *)bary, steps, stats);
+        hipLaunchKernelGGL(k_locate<true>, dim3(g), dim3(kBlock), 0, st, mv, (const float2 *)q, mp, start, elem,
+                           (float *)bary, steps, stats);
     else
-        hipLaunchKernelGGL(k_locate<false>, dim3(grid_for(mp)), dim3(kBlock), 0, st, mv, (const double2 *)q, mp,
-                           start, elem, (double *)bary, steps, stats);
+        hipLaunchKernelGGL(k_locate<false>, dim3(g), dim3(kBlock), 0, st, mv, (const double2 *)q, mp, start, elem,
+                           (double *)bary, steps, stats);
     return hipGetLastError();
 }
 
@@ -893,15 +846,18 @@ hipError_t launch_locate_feet(const DevMesh &m, hipStream_t st, const FieldDev *
                               int scheme, int mode, const int32_t *start, bool feet_in, void *feet, int32_t *elem,
                               void *bary, int32_t *steps, DevStats *stats)
 {
+    unsigned g;
+    if (!tiles_for(m.n_dofs, g))
+        return hipErrorInvalidValue;
     MeshView mv = view_of(m);
     FieldDev fd = f ? *f : FieldDev{0, {0, 0, 0, 0, 0, 0, 0, 0}, {0, 0}};
     field_time_factors(fd, t_np1, dt);
     if (m.coords_f32)
-        hipLaunchKernelGGL(k_locate_feet<true>, dim3(grid_for(m.n_dofs)), dim3(kBlock), 0, st, mv, fd, t_np1, dt,
-                           scheme, mode, start, (int)feet_in, (float2 *)feet, elem, (float *)bary, steps, stats);
+        hipLaunchKernelGGL(k_locate_feet<true>, dim3(g), dim3(kBlock), 0, st, mv, fd, dt, scheme, mode, start,
+                           (int)feet_in, (float2 *)feet, elem, (float *)bary, steps, stats);
     else
-        hipLaunchKernelGGL(k_locate_feet<false>, dim3(grid_for(m.n_dofs)), dim3(kBlock), 0, st, mv, fd, t_np1, dt,
-                           scheme, mode, start, (int)feet_in, (double2 *)feet, elem, (double *)bary, steps, stats);
+        hipLaunchKernelGGL(k_locate_feet<false>, dim3(g), dim3(kBlock), 0, st, mv, fd, dt, scheme, mode, start,
+                           (int)feet_in, (double2 *)feet, elem, (double *)bary, steps, stats);
     return hipGetLastError();
 }
 
@@ -911,27 +867,27 @@ hipError_t launch_interp(const DevMesh &m, hipStream_t st, int order, const int3
 {
     if (mp == 0)
         return hipSuccess;
+    unsigned g;
+    if (!tiles_for(mp, g))
+        return hipErrorInvalidValue;
     MeshView mv = view_of(m);
-    const int g = grid_for(mp);
+#define SLW_INTERP(F32, V, NA)                                                                                     \
+    hipLaunchKernelGGL((k_interp<F32, V, NA>), dim3(g), dim3(kBlock), 0, st, mv, elem,                            \
+                       (const typename CT<F32>::R *)bary, mp, (const V *)v_in, k, (V *)v_out, outside, (int)user_order)
     if (m.coords_f32) {
-        if (vdtype == SLW_F32)
-            hipLaunchKernelGGL((k_interp<true, float>), dim3(g), dim3(kBlock), 0, st, mv, order, elem,
-                               (const float *)bary, mp, (const float *)v_in, k, (float *)v_out, outside,
-                               (int)user_order);
-        else
-            hipLaunchKernelGGL((k_interp<true, double>), dim3(g), dim3(kBlock), 0, st, mv, order, elem,
-                               (const float *)bary, mp, (const double *)v_in, k, (double *)v_out, outside,
-                               (int)user_order);
+        if (vdtype == SLW_F32) {
+            if (order == 1) SLW_INTERP(true, float, 3); else SLW_INTERP(true, float, 6);
+        } else {
+            if (order == 1) SLW_INTERP(true, double, 3); else SLW_INTERP(true, double, 6);
+        }
     } else {
-        if (vdtype == SLW_F32)
-            hipLaunchKernelGGL((k_interp<false, float>), dim3(g), dim3(kBlock), 0, st, mv, order, elem,
-                               (const double *)bary, mp, (const float *)v_in, k, (float *)v_out, outside,
-                               (int)user_order);
-        else
-            hipLaunchKernelGGL((k_interp<false, double>), dim3(g), dim3(kBlock), 0, st, mv, order, elem,
-                               (const double *)bary, mp, (const double *)v_in, k, (double *)v_out, outside,
-                               (int)user_order);
+        if (vdtype == SLW_F32) {
+            if (order == 1) SLW_INTERP(false, float, 3); else SLW_INTERP(false, float, 6);
+        } else {
+            if (order == 1) SLW_INTERP(false, double, 3); else SLW_INTERP(false, double, 6);
+        }
     }
+#undef SLW_INTERP
     return hipGetLastError();
 }
 
@@ -943,15 +899,12 @@ hipError_t launch_step(const DevMesh &m, hipStream_t st, const FieldDev &f0, dou
     FieldDev f = f0;
     field_time_factors(f, t_n + dt, dt);
     const int64_t n_iter = order == 1 ? m.n_nodes : m.n_dofs;
-    const int64_t tiles = (n_iter + kBlock - 1) / kBlock;
-    if (tiles == 0)
-        return hipSuccess;
-    if (tiles > (int64_t)INT32_MAX)
+    unsigned g;
+    if (!tiles_for(n_iter, g))
         return hipErrorInvalidValue;
-    const dim3 g((unsigned)tiles), b(kBlock);
 #define SLW_STEP(F32, V, NA)                                                                                   \
-    hipLaunchKernelGGL((k_step<F32, V, NA>), g, b, 0, st, mv, f, dt, scheme, mode, start, (const V *)v_in, k, \
-                       (V *)v_out, outside, (int)write_prev, out_map, n_iter, stats)
+    hipLaunchKernelGGL((k_step<F32, V, NA>), dim3(g), dim3(kBlock), 0, st, mv, f, dt, scheme, mode, start,    \
+                       (const V *)v_in, k, (V *)v_out, outside, (int)write_prev, out_map, n_iter, stats)
     if (m.coords_f32) {
         if (vdtype == SLW_F32) {
             if (order == 1) SLW_STEP(true, float, 3); else SLW_STEP(true, float, 6);
@@ -969,20 +922,6 @@ hipError_t launch_step(const DevMesh &m, hipStream_t st, const FieldDev &f0, dou
     return hipGetLastError();
 }
 
-void field_time_factors(FieldDev &f, double t_np1, double dt)
-{
-    const double pi = 3.14159265358979323846;
-    const double t[2] = {t_np1, t_np1 - 0.5 * dt};
-    for (int i = 0; i < 2; ++i) {
-        if (f.kind == 2)
-            f.g[i] = cos(pi * t[i] / f.p[0]);
-        else if (f.kind == 3)
-            f.g[i] = f.p[1] * t[i];
-        else
-            f.g[i] = 0.0;
-    }
-}
-
 hipError_t launch_zero_stats(hipStream_t st, DevStats *p)
 {
     const int n = (int)(sizeof(DevStats) / sizeof(unsigned long long));
@@ -996,7 +935,9 @@ hipError_t launch_permute_rows(hipStream_t st, const void *src, void *dst, int64
     if (rows == 0)
         return hipSuccess;
     const int64_t words = row_bytes / 4;
-    hipLaunchKernelGGL(k_permute_rows, dim3(grid_for(rows * words)), dim3(kBlock), 0, st, (const uint32_t *)src,
+    int64_t g = (rows * words + kBlock - 1) / kBlock;
+    g = g < 1 ? 1 : (g > ((int64_t)1 << 20) ? ((int64_t)1 << 20) : g);
+    hipLaunchKernelGGL(k_permute_rows, dim3((unsigned)g), dim3(kBlock), 0, st, (const uint32_t *)src,
                        (uint32_t *)dst, rows, words, map, scatter);
     return hipGetLastError();
 }

@@ -28,6 +28,13 @@ namespace slw {
 
 namespace {
 
+// Star entry of a DOF: an incident triangle and the pseudo-angle (in [0, 4))
+// of the direction where its angular sector at the DOF begins.
+struct StarEnt {
+    float ang;
+    int32_t tri;
+};
+
 // Monotone stand-in for the polar angle of (dx, dy): 0 along +x, increasing
 // counter-clockwise, in [0, 4).
 double pseudo_angle(double dx, double dy)
@@ -96,9 +103,36 @@ bool coord_ok(double v)
 
 }  // namespace
 
+FilterConst filter_constants(bool f32, double cx, double cy, double cmax)
+{
+    FilterConst fc;
+    const double u = 0x1p-24;
+    const double M = cmax * (1.0 + 0x1p-40);
+    if (f32) {
+        fc.c1 = (float)(3.0 * u + 64.0 * u * u);
+        fc.c2 = 0.0f;
+        fc.c3 = 0x1p-140f;
+    } else {
+        fc.c1 = (float)(4.0 * u + 64.0 * u * u);
+        const double c2 = (2.0 * u + 64.0 * u * u) * M;
+        const double c3 = 64.0 * u * u * M * M + 0x1p-140;
+        // rounded up, so the bound is never below its derivation
+        fc.c2 = std::nextafter((float)c2, INFINITY);
+        fc.c3 = std::nextafter((float)c3, INFINITY);
+        if (!(c2 < 1e30 && c3 < 1e30)) {  // huge coordinates: the filter never certifies
+            fc.c2 = INFINITY;
+            fc.c3 = INFINITY;
+        }
+    }
+    fc.c1 = std::nextafter(fc.c1, INFINITY);
+    fc.cx = cx;
+    fc.cy = cy;
+    return fc;
+}
+
 void free_mesh(DevMesh &m)
 {
-    void *ptrs[] = {m.geo, m.top, m.tedge, m.dof_xy, m.star_ptr, m.star, m.vmin, m.dof_user,
+    void *ptrs[] = {m.geo, m.tri_uf, m.tedge, m.dof_xy, m.qstart, m.vmin, m.dof_user,
                     m.dof_int, m.tri_int, m.prev_elem, m.jump};
     for (void *p : ptrs)
         if (p)
@@ -298,44 +332,40 @@ slw_status build_mesh(slw_ctx *ctx, const double *xy, int64_t n, const int32_t *
     const int64_t ndof = n + ne;
 
     // ---------------- device records ----------------
-    std::vector<GeoRec64> geo64(f32 ? 0 : nt);
-    std::vector<GeoRec32> geo32(f32 ? nt : 0);
-    std::vector<TopRec> top(nt);
+    // float copies of the coordinates for the walk's filter: double meshes
+    // subtract the box centre first (smaller magnitudes, tighter bound)
+    const double ccx = f32 ? 0.0 : 0.5 * (bb[0] + bb[2]), ccy = f32 ? 0.0 : 0.5 * (bb[1] + bb[3]);
+    double cmax = 0.0;  // largest |coordinate - centre| (after the double subtraction)
+    for (int64_t i = 0; i < n; ++i)
+        cmax = std::max(cmax, std::max(std::fabs(X[2 * i] - ccx), std::fabs(X[2 * i + 1] - ccy)));
+    std::vector<GeoRec> geo(nt);
+    std::vector<int32_t> tri_uf(nt);
     std::vector<int4> tedge(p2 ? nt : 0);
     for (int64_t ti = 0; ti < nt; ++ti) {
         int64_t t = tri_u[ti];
-        TopRec tr;
-        tr.flags = flip[t];
-        for (int k = 0; k < 3; ++k)
-            tr.v[k] = node_i[T[3 * t + k]];
-        top[ti] = tr;
-        int32_t nbi[3];
-        for (int k = 0; k < 3; ++k)
-            nbi[k] = NB[3 * t + k] < 0 ? -1 : tri_i[NB[3 * t + k]];
-        if (f32) {
-            GeoRec32 g;
-            std::memset(&g, 0, sizeof g);
-            for (int k = 0; k < 3; ++k) {
-                g.p[k] = make_float2((float)X[2 * T[3 * t + k]], (float)X[2 * T[3 * t + k] + 1]);
-                g.nb[k] = nbi[k];
-            }
-            g.uid = (int32_t)t;
-            geo32[ti] = g;
-        } else {
-            GeoRec64 g;
-            std::memset(&g, 0, sizeof g);
-            for (int k = 0; k < 3; ++k) {
-                g.p[k] = make_double2(X[2 * T[3 * t + k]], X[2 * T[3 * t + k] + 1]);
-                g.nb[k] = nbi[k];
-            }
-            g.uid = (int32_t)t;
-            geo64[ti] = g;
+        GeoRec g;
+        std::memset(&g, 0, sizeof g);
+        for (int k = 0; k < 3; ++k) {
+            const int64_t u = T[3 * t + k];
+            g.p[k] = make_float2((float)(X[2 * u] - ccx), (float)(X[2 * u + 1] - ccy));
+            g.nb[k] = NB[3 * t + k] < 0 ? -1 : tri_i[NB[3 * t + k]];
+            g.v[k] = node_i[u];
         }
+        geo[ti] = g;
+        tri_uf[ti] = (int32_t)((uint32_t)t | ((uint32_t)flip[t] << 31));
         if (p2)
             tedge[ti] = make_int4((int32_t)(n + edge_i[tri_edge_user[3 * t]]),
                                   (int32_t)(n + edge_i[tri_edge_user[3 * t + 1]]),
                                   (int32_t)(n + edge_i[tri_edge_user[3 * t + 2]]), 0);
     }
+    // Error bound of the float filter, derived for inputs a~ = fl32(a - c),
+    // b~, q~ (|a - c|, |q - c| <= M): the rounded differences carry an absolute
+    // error <= 2uM + u|diff|, which gives
+    //   |det_float - det| <= (4u + O(u^2))(|l| + |r|) + 2uM (|ax|+|ay|+|bx|+|by|) + O(u^2 M^2);
+    // the constants below add slack for the second-order terms, for rounding
+    // in the bound's own evaluation and for subnormal results.  Float meshes
+    // round nothing (c2 = 0): then it is the static bound (3u + 16u^2).
+    const FilterConst fc = filter_constants(f32, ccx, ccy, cmax);
 
     // DOF coordinates (user order on the host, internal order on the device);
     // edge midpoints are (a + b) * 0.5 in double
@@ -366,7 +396,7 @@ slw_status build_mesh(slw_ctx *ctx, const double *xy, int64_t n, const int32_t *
     std::vector<int32_t> sptr(ndof + 1, 0);
     for (int64_t ti = 0; ti < nt; ++ti)
         for (int k = 0; k < 3; ++k)
-            sptr[top[ti].v[k] + 1]++;
+            sptr[geo[ti].v[k] + 1]++;
     for (int64_t e = 0; e < ne; ++e) {
         int64_t eu = edge_u[e];
         sptr[n + e + 1] = (edge_left[eu] >= 0) + (edge_right[eu] >= 0);
@@ -400,6 +430,22 @@ slw_status build_mesh(slw_ctx *ctx, const double *xy, int64_t n, const int32_t *
         for (int64_t d = 0; d < ndof; ++d)
             std::sort(star.begin() + sptr[d], star.begin() + sptr[d + 1],
                       [](const StarEnt &x, const StarEnt &y) { return x.ang < y.ang; });
+    }
+    // the incident triangle facing each diagonal direction (45, 135, 225 and
+    // 315 degrees; pseudo-angles 0.5, 1.5, 2.5, 3.5): the sector whose start
+    // is the last one at or before that direction, cyclically
+    std::vector<int4> qstart(ndof);
+    for (int64_t d = 0; d < ndof; ++d) {
+        int32_t sel[4];
+        for (int q = 0; q < 4; ++q) {
+            const float dir = 0.5f + (float)q;
+            int32_t pick = sptr[d + 1] - 1;
+            for (int32_t s2 = sptr[d]; s2 < sptr[d + 1]; ++s2)
+                if (star[s2].ang <= dir)
+                    pick = s2;
+            sel[q] = star[pick].tri;
+        }
+        qstart[d] = make_int4(sel[0], sel[1], sel[2], sel[3]);
     }
     // smallest user triangle id around each node (vertex tie rule)
     std::vector<int32_t> vmin(n);
@@ -478,6 +524,7 @@ slw_status build_mesh(slw_ctx *ctx, const double *xy, int64_t n, const int32_t *
     for (int i = 0; i < 4; ++i)
         m.bbox[i] = bb[i];
     m.jump_g = g;
+    m.fc = fc;
     slw_status st = SLW_OK;
     int64_t bytes = 0;
 #define UP(vec, ptr)                                   \
@@ -488,10 +535,9 @@ slw_status build_mesh(slw_ctx *ctx, const double *xy, int64_t n, const int32_t *
             return st;                                 \
         }                                              \
     } while (0)
+    UP(geo, m.geo);
+    UP(tri_uf, m.tri_uf);
     if (f32) {
-        GeoRec32 *g32 = nullptr;
-        UP(geo32, g32);
-        m.geo = g32;
         std::vector<float2> dxy(ndof);
         for (int64_t d = 0; d < ndof; ++d)
             dxy[d] = make_float2((float)dof_user_xy[2 * dof_u[d]], (float)dof_user_xy[2 * dof_u[d] + 1]);
@@ -499,9 +545,6 @@ slw_status build_mesh(slw_ctx *ctx, const double *xy, int64_t n, const int32_t *
         UP(dxy, p);
         m.dof_xy = p;
     } else {
-        GeoRec64 *g64 = nullptr;
-        UP(geo64, g64);
-        m.geo = g64;
         std::vector<double2> dxy(ndof);
         for (int64_t d = 0; d < ndof; ++d)
             dxy[d] = make_double2(dof_user_xy[2 * dof_u[d]], dof_user_xy[2 * dof_u[d] + 1]);
@@ -509,11 +552,9 @@ slw_status build_mesh(slw_ctx *ctx, const double *xy, int64_t n, const int32_t *
         UP(dxy, p);
         m.dof_xy = p;
     }
-    UP(top, m.top);
     if (p2)
         UP(tedge, m.tedge);
-    UP(sptr, m.star_ptr);
-    UP(star, m.star);
+    UP(qstart, m.qstart);
     UP(vmin, m.vmin);
     UP(dof_u, m.dof_user);
     UP(dof_i, m.dof_int);

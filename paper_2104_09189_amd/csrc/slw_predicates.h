@@ -139,6 +139,27 @@ SLW_HD int orient_sign64(double ax, double ay, double bx, double by, double cx, 
     return orient_exact_sign(ax, ay, bx, by, cx, cy);
 }
 
+// The walk's float filter: differences (a~ - q~), (b~ - q~) of inputs that
+// were rounded to float (after subtracting a common centre), and the
+// coefficients of the error bound derived for that rounding (see
+// filter_constants).  Returns +1 / -1 when the sign of the exact determinant
+// is certified, 0 when it is not; det receives the float determinant.
+//   det = fma(dxa, dyb, -(dya dxb)): one rounding fewer than l - r, so the
+//   bound derived for l - r still holds;
+//   |l| + |r| <= Sa Sb with Sv = |dxv| + |dyv|, so c1 Sa Sb + c2 (Sa + Sb) + c3
+//   is at least the derived bound (the slack in c1, c2 absorbs the
+//   rounding of this expression itself).
+SLW_HD int filter_sign_f32(float dxa, float dya, float dxb, float dyb, float c1, float c2, float c3, float &det)
+{
+    det = fmaf(dxa, dyb, -(dya * dxb));
+    const float sa = fabsf(dxa) + fabsf(dya);
+    const float sb = fabsf(dxb) + fabsf(dyb);
+    const float bnd = fmaf(c1, sa * sb, fmaf(c2, sa + sb, c3));
+    if (!(fabsf(det) > bnd))
+        return 0;
+    return det > 0.0f ? 1 : -1;
+}
+
 // Exact sign for float inputs, stages 1-3.
 SLW_HD int orient_sign32(float ax, float ay, float bx, float by, float cx, float cy)
 {

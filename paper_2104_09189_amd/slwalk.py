@@ -105,11 +105,13 @@ _sig("slw_step", ctypes.c_int, [_vp, ctypes.POINTER(slw_field), _dbl, _dbl, ctyp
                                 ctypes.POINTER(slw_stats)])
 _sig("slw_permute_rows", ctypes.c_int, [_vp, _vp, _vp, _i64, ctypes.c_int])
 _sig("slw_orient_sign_host", ctypes.c_int, [_vp, _i64, _vp, ctypes.c_int])
+_sig("slw_float_filter_host", ctypes.c_int, [_vp, _i64, _dbl, _dbl, _dbl, ctypes.c_int, _vp])
 
 EXPORTED = ["slw_status_string", "slw_last_error", "slw_ctx_create", "slw_ctx_set_stream", "slw_ctx_destroy",
             "slw_mesh_upload", "slw_mesh_check", "slw_mesh_free", "slw_mesh_get_info", "slw_mesh_dof_coords", "slw_mesh_dof_order",
             "slw_mesh_set_walk_limits", "slw_locate", "slw_locate_feet", "slw_interpolate", "slw_step",
-            "slw_permute_rows", "slw_orient_sign_host"]
+            "slw_permute_rows", "slw_orient_sign_host",
+            "slw_float_filter_host"]
 
 
 def _check(rc: int, where: str):
@@ -380,6 +382,15 @@ def slw_orient_sign_host(pts, mode: int = 0) -> np.ndarray:
     out = np.empty(pts.shape[0], dtype=np.int8)
     _check(_lib.slw_orient_sign_host(pts.ctypes.data_as(_vp), pts.shape[0], out.ctypes.data_as(_vp), int(mode)),
            "slw_orient_sign_host")
+    return out
+
+
+def slw_float_filter_host(pts, cx: float, cy: float, cmax: float, f32: bool = False) -> np.ndarray:
+    """The walk's float filter on the host: certified sign, or 2 when deferred."""
+    pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 6)
+    out = np.empty(pts.shape[0], dtype=np.int8)
+    _check(_lib.slw_float_filter_host(pts.ctypes.data_as(_vp), pts.shape[0], float(cx), float(cy), float(cmax),
+                                      int(f32), out.ctypes.data_as(_vp)), "slw_float_filter_host")
     return out
 
 

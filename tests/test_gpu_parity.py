@@ -225,8 +225,9 @@ def test_start_modes_and_step_cap_do_not_change_results(S, C, orc):
 
 def test_walk_steps_plateau_random_incident_start(S, C, orc):
     """Section 2.2 remark: a random incident start costs about 1.5 element
-    changes even when the query is the start node; the field-steered start
-    costs none."""
+    changes even when the query is the start node; the start steered by the
+    foot's direction (the incident triangle facing the diagonal of its
+    quadrant) costs a fraction of one."""
     xy, tri = I.jittered_grid(300, 21)
     mesh = S.Mesh(C, xy, tri)
     rng = np.random.default_rng(8)
@@ -248,7 +249,7 @@ def test_walk_steps_plateau_random_incident_start(S, C, orc):
     mean_random = host(out["steps"])[ok].mean()
     assert 1.2 < mean_random < 1.8, mean_random
     out = mesh.locate_feet(feet=dev(q), feet_in=True, want_steps=True)
-    assert host(out["steps"])[ok].mean() < 0.05
+    assert host(out["steps"])[ok].mean() < 0.4
 
 
 def test_interpolate_entry_point(S, C, orc):

@@ -148,3 +148,58 @@ def test_library_predicate_matches_oracle_exact_sign(S, orc):
     # float pipeline: exact on the inputs rounded to float
     p32 = pts.astype(np.float32).astype(np.float64)
     assert (S.slw_orient_sign_host(pts, 2) == orc.orient_sign_batch(p32, use_filter=False)).all()
+
+
+def _filter_cases(rng, m, scale, h):
+    """Walk-like triples: an edge a-b of length ~h somewhere in a box of
+    half-width `scale` about 0.5, and a query q at distances from the edge's
+    line that range from ~h down to zero (points exactly on the line, and
+    points a few float ulps off it)."""
+    c = np.array([0.5, 0.5])
+    a = c + rng.uniform(-scale, scale, (m, 2))
+    ang = rng.uniform(0, 2 * np.pi, m)
+    b = a + h * np.stack([np.cos(ang), np.sin(ang)], axis=1)
+    t = rng.uniform(-1.5, 2.5, m)[:, None]
+    on = a + t * (b - a)
+    nrm = np.stack([-np.sin(ang), np.cos(ang)], axis=1)
+    off = h * 10.0 ** rng.uniform(-12, 0, m)[:, None] * rng.choice([-1.0, 1.0], (m, 1))
+    q = on + off
+    k = m // 4
+    q[:k] = on[:k]                              # rounded points of the line (near-zero determinants)
+    q[k:2 * k] = np.nextafter(on[k:2 * k], np.inf)
+    return np.concatenate([a, b, q], axis=1)
+
+
+def test_walk_float_filter_never_certifies_a_wrong_sign(S, orc):
+    rng = np.random.default_rng(5)
+    for scale, h in ((0.5, 7e-4), (0.5, 1.3e-5), (0.5, 0.05), (3.0e3, 2.0), (1e-3, 1e-6)):
+        pts = _filter_cases(rng, 60000, scale, h)
+        cmax = float(np.abs(pts - 0.5).max())
+        got = S.slw_float_filter_host(pts, 0.5, 0.5, cmax)
+        exact = orc.orient_sign_batch(pts, use_filter=False)
+        cert = got != 2
+        assert (got[cert] == exact[cert]).all(), (scale, h)
+        # it does certify the larger offsets (the share shrinks as h/scale does)
+        assert cert.mean() > 0.05, (scale, h, cert.mean())
+    # float meshes: inputs already float, the plain static bound
+    pts = _filter_cases(rng, 60000, 0.5, 7e-4).astype(np.float32).astype(np.float64)
+    got = S.slw_float_filter_host(pts, 0.0, 0.0, 0.0, f32=True)
+    exact = orc.orient_sign_batch(pts, use_filter=False)
+    cert = got != 2
+    assert (got[cert] == exact[cert]).all()
+    assert cert.mean() > 0.1
+
+
+def test_walk_float_filter_certifies_typical_walk_tests(S, orc):
+    # queries uniformly around a triangle of size h: nearly always certified
+    rng = np.random.default_rng(6)
+    h = 1.0 / 1414
+    a = rng.uniform(0, 1, (50000, 2))
+    b = a + rng.uniform(-h, h, (50000, 2))
+    q = a + rng.uniform(-3 * h, 3 * h, (50000, 2))
+    pts = np.concatenate([a, b, q], axis=1)
+    got = S.slw_float_filter_host(pts, 0.5, 0.5, 0.5)
+    exact = orc.orient_sign_batch(pts, use_filter=False)
+    cert = got != 2
+    assert (got[cert] == exact[cert]).all()
+    assert cert.mean() > 0.99, cert.mean()
