@@ -4,19 +4,26 @@ one MI355X, through the C-ABI.
 Workload (default): the graded 1415 x 1415 grid refined towards the circle
 r = 1/4 (2,002,225 nodes, 3,998,792 triangles), time-dependent swirl with
 period 1, explicit-midpoint (RK2) feet, Courant number 5 on the
-computational spacing, P1, FP64 coordinates and walk, 16 FP32 Gaussian-hill
-fields sharing one location.  A step is one fused launch over all nodes.
+computational spacing, P1, FP64 coordinates and feet, 16 FP32 Gaussian-hill
+fields sharing one location.  A step is one fused kernel launch over all
+nodes: foot, start element, barycentric walk, tie rule, weights, values.
+
+The headline is strategy (a) of the paper (the walk starts from the node's
+own incident triangle, here the one facing the foot).  Strategy (b) (start
+from the element found at the previous step) is measured beside it.
 
 Prints one JSON line: feet located+interpolated per second, the roofline
-position of the step kernel (HBM-bound; algorithmic bytes per step over the
-kernel's mean duration from HIP events on its stream), and the CPU oracle's
-throughput on this host.
+position of the step kernel (HBM-bound; algorithmic bytes per launch over the
+kernel's mean duration from HIP events around each launch of the timed
+region), and the CPU oracle's throughput on this host.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -27,15 +34,35 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "feet located+interpolated/sec; mean walk steps; learned vs plain walk"
+KERNEL_SRC = os.path.join(ROOT, "paper_2104_09189_amd", "csrc", "slw_kernels.hip")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_step_graded1415_rk2_a5_K16_hbm_counters.md")
 
 
 def algorithmic_bytes(n_feet: int, n_tris: int, c_x: int, c_v: int, k: int, order: int = 1) -> int:
     """Each array the step must touch, counted once: per foot its coordinates,
     a start id, an element id, K values in and K values out; per triangle its
-    three vertex ids (P2: 6 DOF ids, 8-byte start/elem pair per DOF)."""
+    three vertex ids (P2: six DOF ids and an 8-byte start/element pair)."""
     if order == 1:
         return n_feet * (c_x + 4 + 4 + 2 * k * c_v) + 12 * n_tris
     return n_feet * (c_x + 8 + 2 * k * c_v) + 24 * n_tris
+
+
+def kernel_source_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel source (else None)."""
+    try:
+        txt = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    h = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
+    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not h or not b or h.group(1) != kernel_source_hash():
+        return None
+    return float(b.group(1))
 
 
 def cpu_baseline(w, budget_s: float = 10.0):
@@ -59,6 +86,53 @@ def cpu_baseline(w, budget_s: float = 10.0):
             "sample": f"{steps} whole oracle steps of the same workload ({feet} feet, {el:.1f} s)"}
 
 
+def run_steps(mesh, w, v_a, v_b, step0, count, start_mode, per_launch_events=False):
+    import torch
+    evs = []
+    stream = torch.cuda.current_stream()
+    for s in range(count):
+        if per_launch_events:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+        mesh.step(w.field, (step0 + s) * w.dt, w.dt, w.scheme, v_a, v_b, start_mode=start_mode)
+        if per_launch_events:
+            e1 = torch.cuda.Event(enable_timing=True)
+            e1.record(stream)
+            evs.append((e0, e1))
+        v_a, v_b = v_b, v_a
+    return v_a, v_b, evs
+
+
+def measure(mesh, w, v0, steps, warmup, start_mode):
+    """Warm up, then time exactly `steps` steps between two synchronisations;
+    the kernel's own mean duration comes from events around each launch."""
+    import torch
+    from paper_2104_09189_amd import slwalk as S
+    v_a = v0.clone()
+    v_b = torch.empty_like(v_a)
+    # walk statistics of one step (the counting variant of the kernel)
+    t_stats = 0.0
+    if start_mode == S.START_PREV:
+        # strategy (b): the first step starts as (a); measure the one after it
+        mesh.step(w.field, 0.0, w.dt, w.scheme, v_a, v_b, start_mode=start_mode)
+        t_stats = w.dt
+    _, st = mesh.step(w.field, t_stats, w.dt, w.scheme, v_a, v_b, start_mode=start_mode, stats=True)
+    v_a, v_b, _ = run_steps(mesh, w, v_a, v_b, 0, warmup, start_mode)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    v_a, v_b, evs = run_steps(mesh, w, v_a, v_b, warmup, steps, start_mode, per_launch_events=True)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    return {"ms_per_step": gpu_ms / steps, "kernel_ms": kernel_ms, "wall_s": wall, "stats": st}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,6 +142,7 @@ def main():
     ap.add_argument("--n", type=int, default=1415)
     ap.add_argument("--k", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--only-a", action="store_true", help="measure strategy (a) only")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times (to scale HBM counters)")
@@ -83,8 +158,9 @@ def main():
         print(json.dumps({"copy_bytes_read_per_launch": 4 * n, "copy_bytes_written_per_launch": 4 * n, "launches": 5}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU sharding is a design "
-                                   "(halo exchange of V^n rows), not an implementation", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this build runs on one GPU only; how the path would shard over several GPUs "
+                                   "(replicated mesh, halo exchange of value rows) is a design, not an implementation",
+                          "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
@@ -93,53 +169,19 @@ def main():
 
     w = I.graded_swirl(alpha=args.alpha, n=args.n, k_fields=args.k)
     ctx = S.Context(0)
-    stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
     mesh = S.Mesh(ctx, w.xy, w.tri, S.INTERNAL_ORDER)
     upload_s = time.perf_counter() - t0
     perm = mesh.dof_order()
-    v_a = torch.from_numpy(np.ascontiguousarray(w.v0[perm])).to("cuda:0")
-    v_b = torch.empty_like(v_a)
+    v0 = torch.from_numpy(np.ascontiguousarray(w.v0[perm])).to("cuda:0")
     n_feet = mesh.n_nodes
 
-    # walk statistics of one step (separate call: counters are a different kernel variant)
-    _, st = mesh.step(w.field, 0.0, w.dt, w.scheme, v_a, v_b, stats=True)
-
-    def run(step0, count):
-        nonlocal v_a, v_b
-        for s in range(count):
-            mesh.step(w.field, (step0 + s) * w.dt, w.dt, w.scheme, v_a, v_b)
-            v_a, v_b = v_b, v_a
-
-    run(0, args.warmup)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    run(args.warmup, args.steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
-    ms_per_step = gpu_ms / args.steps
-    value = n_feet * args.steps / (gpu_ms * 1e-3)
-
-    # the step kernel alone, per launch (one launch per step in this mode)
-    kernel_ms = []
-    for s in range(min(args.steps, 20)):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        mesh.step(w.field, s * w.dt, w.dt, w.scheme, v_a, v_b)
-        e1.record(stream)
-        v_a, v_b = v_b, v_a
-        kernel_ms.append((e0, e1))
-    torch.cuda.synchronize()
-    kms = float(np.mean([a.elapsed_time(b) for a, b in kernel_ms]))
+    ra = measure(mesh, w, v0, args.steps, args.warmup, S.START_STEERED)
+    value = n_feet / (ra["ms_per_step"] * 1e-3)
     abytes = algorithmic_bytes(n_feet, mesh.n_tris, 16, 4, args.k)
-    achieved = abytes / (kms * 1e-3) / 1e9
-
+    achieved = abytes / (ra["kernel_ms"] * 1e-3) / 1e9
+    traffic = measured_traffic() if (args.alpha == 5.0 and args.n == 1415 and args.k == 16) else None
+    st = ra["stats"]
     out = {
         "metric": METRIC,
         "value": value,
@@ -147,7 +189,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": ra["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -155,17 +197,25 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n_nodes": int(n_feet), "n_tris": int(mesh.n_tris), "alpha": args.alpha,
                    "k_fields": args.k, "coords": "f64", "values": "f32", "order": 1, "scheme": "rk2",
-                   "start": "steered incident triangle", "parallelism": "none (1 GPU)"},
+                   "start": "strategy (a): incident triangle facing the foot", "parallelism": "none (1 GPU)"},
         "field_values_per_s": value * args.k,
         "mean_walk_steps": st["walk_steps"] / max(st["feet"], 1),
-        "walk": {k: st[k] for k in ("max_steps", "outside", "exact_tests", "fallback_walks", "edge_ties",
-                                    "vertex_ties")},
+        "walk": {k: st[k] for k in ("max_steps", "outside", "exact_tests", "fp64_tests", "fallback_walks",
+                                    "edge_ties", "vertex_ties")},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_step<false, float>",
-                     "kernel_ms": kms, "algorithmic_bytes": abytes},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_step<false, float, 3>",
+                     "kernel_ms": ra["kernel_ms"], "algorithmic_bytes_per_launch": abytes},
         "upload_s": upload_s,
-        "wall_s": wall,
+        "wall_s": ra["wall_s"],
     }
+    if not args.only_a:
+        rb = measure(mesh, w, v0, args.steps, args.warmup, S.START_PREV)
+        stb = rb["stats"]
+        out["strategy_b"] = {
+            "start": "element found at the previous step", "value": n_feet / (rb["ms_per_step"] * 1e-3),
+            "ms_per_step": rb["ms_per_step"], "kernel_ms": rb["kernel_ms"],
+            "mean_walk_steps": stb["walk_steps"] / max(stb["feet"], 1),
+            "roofline_frac": abytes / (rb["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(out), flush=True)
