@@ -214,6 +214,51 @@ slw_status slw_step(slw_mesh *mesh, const slw_field *field, double t_n, double d
  * order and the internal order (to_internal != 0: user -> internal). */
 slw_status slw_permute_rows(slw_mesh *mesh, const void *src, void *dst, int64_t row_bytes, int to_internal);
 
+/* ---------------------------------------------------------------------
+ * Batches: many meshes advanced by one P1 step each in a single launch
+ * (extension of the method to uneven workloads; each mesh is stepped exactly
+ * as slw_step with SLW_START_STEERED would).  Work items are the meshes'
+ * 256-DOF tiles (block-sized tiles), concatenated; schedule 0 gives each
+ * workgroup one tile in an XCD-contiguous order, schedule 1 runs persistent
+ * workgroups that pull tiles from per-XCD queues.  The step index lives on
+ * the device: step n of mesh i advances its values from t0_i + n dt_i to
+ * t0_i + (n + 1) dt_i, reading va_i and writing vb_i when n is even and the
+ * reverse when n is odd, then the index is incremented -- so a captured
+ * graph of steps can be replayed and keeps advancing in time.
+ * All meshes must share the coordinate type and use SLW_INTERNAL_ORDER.  The
+ * batch references the meshes (they must outlive it).
+ * ------------------------------------------------------------------- */
+typedef struct slw_batch slw_batch;
+typedef struct slw_graph slw_graph;
+
+slw_status slw_batch_create(slw_ctx *ctx, slw_mesh *const *meshes_h, int n, slw_batch **out);
+slw_status slw_batch_free(slw_batch *b);
+/* fields_h[i], dt_h[i] and (nullable, default 0) t0_h[i] for each mesh */
+slw_status slw_batch_set_fields(slw_batch *b, const slw_field *fields_h, const double *dt_h, const double *t0_h);
+/* device value buffers va_h[i], vb_h[i] (n_nodes x k of vdtype, internal order) */
+slw_status slw_batch_set_values(slw_batch *b, void *const *va_h, void *const *vb_h, int vdtype, int k);
+/* set / read the device step index (both synchronise the context's stream) */
+slw_status slw_batch_set_step(slw_batch *b, int64_t n);
+slw_status slw_batch_get_step(slw_batch *b, int64_t *n_h);
+/* schedule 0 (static, XCD-contiguous) or 1 (persistent queues); workgroup size 64, 128, 256 or 512 */
+slw_status slw_batch_set_schedule(slw_batch *b, int schedule, int block);
+/* one step of every mesh (asynchronous unless stats_h is given) */
+slw_status slw_batch_step(slw_batch *b, int scheme, double outside_value, slw_stats *stats_h);
+/* Capture n_steps batch steps into a HIP graph (on a private stream; no
+ * memset nodes: counters are cleared by kernels).  Replays run on the
+ * context's stream and advance the device step index by n_steps. */
+slw_status slw_batch_graph_capture(slw_batch *b, int n_steps, int scheme, double outside_value, slw_graph **out);
+slw_status slw_graph_launch(slw_graph *g);
+slw_status slw_graph_free(slw_graph *g);
+/* Autotuner: times every (schedule, workgroup size) on private copies of the
+ * batch's current values, keeps only candidates whose first step is bit-
+ * identical to the reference candidate's, selects the fastest and records it
+ * in the JSON file cache_path (nullable) under a signature of the batch
+ * (mesh count, DOF count bucket, types, k); a later call with a cached
+ * signature applies the cached choice without timing.  Synchronous; the
+ * caller's values and step index are left as they were. */
+slw_status slw_batch_autotune(slw_batch *b, int scheme, const char *cache_path, int *schedule_out, int *block_out);
+
 /* The library's orientation predicate evaluated on the host, for testing:
  * out_h[i] = sign of orient(a, b, c) for the triple pts_h[6i .. 6i+5] =
  * (ax, ay, bx, by, cx, cy).  mode 0: FP64 filter then exact stage (what a

@@ -463,3 +463,492 @@ slw_status slw_permute_rows(slw_mesh *mesh, const void *src, void *dst, int64_t 
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// batches of meshes, graphs, autotuning
+
+#include <chrono>
+#include <cstdio>
+#include <fstream>
+#include <sstream>
+
+struct slw_batch {
+    slw_ctx *ctx = nullptr;
+    std::vector<slw_mesh *> meshes;
+    std::vector<slw::BatchItem> items_h;  // tile0 filled for `block`
+    slw::BatchItem *items = nullptr;      // device copy
+    int64_t *counter = nullptr;           // device step counter
+    unsigned *queues = nullptr;           // 8 per-XCD queues
+    int coords_f32 = 0;
+    int vdtype = SLW_F32;
+    int k = 0;
+    int block = 256;
+    int schedule = 0;
+    int have_fields = 0, have_values = 0;
+    int64_t total_tiles = 0;
+    int persistent_blocks = 0;
+};
+
+struct slw_graph {
+    slw_ctx *ctx = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+slw_status batch_upload_items(slw_batch *b)
+{
+    int64_t tile = 0;
+    for (auto &it : b->items_h) {
+        it.tile0 = tile;
+        tile += (it.n_iter + b->block - 1) / b->block;
+    }
+    b->total_tiles = tile;
+    return hip_check(hipMemcpy(b->items, b->items_h.data(), b->items_h.size() * sizeof(slw::BatchItem),
+                               hipMemcpyHostToDevice),
+                     "hipMemcpy(batch items)");
+}
+
+int device_cu_count(int dev)
+{
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0)
+        cu = 256;
+    return cu;
+}
+
+slw_status batch_launch(slw_batch *b, int scheme, double outside, slw::DevStats *st, hipStream_t stream)
+{
+    return hip_check(launch_batch_step(stream, b->coords_f32, b->vdtype, b->block, b->schedule, b->items,
+                                       (int)b->items_h.size(), b->total_tiles, b->counter, scheme, b->k, outside,
+                                       b->queues, b->persistent_blocks, st),
+                     "batch step");
+}
+
+}  // namespace
+
+extern "C" {
+
+slw_status slw_batch_create(slw_ctx *ctx, slw_mesh *const *meshes_h, int n, slw_batch **out)
+{
+    if (!ctx || !meshes_h || n < 1 || !out)
+        return set_error(SLW_E_ARG, "slw_batch_create: null pointer or n < 1");
+    *out = nullptr;
+    int f32 = -1;
+    for (int i = 0; i < n; ++i) {
+        if (!meshes_h[i] || meshes_h[i]->ctx != ctx)
+            return set_error(SLW_E_ARG, "slw_batch_create: mesh missing or from another context");
+        if (!meshes_h[i]->m.internal_order)
+            return set_error(SLW_E_UNSUPPORTED, "slw_batch_create: meshes must use SLW_INTERNAL_ORDER");
+        if (f32 >= 0 && f32 != meshes_h[i]->m.coords_f32)
+            return set_error(SLW_E_UNSUPPORTED, "slw_batch_create: all meshes need the same coordinate type");
+        f32 = meshes_h[i]->m.coords_f32;
+    }
+    DeviceGuard g(ctx->device);
+    slw_batch *b = new (std::nothrow) slw_batch();
+    if (!b)
+        return set_error(SLW_E_NOMEM, "batch");
+    b->ctx = ctx;
+    b->coords_f32 = f32;
+    b->meshes.assign(meshes_h, meshes_h + n);
+    b->items_h.resize(n);
+    for (int i = 0; i < n; ++i) {
+        slw::BatchItem &it = b->items_h[i];
+        std::memset(&it, 0, sizeof it);
+        it.mv = view_of(meshes_h[i]->m);
+        it.n_iter = meshes_h[i]->m.n_nodes;
+    }
+    b->persistent_blocks = device_cu_count(ctx->device) * 8;
+    if (hipMalloc((void **)&b->items, n * sizeof(slw::BatchItem)) != hipSuccess ||
+        hipMalloc((void **)&b->counter, sizeof(int64_t)) != hipSuccess ||
+        hipMalloc((void **)&b->queues, 8 * sizeof(unsigned)) != hipSuccess) {
+        slw_batch_free(b);
+        return set_error(SLW_E_NOMEM, "batch device tables");
+    }
+    int64_t zero = 0;
+    slw_status st = hip_check(hipMemcpy(b->counter, &zero, sizeof zero, hipMemcpyHostToDevice), "hipMemcpy(counter)");
+    if (st == SLW_OK)
+        st = batch_upload_items(b);
+    if (st != SLW_OK) {
+        slw_batch_free(b);
+        return st;
+    }
+    *out = b;
+    return SLW_OK;
+}
+
+slw_status slw_batch_free(slw_batch *b)
+{
+    if (!b)
+        return SLW_OK;
+    DeviceGuard g(b->ctx->device);
+    (void)hipStreamSynchronize(b->ctx->stream);
+    if (b->items)
+        (void)hipFree(b->items);
+    if (b->counter)
+        (void)hipFree(b->counter);
+    if (b->queues)
+        (void)hipFree(b->queues);
+    delete b;
+    return SLW_OK;
+}
+
+slw_status slw_batch_set_fields(slw_batch *b, const slw_field *fields_h, const double *dt_h, const double *t0_h)
+{
+    if (!b || !fields_h || !dt_h)
+        return set_error(SLW_E_ARG, "slw_batch_set_fields: null pointer");
+    for (size_t i = 0; i < b->items_h.size(); ++i) {
+        if (!field_ok(&fields_h[i]) || !(dt_h[i] == dt_h[i]))
+            return set_error(SLW_E_ARG, "slw_batch_set_fields: bad field or dt at mesh " + std::to_string(i));
+        b->items_h[i].f = to_dev(&fields_h[i]);
+        b->items_h[i].dt = dt_h[i];
+        b->items_h[i].t0 = t0_h ? t0_h[i] : 0.0;
+    }
+    b->have_fields = 1;
+    DeviceGuard g(b->ctx->device);
+    return batch_upload_items(b);
+}
+
+slw_status slw_batch_set_values(slw_batch *b, void *const *va_h, void *const *vb_h, int vdtype, int k)
+{
+    if (!b || !va_h || !vb_h || k < 1 || (vdtype != SLW_F32 && vdtype != SLW_F64))
+        return set_error(SLW_E_ARG, "slw_batch_set_values: bad arguments");
+    for (size_t i = 0; i < b->items_h.size(); ++i) {
+        if (!va_h[i] || !vb_h[i] || va_h[i] == vb_h[i])
+            return set_error(SLW_E_ARG, "slw_batch_set_values: value buffers missing or equal at mesh " +
+                                            std::to_string(i));
+        b->items_h[i].va = va_h[i];
+        b->items_h[i].vb = vb_h[i];
+    }
+    b->vdtype = vdtype;
+    b->k = k;
+    b->have_values = 1;
+    DeviceGuard g(b->ctx->device);
+    return batch_upload_items(b);
+}
+
+slw_status slw_batch_set_step(slw_batch *b, int64_t n)
+{
+    if (!b || n < 0)
+        return set_error(SLW_E_ARG, "slw_batch_set_step: bad arguments");
+    DeviceGuard g(b->ctx->device);
+    slw_status st = hip_check(hipStreamSynchronize(b->ctx->stream), "hipStreamSynchronize");
+    if (st != SLW_OK)
+        return st;
+    return hip_check(hipMemcpy(b->counter, &n, sizeof n, hipMemcpyHostToDevice), "hipMemcpy(counter)");
+}
+
+slw_status slw_batch_get_step(slw_batch *b, int64_t *n_h)
+{
+    if (!b || !n_h)
+        return set_error(SLW_E_ARG, "slw_batch_get_step: bad arguments");
+    DeviceGuard g(b->ctx->device);
+    slw_status st = hip_check(hipStreamSynchronize(b->ctx->stream), "hipStreamSynchronize");
+    if (st != SLW_OK)
+        return st;
+    return hip_check(hipMemcpy(n_h, b->counter, sizeof *n_h, hipMemcpyDeviceToHost), "hipMemcpy(counter)");
+}
+
+slw_status slw_batch_set_schedule(slw_batch *b, int schedule, int block)
+{
+    if (!b || (schedule != 0 && schedule != 1) || (block != 64 && block != 128 && block != 256 && block != 512))
+        return set_error(SLW_E_ARG, "slw_batch_set_schedule: schedule 0/1, block 64/128/256/512");
+    b->schedule = schedule;
+    b->block = block;
+    DeviceGuard g(b->ctx->device);
+    return batch_upload_items(b);
+}
+
+slw_status slw_batch_step(slw_batch *b, int scheme, double outside_value, slw_stats *stats_h)
+{
+    if (!b || (scheme != SLW_EULER && scheme != SLW_RK2))
+        return set_error(SLW_E_ARG, "slw_batch_step: bad arguments");
+    if (!b->have_fields || !b->have_values)
+        return set_error(SLW_E_ARG, "slw_batch_step: set fields and values first");
+    DeviceGuard g(b->ctx->device);
+    slw_status st = begin_stats(b->ctx, stats_h);
+    if (st != SLW_OK)
+        return st;
+    st = batch_launch(b, scheme, outside_value, stats_h ? b->ctx->stats : nullptr, b->ctx->stream);
+    if (st != SLW_OK)
+        return st;
+    return end_stats(b->ctx, stats_h);
+}
+
+slw_status slw_batch_graph_capture(slw_batch *b, int n_steps, int scheme, double outside_value, slw_graph **out)
+{
+    if (!b || n_steps < 1 || !out || (scheme != SLW_EULER && scheme != SLW_RK2))
+        return set_error(SLW_E_ARG, "slw_batch_graph_capture: bad arguments");
+    if (!b->have_fields || !b->have_values)
+        return set_error(SLW_E_ARG, "slw_batch_graph_capture: set fields and values first");
+    *out = nullptr;
+    DeviceGuard g(b->ctx->device);
+    slw_status st = hip_check(hipStreamSynchronize(b->ctx->stream), "hipStreamSynchronize");
+    if (st != SLW_OK)
+        return st;
+    // capture on a private stream (the caller's may be the null stream); default priority
+    hipStream_t cs = nullptr;
+    st = hip_check(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate");
+    if (st != SLW_OK)
+        return st;
+    hipGraph_t graph = nullptr;
+    st = hip_check(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    if (st == SLW_OK) {
+        for (int i = 0; i < n_steps && st == SLW_OK; ++i)
+            st = batch_launch(b, scheme, outside_value, nullptr, cs);
+        hipError_t e = hipStreamEndCapture(cs, &graph);
+        if (st == SLW_OK)
+            st = hip_check(e, "hipStreamEndCapture");
+    }
+    (void)hipStreamDestroy(cs);
+    if (st != SLW_OK) {
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        return st;
+    }
+    slw_graph *gr = new (std::nothrow) slw_graph();
+    if (!gr) {
+        (void)hipGraphDestroy(graph);
+        return set_error(SLW_E_NOMEM, "graph");
+    }
+    gr->ctx = b->ctx;
+    gr->graph = graph;
+    st = hip_check(hipGraphInstantiate(&gr->exec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+    if (st != SLW_OK) {
+        slw_graph_free(gr);
+        return st;
+    }
+    *out = gr;
+    return SLW_OK;
+}
+
+slw_status slw_graph_launch(slw_graph *gr)
+{
+    if (!gr || !gr->exec)
+        return set_error(SLW_E_ARG, "slw_graph_launch: null graph");
+    DeviceGuard g(gr->ctx->device);
+    return hip_check(hipGraphLaunch(gr->exec, gr->ctx->stream), "hipGraphLaunch");
+}
+
+slw_status slw_graph_free(slw_graph *gr)
+{
+    if (!gr)
+        return SLW_OK;
+    DeviceGuard g(gr->ctx->device);
+    (void)hipStreamSynchronize(gr->ctx->stream);
+    if (gr->exec)
+        (void)hipGraphExecDestroy(gr->exec);
+    if (gr->graph)
+        (void)hipGraphDestroy(gr->graph);
+    delete gr;
+    return SLW_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+std::string batch_signature(const slw_batch *b)
+{
+    int64_t dofs = 0;
+    for (const auto &it : b->items_h)
+        dofs += it.n_iter;
+    int bucket = 0;
+    while ((int64_t)1 << (bucket + 1) <= dofs)
+        ++bucket;
+    std::ostringstream os;
+    os << "meshes" << b->items_h.size() << "_dofs2^" << bucket << "_c" << (b->coords_f32 ? "f32" : "f64") << "_v"
+       << (b->vdtype == SLW_F32 ? "f32" : "f64") << "_k" << b->k;
+    return os.str();
+}
+
+// tiny JSON cache: {"signature": {"schedule": s, "block": b, "ms": t}, ...}
+bool cache_lookup(const char *path, const std::string &sig, int &schedule, int &block)
+{
+    std::ifstream f(path);
+    if (!f)
+        return false;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string txt = ss.str();
+    const size_t at = txt.find("\"" + sig + "\"");
+    if (at == std::string::npos)
+        return false;
+    const size_t s1 = txt.find("\"schedule\":", at), b1 = txt.find("\"block\":", at);
+    if (s1 == std::string::npos || b1 == std::string::npos)
+        return false;
+    schedule = std::atoi(txt.c_str() + s1 + 11);
+    block = std::atoi(txt.c_str() + b1 + 8);
+    return (schedule == 0 || schedule == 1) && (block == 64 || block == 128 || block == 256 || block == 512);
+}
+
+void cache_store(const char *path, const std::string &sig, int schedule, int block, double ms)
+{
+    std::string txt;
+    {
+        std::ifstream f(path);
+        if (f) {
+            std::stringstream ss;
+            ss << f.rdbuf();
+            txt = ss.str();
+        }
+    }
+    std::ostringstream entry;
+    entry << "\"" << sig << "\": {\"schedule\": " << schedule << ", \"block\": " << block << ", \"ms\": " << ms << "}";
+    const size_t at = txt.find("\"" + sig + "\"");
+    if (at != std::string::npos) {
+        const size_t end = txt.find('}', at);
+        txt.replace(at, end + 1 - at, entry.str());
+    } else {
+        const size_t close = txt.rfind('}');
+        if (txt.empty() || close == std::string::npos)
+            txt = "{\n  " + entry.str() + "\n}\n";
+        else {
+            const bool empty = txt.find('"') == std::string::npos;
+            txt.insert(close, (empty ? "  " : ",\n  ") + entry.str() + "\n");
+        }
+    }
+    std::ofstream f(path);
+    f << txt;
+}
+
+}  // namespace
+
+extern "C" slw_status slw_batch_autotune(slw_batch *b, int scheme, const char *cache_path, int *schedule_out,
+                                         int *block_out)
+{
+    if (!b || (scheme != SLW_EULER && scheme != SLW_RK2))
+        return set_error(SLW_E_ARG, "slw_batch_autotune: bad arguments");
+    if (!b->have_fields || !b->have_values)
+        return set_error(SLW_E_ARG, "slw_batch_autotune: set fields and values first");
+    DeviceGuard g(b->ctx->device);
+    const std::string sig = batch_signature(b);
+    int schedule = 0, block = 256;
+    if (cache_path && cache_lookup(cache_path, sig, schedule, block)) {
+        slw_status st = slw_batch_set_schedule(b, schedule, block);
+        if (st == SLW_OK) {
+            if (schedule_out)
+                *schedule_out = schedule;
+            if (block_out)
+                *block_out = block;
+        }
+        return st;
+    }
+    // Tune on private copies of the value buffers (the caller's stay untouched):
+    // every candidate runs the same first step from the same input and must
+    // reproduce the reference candidate's output bit for bit (parity guard),
+    // then is timed over a few steps.
+    const size_t vsz = b->vdtype == SLW_F64 ? 8 : 4;
+    std::vector<size_t> bytes(b->items_h.size());
+    size_t total = 0;
+    for (size_t i = 0; i < b->items_h.size(); ++i) {
+        bytes[i] = (size_t)b->items_h[i].n_iter * b->k * vsz;
+        total += bytes[i];
+    }
+    char *work = nullptr;
+    if (hipMalloc((void **)&work, 3 * total) != hipSuccess)
+        return set_error(SLW_E_NOMEM, "autotune workspace");
+    std::vector<slw::BatchItem> saved = b->items_h;
+    int64_t saved_step = 0;
+    slw_status st = hip_check(hipStreamSynchronize(b->ctx->stream), "hipStreamSynchronize");
+    if (st == SLW_OK)
+        st = hip_check(hipMemcpy(&saved_step, b->counter, sizeof saved_step, hipMemcpyDeviceToHost), "counter");
+    const int saved_schedule = b->schedule, saved_block = b->block;
+    // layout of work: [A copies | B copies | reference output]
+    size_t off = 0;
+    for (size_t i = 0; i < b->items_h.size() && st == SLW_OK; ++i) {
+        st = hip_check(hipMemcpy(work + off, saved[i].va, bytes[i], hipMemcpyDeviceToDevice), "copy values");
+        b->items_h[i].va = work + off;
+        b->items_h[i].vb = work + total + off;
+        off += bytes[i];
+    }
+    const int64_t even_step = saved_step & ~(int64_t)1;
+    double best_ms = 1e300;
+    int best_s = saved_schedule, best_b = saved_block;
+    bool have_ref = false;
+    std::vector<char> ref_h, out_h;
+    const int schedules[2] = {0, 1};
+    const int blocks[4] = {64, 128, 256, 512};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (st == SLW_OK)
+        st = hip_check(hipEventCreate(&e0), "hipEventCreate");
+    if (st == SLW_OK)
+        st = hip_check(hipEventCreate(&e1), "hipEventCreate");
+    for (int si = 0; si < 2 && st == SLW_OK; ++si)
+        for (int bi = 0; bi < 4 && st == SLW_OK; ++bi) {
+            b->schedule = schedules[si];
+            b->block = blocks[bi];
+            st = batch_upload_items(b);
+            if (st != SLW_OK)
+                break;
+            // parity guard: one step from the copy of the input (even step: A -> B)
+            st = slw_batch_set_step(b, even_step);
+            if (st == SLW_OK)
+                st = batch_launch(b, scheme, 0.0, nullptr, b->ctx->stream);
+            if (st == SLW_OK)
+                st = hip_check(hipStreamSynchronize(b->ctx->stream), "sync");
+            if (st != SLW_OK)
+                break;
+            out_h.resize(total);
+            st = hip_check(hipMemcpy(out_h.data(), work + total, total, hipMemcpyDeviceToHost), "copy output");
+            if (st != SLW_OK)
+                break;
+            if (!have_ref) {
+                ref_h = out_h;
+                have_ref = true;
+            } else if (std::memcmp(ref_h.data(), out_h.data(), total) != 0) {
+                continue;  // not bit-identical: never chosen
+            }
+            // timing: 5 steps (values evolve in the private buffers)
+            const int reps = 5;
+            st = hip_check(hipEventRecord(e0, b->ctx->stream), "event");
+            for (int r = 0; r < reps && st == SLW_OK; ++r)
+                st = batch_launch(b, scheme, 0.0, nullptr, b->ctx->stream);
+            if (st == SLW_OK)
+                st = hip_check(hipEventRecord(e1, b->ctx->stream), "event");
+            if (st == SLW_OK)
+                st = hip_check(hipEventSynchronize(e1), "event sync");
+            float ms = 0.f;
+            if (st == SLW_OK)
+                st = hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+            if (st == SLW_OK && ms / reps < best_ms) {
+                best_ms = ms / reps;
+                best_s = b->schedule;
+                best_b = b->block;
+            }
+            // restore the private input for the next candidate
+            off = 0;
+            for (size_t i = 0; i < b->items_h.size() && st == SLW_OK; ++i) {
+                st = hip_check(hipMemcpy(work + off, saved[i].va, bytes[i], hipMemcpyDeviceToDevice), "copy values");
+                off += bytes[i];
+            }
+        }
+    if (e0)
+        (void)hipEventDestroy(e0);
+    if (e1)
+        (void)hipEventDestroy(e1);
+    // restore the caller's buffers and step; keep the winner
+    for (size_t i = 0; i < b->items_h.size(); ++i) {
+        b->items_h[i].va = saved[i].va;
+        b->items_h[i].vb = saved[i].vb;
+    }
+    b->schedule = st == SLW_OK ? best_s : saved_schedule;
+    b->block = st == SLW_OK ? best_b : saved_block;
+    slw_status st2 = batch_upload_items(b);
+    slw_status st3 = slw_batch_set_step(b, saved_step);
+    (void)hipFree(work);
+    if (st != SLW_OK)
+        return st;
+    if (st2 != SLW_OK)
+        return st2;
+    if (st3 != SLW_OK)
+        return st3;
+    if (cache_path)
+        cache_store(cache_path, sig, b->schedule, b->block, best_ms);
+    if (schedule_out)
+        *schedule_out = b->schedule;
+    if (block_out)
+        *block_out = b->block;
+    return SLW_OK;
+}

@@ -93,6 +93,30 @@ void free_mesh(DevMesh &m);
 FilterConst filter_constants(bool f32, double cx, double cy, double cmax);
 
 // launchers (slw_kernels.hip)
+
+// Everything a kernel needs to know about a mesh (device pointers, sizes,
+// filter constants), passed by value.
+struct MeshView {
+    const GeoRec *geo;
+    const int32_t *tri_uf;
+    const int4 *tedge;
+    const void *dof_xy;
+    const int4 *qstart;
+    const int32_t *vmin;
+    const int32_t *dof_user;
+    const int32_t *tri_int;
+    int32_t *prev;
+    const int32_t *jump;
+    int jump_g;
+    int internal_order;
+    int64_t n_dofs;
+    int64_t n_tris;
+    double bb[4];
+    FilterConst fc;
+    int32_t step_cap, hard_limit;
+};
+MeshView view_of(const DevMesh &m);
+
 struct FieldDev {
     int kind;
     double p[8];
@@ -116,6 +140,20 @@ hipError_t launch_step(const DevMesh &m, hipStream_t st, const FieldDev &f, doub
                        int order, int start_mode, const int32_t *start, const void *v_in, int vdtype, int k,
                        void *v_out, double outside, bool write_prev, const int32_t *out_map, DevStats *stats);
 hipError_t launch_zero_stats(hipStream_t st, DevStats *p);
+
+// one mesh of a batch (device table; see slw_batch_* in slwalk.h)
+struct BatchItem {
+    MeshView mv;
+    FieldDev f;      // g is filled on the device for each step
+    double dt, t0;   // step n advances from t0 + n dt to t0 + (n + 1) dt
+    const void *va;  // even steps read va and write vb, odd steps the reverse
+    void *vb;
+    int64_t n_iter;  // DOFs stepped (the nodes: P1)
+    int64_t tile0;   // first tile of this mesh in the concatenated tile space
+};
+hipError_t launch_batch_step(hipStream_t st, int coords_f32, int vdtype, int block, int schedule,
+                             const BatchItem *items, int n_items, int64_t total_tiles, int64_t *counter, int scheme,
+                             int k, double outside, unsigned *queues, int persistent_blocks, DevStats *stats);
 hipError_t launch_permute_rows(hipStream_t st, const void *src, void *dst, int64_t rows, int64_t row_bytes,
                                const int32_t *map, int scatter);
 }  // namespace slw

@@ -101,28 +101,7 @@ __device__ inline void foot_of(const FieldDev &f, int scheme, R x, R y, R dt, R 
     qy = y - dt * fy;
 }
 
-// ---------------------------------------------------------------------------
-// mesh view passed to every kernel
-
-struct MeshView {
-    const GeoRec *geo;
-    const int32_t *tri_uf;
-    const int4 *tedge;
-    const void *dof_xy;
-    const int4 *qstart;
-    const int32_t *vmin;
-    const int32_t *dof_user;
-    const int32_t *tri_int;
-    int32_t *prev;
-    const int32_t *jump;
-    int jump_g;
-    int internal_order;
-    int64_t n_dofs;
-    int64_t n_tris;
-    double bb[4];
-    FilterConst fc;
-    int32_t step_cap, hard_limit;
-};
+}  // namespace
 
 MeshView view_of(const DevMesh &m)
 {
@@ -148,6 +127,8 @@ MeshView view_of(const DevMesh &m)
     v.hard_limit = m.hard_limit;
     return v;
 }
+
+namespace {
 
 // ---------------------------------------------------------------------------
 // start selection: strategy (a) of Section 3 (the walk starts at the DOF),
@@ -729,18 +710,18 @@ __global__ void __launch_bounds__(kBlock)
     wave_interp<V, NA>(row, wgt, nf, vin, k, vout, nullptr, base, (V)outside);
 }
 
-// The fused step (Algorithm 2, one pass of its loop): one lane per foot for
-// foot -> start -> walk -> tie rule -> weights; then the wavefront computes
-// its 64 feet's values cooperatively.
+// The fused step (Algorithm 2, one pass of its loop) for the 64 DOFs
+// [base, base + 64) of one wavefront: one lane per foot for foot -> start ->
+// walk -> tie rule -> weights; then the wavefront computes its feet's values
+// cooperatively.  Every lane of the wavefront calls it.
 template <bool F32, typename V, int NA>
-__global__ void __launch_bounds__(kBlock)
-    k_step(MeshView mv, FieldDev f, double dt, int scheme, int mode, const int32_t *__restrict__ start,
-           const V *__restrict__ vin, int k, V *__restrict__ vout, double outside, int write_prev,
-           const int32_t *__restrict__ out_map, int64_t n_iter, DevStats *st)
+__device__ inline void step_wave(const MeshView &mv, const FieldDev &f, double dt, int scheme, int mode,
+                                 const int32_t *__restrict__ start, const V *__restrict__ vin, int k,
+                                 V *__restrict__ vout, double outside, int write_prev,
+                                 const int32_t *__restrict__ out_map, int64_t n_iter, int64_t base, DevStats *st)
 {
     using R = typename CT<F32>::R;
     using R2 = typename CT<F32>::R2;
-    const int64_t base = xcd_tile(blockIdx.x, gridDim.x) * kBlock + (threadIdx.x & ~(kWave - 1));
     const int64_t d = base + (threadIdx.x & (kWave - 1));
     LaneStats ls;
     int32_t row[NA];
@@ -775,6 +756,112 @@ __global__ void __launch_bounds__(kBlock)
         return;
     const int nf = (int)min<int64_t>(kWave, n_iter - base);
     wave_interp<V, NA>(row, wgt, nf, vin, k, vout, out_map, base, (V)outside);
+}
+
+template <bool F32, typename V, int NA>
+__global__ void __launch_bounds__(kBlock)
+    k_step(MeshView mv, FieldDev f, double dt, int scheme, int mode, const int32_t *__restrict__ start,
+           const V *__restrict__ vin, int k, V *__restrict__ vout, double outside, int write_prev,
+           const int32_t *__restrict__ out_map, int64_t n_iter, DevStats *st)
+{
+    const int64_t base = xcd_tile(blockIdx.x, gridDim.x) * kBlock + (threadIdx.x & ~(kWave - 1));
+    step_wave<F32, V, NA>(mv, f, dt, scheme, mode, start, vin, k, vout, outside, write_prev, out_map, n_iter, base,
+                          st);
+}
+
+// ---------------------------------------------------------------------------
+// batches: every mesh of a batch advanced by one step in one launch
+
+// time factors of a field on the device (per workgroup; uniform values)
+__device__ inline void field_time_factors_dev(FieldDev &f, double t_np1, double dt)
+{
+    const double pi = 3.14159265358979323846;
+    const double t[2] = {t_np1, t_np1 - 0.5 * dt};
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+        f.g[i] = f.kind == 2 ? cos(pi * t[i] / f.p[0]) : (f.kind == 3 ? f.p[1] * t[i] : 0.0);
+}
+
+// Items of the concatenated tile space [0, total) of a batch: mesh m owns
+// tiles [items[m].tile0, items[m + 1].tile0).
+template <bool F32, typename V, int BS>
+__device__ inline void batch_tile(const BatchItem *__restrict__ items, int n_items, int64_t tile, int64_t step,
+                                  int scheme, int k, double outside, DevStats *st)
+{
+    int lo = 0, hi = n_items - 1;  // last item with tile0 <= tile (uniform binary search)
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].tile0 <= tile)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const BatchItem &it = items[lo];
+    FieldDev f = it.f;
+    field_time_factors_dev(f, it.t0 + (double)(step + 1) * it.dt, it.dt);
+    const bool even = (step & 1) == 0;
+    const V *vin = (const V *)(even ? it.va : it.vb);
+    V *vout = (V *)(even ? it.vb : it.va);
+    const int64_t base = (tile - it.tile0) * BS + (threadIdx.x & ~(kWave - 1));
+    step_wave<F32, V, 3>(it.mv, f, it.dt, scheme, SLW_START_STEERED, nullptr, vin, k, vout, outside, 0, nullptr,
+                         it.n_iter, base, st);
+}
+
+// schedule 0: one workgroup per tile, XCD-contiguous ranges of the
+// concatenated tile space; schedule 1: persistent workgroups pulling tiles
+// from 8 per-XCD queues (each queue covers one XCD's contiguous range) and
+// stealing from the other queues when their own is empty.
+template <bool F32, typename V, int BS>
+__global__ void __launch_bounds__(BS)
+    k_batch_step(const BatchItem *__restrict__ items, int n_items, int64_t total, const int64_t *__restrict__ counter,
+                 int scheme, int k, double outside, int schedule, unsigned *queues, DevStats *st)
+{
+    const int64_t step = *counter;
+    if (schedule == 0) {
+        batch_tile<F32, V, BS>(items, n_items, xcd_tile(blockIdx.x, gridDim.x), step, scheme, k, outside, st);
+        return;
+    }
+    __shared__ int64_t s_tile;
+    constexpr int64_t kXcd = 8;
+    const int64_t q = total / kXcd, r = total % kXcd;
+    int x = (int)(blockIdx.x % kXcd);
+    int tried = 0;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int64_t got = -1;
+            while (tried < kXcd) {
+                const int64_t size = q + (x < r ? 1 : 0);
+                const int64_t first = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
+                const unsigned i = atomicAdd(&queues[x], 1u);
+                if ((int64_t)i < size) {
+                    got = first + i;
+                    break;
+                }
+                x = (x + 1) % (int)kXcd;
+                ++tried;
+            }
+            s_tile = got;
+        }
+        __syncthreads();
+        const int64_t tile = s_tile;
+        if (tile < 0)
+            return;  // every queue is empty: all waves of the workgroup exit together
+        batch_tile<F32, V, BS>(items, n_items, tile, step, scheme, k, outside, st);
+    }
+}
+
+__global__ void k_zero_u32(unsigned *p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        p[i] = 0u;
+}
+
+__global__ void k_advance(int64_t *counter, int64_t by)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        *counter += by;
 }
 
 __global__ void k_permute_rows(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst, int64_t rows,
@@ -919,6 +1006,45 @@ hipError_t launch_step(const DevMesh &m, hipStream_t st, const FieldDev &f0, dou
         }
     }
 #undef SLW_STEP
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_step(hipStream_t st, int coords_f32, int vdtype, int block, int schedule,
+                             const BatchItem *items, int n_items, int64_t total_tiles, int64_t *counter, int scheme,
+                             int k, double outside, unsigned *queues, int persistent_blocks, DevStats *stats)
+{
+    if (total_tiles <= 0)
+        return hipSuccess;
+    if (total_tiles > (int64_t)INT32_MAX)
+        return hipErrorInvalidValue;
+    if (schedule == 1) {
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, queues, 8);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    const unsigned g = schedule == 1 ? (unsigned)persistent_blocks : (unsigned)total_tiles;
+#define SLW_BSTEP(F32, V, BS)                                                                                      \
+    hipLaunchKernelGGL((k_batch_step<F32, V, BS>), dim3(g), dim3(BS), 0, st, items, n_items, total_tiles, counter, \
+                       scheme, k, outside, schedule, queues, stats)
+#define SLW_BSTEP_BS(F32, V)            \
+    switch (block) {                    \
+    case 64: SLW_BSTEP(F32, V, 64); break;   \
+    case 128: SLW_BSTEP(F32, V, 128); break; \
+    case 512: SLW_BSTEP(F32, V, 512); break; \
+    default: SLW_BSTEP(F32, V, 256); break;  \
+    }
+    if (coords_f32) {
+        if (vdtype == SLW_F32) { SLW_BSTEP_BS(true, float); } else { SLW_BSTEP_BS(true, double); }
+    } else {
+        if (vdtype == SLW_F32) { SLW_BSTEP_BS(false, float); } else { SLW_BSTEP_BS(false, double); }
+    }
+#undef SLW_BSTEP_BS
+#undef SLW_BSTEP
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, counter, (int64_t)1);
     return hipGetLastError();
 }
 

@@ -106,12 +106,27 @@ _sig("slw_step", ctypes.c_int, [_vp, ctypes.POINTER(slw_field), _dbl, _dbl, ctyp
 _sig("slw_permute_rows", ctypes.c_int, [_vp, _vp, _vp, _i64, ctypes.c_int])
 _sig("slw_orient_sign_host", ctypes.c_int, [_vp, _i64, _vp, ctypes.c_int])
 _sig("slw_float_filter_host", ctypes.c_int, [_vp, _i64, _dbl, _dbl, _dbl, ctypes.c_int, _vp])
+_sig("slw_batch_create", ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.POINTER(_vp)])
+_sig("slw_batch_free", ctypes.c_int, [_vp])
+_sig("slw_batch_set_fields", ctypes.c_int, [_vp, ctypes.POINTER(slw_field), _vp, _vp])
+_sig("slw_batch_set_values", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int])
+_sig("slw_batch_set_step", ctypes.c_int, [_vp, _i64])
+_sig("slw_batch_get_step", ctypes.c_int, [_vp, ctypes.POINTER(_i64)])
+_sig("slw_batch_set_schedule", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int])
+_sig("slw_batch_step", ctypes.c_int, [_vp, ctypes.c_int, _dbl, ctypes.POINTER(slw_stats)])
+_sig("slw_batch_graph_capture", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _dbl, ctypes.POINTER(_vp)])
+_sig("slw_graph_launch", ctypes.c_int, [_vp])
+_sig("slw_graph_free", ctypes.c_int, [_vp])
+_sig("slw_batch_autotune", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int),
+                                          ctypes.POINTER(ctypes.c_int)])
 
 EXPORTED = ["slw_status_string", "slw_last_error", "slw_ctx_create", "slw_ctx_set_stream", "slw_ctx_destroy",
             "slw_mesh_upload", "slw_mesh_check", "slw_mesh_free", "slw_mesh_get_info", "slw_mesh_dof_coords", "slw_mesh_dof_order",
             "slw_mesh_set_walk_limits", "slw_locate", "slw_locate_feet", "slw_interpolate", "slw_step",
             "slw_permute_rows", "slw_orient_sign_host",
-            "slw_float_filter_host"]
+            "slw_float_filter_host", "slw_batch_create", "slw_batch_free", "slw_batch_set_fields",
+            "slw_batch_set_values", "slw_batch_set_step", "slw_batch_get_step", "slw_batch_set_schedule",
+            "slw_batch_step", "slw_batch_graph_capture", "slw_graph_launch", "slw_graph_free", "slw_batch_autotune"]
 
 
 def _check(rc: int, where: str):
@@ -163,11 +178,17 @@ import weakref  # noqa: E402
 
 _live_meshes = weakref.WeakSet()
 _live_ctxs = weakref.WeakSet()
+_live_other = weakref.WeakSet()  # batches and graphs
 
 
 @atexit.register
 def _release_all():
     # free every handle before interpreter teardown unloads the HIP runtime
+    for o in list(_live_other):
+        if isinstance(o, Graph):
+            o.free()
+    for o in list(_live_other):
+        o.free()
     for m in list(_live_meshes):
         m.free()
     for c in list(_live_ctxs):
@@ -353,6 +374,105 @@ class Mesh:
         _check(_lib.slw_permute_rows(self.h, _ptr(src, None, dev, "src"), _ptr(dst, None, dev, "dst"), row_bytes,
                                      1 if to_internal else 0), "slw_permute_rows")
         return dst
+
+
+class Batch:
+    """slw_batch_*: several meshes (SLW_INTERNAL_ORDER, same coordinate
+    type) stepped together in one launch per step."""
+
+    def __init__(self, ctx: Context, meshes):
+        self.ctx = ctx
+        self.meshes = list(meshes)
+        arr = (ctypes.c_void_p * len(self.meshes))(*[m.h.value for m in self.meshes])
+        h = ctypes.c_void_p()
+        _check(_lib.slw_batch_create(ctx.h, arr, len(self.meshes), ctypes.byref(h)), "slw_batch_create")
+        self.h = h
+        self._values = None
+        _live_other.add(self)
+
+    def set_fields(self, fields, dts, t0s=None):
+        n = len(self.meshes)
+        fa = (slw_field * n)(*[make_field(f) for f in fields])
+        da = np.ascontiguousarray(dts, dtype=np.float64)
+        ta = None if t0s is None else np.ascontiguousarray(t0s, dtype=np.float64)
+        _check(_lib.slw_batch_set_fields(self.h, fa, da.ctypes.data_as(_vp),
+                                         None if ta is None else ta.ctypes.data_as(_vp)), "slw_batch_set_fields")
+
+    def set_values(self, va, vb):
+        """va[i], vb[i]: device tensors n_nodes_i x k (internal order), same dtype and k."""
+        n = len(self.meshes)
+        k = 1 if va[0].ndim == 1 else va[0].shape[1]
+        dev = self.ctx.device
+        for i in range(n):
+            if va[i].shape[0] != self.meshes[i].n_nodes or vb[i].shape != va[i].shape:
+                raise ValueError(f"value buffers of mesh {i} must be n_nodes x k")
+            _ptr(va[i], va[0].dtype, dev, "va")
+            _ptr(vb[i], va[0].dtype, dev, "vb")
+        pa = (ctypes.c_void_p * n)(*[t.data_ptr() for t in va])
+        pb = (ctypes.c_void_p * n)(*[t.data_ptr() for t in vb])
+        _check(_lib.slw_batch_set_values(self.h, pa, pb, _vdtype(va[0]), k), "slw_batch_set_values")
+        self._values = (list(va), list(vb))
+
+    def set_step(self, n: int):
+        _check(_lib.slw_batch_set_step(self.h, int(n)), "slw_batch_set_step")
+
+    def get_step(self) -> int:
+        v = ctypes.c_int64()
+        _check(_lib.slw_batch_get_step(self.h, ctypes.byref(v)), "slw_batch_get_step")
+        return int(v.value)
+
+    def set_schedule(self, schedule: int, block: int = 256):
+        _check(_lib.slw_batch_set_schedule(self.h, int(schedule), int(block)), "slw_batch_set_schedule")
+
+    def step(self, scheme=SLW_EULER, outside_value=0.0, stats=False):
+        st = slw_stats() if stats else None
+        _check(_lib.slw_batch_step(self.h, int(scheme), float(outside_value),
+                                   ctypes.byref(st) if st is not None else None), "slw_batch_step")
+        return st.as_dict() if st is not None else None
+
+    def capture(self, n_steps: int, scheme=SLW_EULER, outside_value=0.0) -> "Graph":
+        h = ctypes.c_void_p()
+        _check(_lib.slw_batch_graph_capture(self.h, int(n_steps), int(scheme), float(outside_value), ctypes.byref(h)),
+               "slw_batch_graph_capture")
+        return Graph(h, self)
+
+    def autotune(self, scheme=SLW_EULER, cache_path=None):
+        s, b = ctypes.c_int(), ctypes.c_int()
+        _check(_lib.slw_batch_autotune(self.h, int(scheme), None if cache_path is None else str(cache_path).encode(),
+                                       ctypes.byref(s), ctypes.byref(b)), "slw_batch_autotune")
+        return int(s.value), int(b.value)
+
+    def free(self):
+        if getattr(self, "h", None) and getattr(self.ctx, "h", None):
+            _lib.slw_batch_free(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Graph:
+    def __init__(self, h, owner):
+        self.h = h
+        self.owner = owner
+        _live_other.add(self)
+
+    def launch(self):
+        _check(_lib.slw_graph_launch(self.h), "slw_graph_launch")
+
+    def free(self):
+        if getattr(self, "h", None):
+            _lib.slw_graph_free(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 def _vdtype(t):

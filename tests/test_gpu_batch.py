@@ -1,0 +1,126 @@
+"""Batches of uneven meshes in one launch, graph-captured steps, autotuner."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2104_09189_amd import inputs as I
+from gpu_util import ctx as _ctx, dev, host, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2104_09189_amd import slwalk
+    return slwalk
+
+
+@pytest.fixture(scope="module")
+def C(S):
+    return _ctx()
+
+
+def _workloads():
+    # uneven jittered grids, own swirl period each, Courant 5, Euler
+    out = []
+    for k, (n, period) in enumerate(((21, 0.7), (64, 1.3), (9, 2.0), (37, 0.5), (50, 1.0))):
+        xy, tri = I.jittered_grid(n, 4100 + k)
+        h = 1.0 / (n - 1)
+        out.append((xy, tri, I.swirl(period), 5.0 * h))
+    return out
+
+
+def _setup(S, C, coords_flag=0):
+    import torch
+    wl = _workloads()
+    meshes = [S.Mesh(C, xy, tri, S.INTERNAL_ORDER | coords_flag) for xy, tri, _, _ in wl]
+    perms = [m.dof_order() for m in meshes]
+    v0 = [I.gaussian_hill(xy)[:, None].astype(np.float32) for xy, _, _, _ in wl]
+    va = [dev(v[p]) for v, p in zip(v0, perms)]
+    vb = [torch.empty_like(a) for a in va]
+    b = S.Batch(C, meshes)
+    b.set_fields([f for _, _, f, _ in wl], [dt for _, _, _, dt in wl])
+    b.set_values(va, vb)
+    return wl, meshes, perms, v0, va, vb, b
+
+
+def test_batch_step_matches_oracle_every_schedule(S, C, orc):
+    wl, meshes, perms, v0, va, vb, b = _setup(S, C)
+    results = []
+    for schedule in (0, 1):
+        for block in (64, 128, 256, 512):
+            b.set_schedule(schedule, block)
+            b.set_step(4)                      # even: va -> vb, times 4 dt -> 5 dt
+            st = b.step(S.SLW_EULER, stats=True)
+            assert st["feet"] == sum(m.n_nodes for m in meshes)
+            assert b.get_step() == 5
+            results.append([host(t).copy() for t in vb])
+    # identical bits whatever the schedule and workgroup size
+    for r in results[1:]:
+        for a, c in zip(results[0], r):
+            assert np.array_equal(a, c)
+    for (xy, tri, fld, dt), p, v, out in zip(wl, perms, v0, results[0]):
+        ref, _, _, _ = orc.sl_step(xy, tri, v.astype(np.float64), fld, 4 * dt, dt, I.SCHEME_EULER)
+        assert rel_err(out, ref[p], 1.0) < 1e-5
+
+
+def test_graph_replay_equals_stepping(S, C):
+    wl, meshes, perms, v0, va, vb, b = _setup(S, C)
+    a0 = [t.clone() for t in va]
+    b.set_schedule(1, 256)
+    b.set_step(0)
+    for _ in range(6):
+        b.step(S.SLW_EULER)
+    stepped = [host(t).copy() for t in va]   # 6 steps: newest values back in va
+    for t, s in zip(va, a0):
+        t.copy_(s)
+    b.set_step(0)
+    g = b.capture(3, S.SLW_EULER)
+    assert b.get_step() == 0                 # capture does not run the steps
+    g.launch()
+    g.launch()                               # replays continue in time (device step index)
+    assert b.get_step() == 6
+    replayed = [host(t).copy() for t in va]
+    for x, y in zip(stepped, replayed):
+        assert np.array_equal(x, y)
+    g.free()
+
+
+def test_autotune_keeps_caller_state_and_caches(S, C, tmp_path):
+    wl, meshes, perms, v0, va, vb, b = _setup(S, C)
+    b.set_step(2)
+    before = [host(t).copy() for t in va]
+    cache = tmp_path / "tune.json"
+    s, blk = b.autotune(S.SLW_EULER, cache)
+    assert s in (0, 1) and blk in (64, 128, 256, 512)
+    assert b.get_step() == 2
+    for x, t in zip(before, va):
+        assert np.array_equal(x, host(t))
+    data = json.loads(cache.read_text())
+    assert len(data) == 1
+    entry = next(iter(data.values()))
+    assert entry["schedule"] == s and entry["block"] == blk and entry["ms"] > 0
+    # a second call reads the cache and applies the same choice
+    assert b.autotune(S.SLW_EULER, cache) == (s, blk)
+
+
+def test_batch_float_meshes(S, C, orc):
+    wl, meshes, perms, v0, va, vb, b = _setup(S, C, coords_flag=0x1)
+    b.set_step(0)
+    b.step(S.SLW_EULER)
+    for (xy, tri, fld, dt), p, v, out in zip(wl, perms, v0, vb):
+        ref, _, _, _ = orc.sl_step(xy, tri, v.astype(np.float64), fld, 0.0, dt, I.SCHEME_EULER)
+        assert rel_err(host(out), ref[p], 1.0) < 1e-4
+
+
+def test_batch_rejects_mixed_meshes(S, C):
+    xy, tri = I.jittered_grid(10, 1)
+    m1 = S.Mesh(C, xy, tri, S.INTERNAL_ORDER)
+    m2 = S.Mesh(C, xy, tri)
+    with pytest.raises(S.SlwError):
+        S.Batch(C, [m1, m2])
+    m3 = S.Mesh(C, xy, tri, S.INTERNAL_ORDER | S.COORDS_F32)
+    with pytest.raises(S.SlwError):
+        S.Batch(C, [m1, m3])

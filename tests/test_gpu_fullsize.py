@@ -1,0 +1,101 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py
+times (internal order, one fused step launch over all DOFs).
+
+The 1415 x 1415 graded mesh (3,998,792 triangles) is checked on a seeded
+sample of feet the oracle locates one by one; the 500 x 500 jittered mesh
+(498,002 triangles, random input order) is checked in full.
+"""
+import numpy as np
+import pytest
+
+from paper_2104_09189_amd import inputs as I
+from gpu_util import ctx as _ctx, dev, host, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2104_09189_amd import slwalk
+    return slwalk
+
+
+@pytest.fixture(scope="module")
+def C(S):
+    return _ctx()
+
+
+@pytest.fixture(scope="module")
+def graded():
+    return I.graded_swirl(alpha=5.0)
+
+
+def test_graded_1415_sampled_indices_and_values(S, C, orc, graded):
+    w = graded
+    mesh = S.Mesh(C, w.xy, w.tri, S.INTERNAL_ORDER)
+    perm = mesh.dof_order()                     # internal position -> user node id
+    t_n = 7 * w.dt
+    # indices on the oracle's feet, all 2,002,225 of them, sampled comparison
+    feet = orc.feet(w.xy, w.field, t_n + w.dt, w.dt, w.scheme)
+    out = mesh.locate_feet(feet=dev(feet[perm]), feet_in=True, want_steps=True, stats=True)
+    e_gpu = host(out["elem"])                   # internal order
+    rng = np.random.default_rng(3030)
+    sample = rng.choice(w.xy.shape[0], 20000, replace=False)   # internal positions
+    users = perm[sample]
+    e_ref, b_ref = orc.locate(w.xy, w.tri, feet[users])
+    assert (e_gpu[sample] == e_ref).all()
+    assert np.abs(host(out["bary"])[sample] - b_ref).max() < 1e-12
+    assert out["stats"]["feet"] == w.xy.shape[0]
+    # values of one fused step (16 FP32 fields) at the sampled DOFs
+    v0 = w.v0.astype(np.float32)
+    v_out = host(mesh.step(w.field, t_n, w.dt, w.scheme, dev(v0[perm])))
+    q_ref = orc.feet(w.xy[users], w.field, t_n + w.dt, w.dt, w.scheme)
+    e2, b2 = orc.locate(w.xy, w.tri, q_ref)
+    ref = orc.interp(1, w.tri, e2, b2, v0.astype(np.float64), w.xy.shape[0])
+    assert rel_err(v_out[sample], ref, np.abs(v0).max()) < 1e-5
+
+
+@pytest.mark.parametrize("alpha", [1.0, 5.0, 20.0])
+def test_swirl_500_random_order_full(S, C, orc, alpha):
+    w = I.swirl_500(alpha=alpha, order="random")
+    mesh = S.Mesh(C, w.xy, w.tri)
+    t_n = 3 * w.dt
+    out = mesh.locate_feet(w.field, t_n + w.dt, w.dt, w.scheme, want_feet=True, stats=True)
+    f_gpu = host(out["feet"])
+    f_ref = orc.feet(w.xy, w.field, t_n + w.dt, w.dt, w.scheme)
+    assert np.abs(f_gpu - f_ref).max() < 8 * 2.0 ** -52
+    # indices on identical (oracle) feet, every DOF
+    out = mesh.locate_feet(feet=dev(f_ref), feet_in=True)
+    e_ref, b_ref = orc.locate(w.xy, w.tri, f_ref)
+    assert (host(out["elem"]) == e_ref).all()
+    # values, P1 FP64, one step from identical V^n
+    v = host(mesh.step(w.field, t_n, w.dt, w.scheme, dev(w.v0)))
+    ref, _, _, _ = orc.sl_step(w.xy, w.tri, w.v0, w.field, t_n, w.dt, w.scheme)
+    assert rel_err(v, ref, np.abs(w.v0).max()) < 1e-12
+
+
+def test_swirl_500_p2_full(S, C, orc):
+    w = I.swirl_500(alpha=5.0, order="random")
+    p2 = orc.P2Dofs(w.xy, w.tri)
+    mesh = S.Mesh(C, w.xy, w.tri, S.P2)
+    assert mesh.n_dofs == p2.ndof == 998001
+    assert np.array_equal(mesh.dof_coords(), p2.xy)
+    v0 = I.gaussian_hill(p2.xy)[:, None]
+    v = host(mesh.step(w.field, 0.0, w.dt, w.scheme, dev(v0), order=2))
+    ref, _, _, _ = orc.sl_step(w.xy, w.tri, v0, w.field, 0.0, w.dt, w.scheme, order=2, p2=p2)
+    assert rel_err(v, ref, np.abs(v0).max()) < 1e-12
+
+
+def test_swirl_500_fp32_mesh_indices_on_rounded_inputs(S, C, orc):
+    w = I.swirl_500(alpha=5.0, order="morton")
+    mesh = S.Mesh(C, w.xy, w.tri, S.COORDS_F32)
+    f_ref = orc.feet(w.xy, w.field, 0.4, w.dt, w.scheme).astype(np.float32)
+    out = mesh.locate_feet(feet=dev(f_ref), feet_in=True)
+    e_ref, _ = orc.locate(w.xy.astype(np.float32).astype(np.float64), w.tri, f_ref.astype(np.float64))
+    assert (host(out["elem"]) == e_ref).all()
+    # FP32 feet, weights and values: error against the full-FP64 oracle step
+    v0 = w.v0.astype(np.float32)
+    v = host(mesh.step(w.field, 0.4 - w.dt, w.dt, w.scheme, dev(v0)))
+    ref, _, _, _ = orc.sl_step(w.xy, w.tri, v0.astype(np.float64), w.field, 0.4 - w.dt, w.dt, w.scheme)
+    err = rel_err(v, ref, np.abs(v0).max())
+    assert err < 1e-4, err
