@@ -133,6 +133,89 @@ def measure(mesh, w, v0, steps, warmup, start_mode):
     return {"ms_per_step": gpu_ms / steps, "kernel_ms": kernel_ms, "wall_s": wall, "stats": st}
 
 
+def measure_k_reuse(mesh, w, v0, reps=20):
+    """One location reused by K fields (one K = 16 step) against K separate
+    single-field steps (K locations) on the same mesh and feet."""
+    import torch
+    stream = torch.cuda.current_stream()
+    k = v0.shape[1]
+    v_out = torch.empty_like(v0)
+    singles = [v0[:, i:i + 1].contiguous() for i in range(k)]
+    outs = [torch.empty_like(x) for x in singles]
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    t_k = timed(lambda: mesh.step(w.field, 0.0, w.dt, w.scheme, v0, v_out))
+    t_1 = timed(lambda: [mesh.step(w.field, 0.0, w.dt, w.scheme, a, b) for a, b in zip(singles, outs)])
+    return {"k_fields": k, "one_location_ms": t_k, "separate_locations_ms": t_1, "speedup": t_1 / t_k}
+
+
+def measure_batch(steps=100):
+    """64 jittered meshes, triangle counts log-uniform in [1e4, 5e5], own swirl
+    period each, Courant 5, Euler, float coordinates (float filter, FP64 and
+    exact fallback), one float field: one launch per step for all meshes,
+    100 steps captured in one HIP graph, schedule chosen by the autotuner;
+    against the plain path (one step launch per mesh)."""
+    import torch
+    from paper_2104_09189_amd import inputs as I
+    from paper_2104_09189_amd import slwalk as S
+    wl = I.batch_meshes()
+    ctx = S.Context(0)
+    meshes = [S.Mesh(ctx, w.xy, w.tri, S.INTERNAL_ORDER | S.COORDS_F32) for w in wl]
+    va = [torch.from_numpy(np.ascontiguousarray(w.v0[m.dof_order()])).cuda() for w, m in zip(wl, meshes)]
+    vb = [torch.empty_like(a) for a in va]
+    b = S.Batch(ctx, meshes)
+    b.set_fields([w.field for w in wl], [w.dt for w in wl])
+    b.set_values(va, vb)
+    schedule, block = b.autotune(S.SLW_EULER)
+    b.set_step(0)
+    g = b.capture(steps, S.SLW_EULER)
+    stream = torch.cuda.current_stream()
+    g.launch()                      # warm-up replay
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    g.launch()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    graph_ms = e0.elapsed_time(e1) / steps
+    st = b.step(S.SLW_EULER, stats=True)
+    # plain path: one slw_step launch per mesh and step
+    outs = [torch.empty_like(a) for a in va]
+
+    def plain_step(n):
+        for w, m, a, o in zip(wl, meshes, va, outs):
+            m.step(w.field, n * w.dt, w.dt, w.scheme, a, o)
+    plain_step(0)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for n in range(10):
+        plain_step(n)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1) / 10
+    n_nodes = sum(m.n_nodes for m in meshes)
+    n_tris = sum(m.n_tris for m in meshes)
+    abytes = n_nodes * (8 + 4 + 4 + 2 * 4) + 12 * n_tris
+    g.free()
+    b.free()
+    return {"workload": f"{len(meshes)} jittered meshes, swirl, Courant 5, float coordinates, 1 field",
+            "n_nodes": n_nodes, "n_tris": n_tris, "steps_in_graph": steps, "schedule": schedule, "block": block,
+            "ms_per_step": graph_ms, "feet_per_s": n_nodes / (graph_ms * 1e-3),
+            "roofline_frac": abytes / (graph_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "mean_walk_steps": st["walk_steps"] / max(st["feet"], 1),
+            "plain_one_launch_per_mesh_ms_per_step": plain_ms, "speedup_vs_plain": plain_ms / graph_ms}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,6 +226,7 @@ def main():
     ap.add_argument("--k", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--only-a", action="store_true", help="measure strategy (a) only")
+    ap.add_argument("--no-batch", action="store_true", help="skip the multi-mesh batch measurement")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times (to scale HBM counters)")
@@ -216,6 +300,9 @@ def main():
             "ms_per_step": rb["ms_per_step"], "kernel_ms": rb["kernel_ms"],
             "mean_walk_steps": stb["walk_steps"] / max(stb["feet"], 1),
             "roofline_frac": abytes / (rb["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        out["k_field_reuse"] = measure_k_reuse(mesh, w, v0)
+    if not args.no_batch and not args.only_a:
+        out["batch"] = measure_batch()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(out), flush=True)

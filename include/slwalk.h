@@ -84,6 +84,7 @@ typedef enum slw_status {
 
 typedef struct slw_ctx slw_ctx;
 typedef struct slw_mesh slw_mesh;
+typedef struct slw_mlp slw_mlp;
 
 /* dtype codes */
 enum { SLW_F64 = 0, SLW_F32 = 1 };
@@ -95,8 +96,10 @@ enum {
     SLW_START_GIVEN = 1,   /* start[dof] = user triangle id */
     SLW_START_PREV = 2,    /* strategy (b): the element found for this DOF by the previous
                               SLW_START_PREV call on this mesh (steered when there is none) */
-    SLW_START_FIXED = 3    /* every walk starts at user triangle start[0] (the paper's
+    SLW_START_FIXED = 3,   /* every walk starts at user triangle start[0] (the paper's
                               fixed-start baseline, Section 2.2 complexity) */
+    SLW_START_LEARNED = 4  /* the triangle proposed by the network attached with
+                              slw_mesh_attach_mlp (learned start; see below) */
 };
 /* slw_mesh_upload flags */
 #define SLW_COORDS_F32 0x1u     /* store coordinates as float (FP32 walk, FP64/exact fallback) */
@@ -258,6 +261,75 @@ slw_status slw_graph_free(slw_graph *g);
  * signature applies the cached choice without timing.  Synchronous; the
  * caller's values and step index are left as they were. */
 slw_status slw_batch_autotune(slw_batch *b, int scheme, const char *cache_path, int *schedule_out, int *block_out);
+
+/* ------------------------------------------------------------------------
+ * Learned start proposal.  A network (x, y, dx, dy, t) -> 64 -> 64 -> 2 with
+ * ReLU maps a foot (node x, y; displacement dx, dy to the foot; time t =
+ * t_{n+1}) to chart coordinates (u, v) of the mesh; a G x G table maps
+ * (floor(u G), floor(v G)) to a start triangle, and the exact walk finishes
+ * the search.  This follows the hybrid idea that closes the numerical
+ * section (Section 4) of the paper: the start comes from local information
+ * about the dynamics.  Results never depend on the network: the element
+ * found is the walk's exact answer from any start (a bad network only costs
+ * steps).  The chart is the Rosenblatt transform of the triangle-centroid
+ * distribution: u = rank of the centroid's x among all centroids (in (0,1)),
+ * v = rank of its y among the centroids of its u slab (slab = floor(u G)).
+ *
+ * Parameters: one float vector of 4674 numbers, W1 (5 x 64, input-major:
+ * W1[i][j] at i * 64 + j), b1 (64), W2 (64 x 64), b2 (64), W3 (64 x 2), b3
+ * (2); a layer computes act(h W + b).  Inputs are normalised as
+ * (f - shift) * scale in float, norm = shift[5], scale[5].  Training is FP32
+ * (own forward/backward kernels, Adam); inference uses bfloat16 operands
+ * (round to nearest even) on the matrix cores with FP32 accumulation.
+ * Sample arrays: X (device, m x 5 floats: x, y, dx, dy, t), Y (device, m x 2
+ * floats: target u, v; a negative u marks a sample without target, which
+ * counts in the batch size but not in the loss). */
+
+/* Builds (or rebuilds) the chart of a mesh with a g x g start table
+ * (1 <= g <= 8192), on the host from the device records; synchronous.
+ * Device memory: 8 B per triangle + 4 g^2 B. */
+slw_status slw_chart_build(slw_mesh *mesh, int g);
+/* Chart coordinates of every triangle's centroid, user triangle order:
+ * uv_h[2 t], uv_h[2 t + 1] (host, n_tris x 2); synchronous. */
+slw_status slw_chart_coords(slw_mesh *mesh, float *uv_h);
+/* New network on the context's device: He-uniform weights (limit
+ * sqrt(6 / fan_in), from a splitmix64 stream seeded with seed), zero biases,
+ * identity normalisation, zero Adam state.  Free with slw_mlp_free. */
+slw_status slw_mlp_create(slw_ctx *ctx, uint64_t seed, slw_mlp **out);
+slw_status slw_mlp_free(slw_mlp *n);
+/* Host copies of the FP32 parameters (4674 floats) and the normalisation
+ * (10 floats); setting parameters also refreshes the bfloat16 operands. */
+slw_status slw_mlp_set_params(slw_mlp *n, const float *params_h);
+slw_status slw_mlp_get_params(slw_mlp *n, float *params_h);
+slw_status slw_mlp_set_normalization(slw_mlp *n, const float *norm_h);
+slw_status slw_mlp_get_normalization(slw_mlp *n, float *norm_h);
+/* shift = mean, scale = 1 / standard deviation (1 where it is 0) of each
+ * input over the m samples X (FP64 sums). */
+slw_status slw_mlp_fit_normalization(slw_mlp *n, const float *X, int64_t m);
+/* Training samples from the plain walk: for the DOFs dofs[i] (device, m
+ * ints, internal positions 0 .. n_dofs-1) the foot of the step ending at
+ * t_np1 is computed and located with the strategy (a) start; X[i] gets the
+ * foot's inputs, Y[i] the chart coordinates of the element found ((-1, -1)
+ * when outside; out-of-range ids give zeros and (-1, -1)).  Needs a chart. */
+slw_status slw_learned_gather(slw_mesh *mesh, const slw_field *field, double t_np1, double dt, int scheme,
+                              const int32_t *dofs, int64_t m, float *X, float *Y);
+/* Gradient of the loss = mean over the m samples of |out - Y|^2 (FP32,
+ * per-workgroup partial sums added in a fixed order: bit-reproducible).
+ * grad_h (host, 4674 floats) and loss_h (mean over samples with a target)
+ * are nullable; synchronous. */
+slw_status slw_mlp_grad(slw_mlp *n, const float *X, const float *Y, int64_t m, float *grad_h, float *loss_h);
+/* Adam (beta 0.9, 0.999, eps 1e-8, step lr) over epochs passes of
+ * minibatches of `batch` samples, the samples of each epoch in the order
+ * i -> (a i + c) mod m with a, c drawn from seed; loss_h (nullable) gets
+ * the loss of the last minibatch before its update; synchronous at the end. */
+slw_status slw_mlp_train(slw_mlp *n, const float *X, const float *Y, int64_t m, int epochs, int64_t batch,
+                         float lr, uint64_t seed, float *loss_h);
+/* Network outputs (bfloat16 matrix-core path) of m samples: out (device,
+ * m x 2 floats). */
+slw_status slw_mlp_forward(slw_mlp *n, const float *X, int64_t m, float *out);
+/* Attaches a network (borrowed: keep it alive while attached; NULL
+ * detaches) to a mesh with a chart, for SLW_START_LEARNED. */
+slw_status slw_mesh_attach_mlp(slw_mesh *mesh, slw_mlp *n);
 
 /* The library's orientation predicate evaluated on the host, for testing:
  * out_h[i] = sign of orient(a, b, c) for the triple pts_h[6i .. 6i+5] =

@@ -46,27 +46,24 @@ slw_status ensure_work(slw_ctx *ctx, size_t bytes)
     return SLW_OK;
 }
 
+bool field_ok(const slw_field *f) { return f && f->kind >= 0 && f->kind <= 4; }
+
+FieldDev to_dev(const slw_field *f)
+{
+    FieldDev d{};
+    if (f) {
+        d.kind = f->kind;
+        for (int i = 0; i < 8; ++i)
+            d.p[i] = f->p[i];
+    }
+    return d;
+}
+
 }  // namespace slw
 
 using namespace slw;
 
 namespace {
-
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev)
-    {
-        if (hipGetDevice(&prev) != hipSuccess)
-            prev = -1;
-        if (prev != dev)
-            (void)hipSetDevice(dev);
-    }
-    ~DeviceGuard()
-    {
-        if (prev >= 0)
-            (void)hipSetDevice(prev);
-    }
-};
 
 slw_status begin_stats(slw_ctx *ctx, slw_stats *stats_h)
 {
@@ -101,19 +98,6 @@ slw_status end_stats(slw_ctx *ctx, slw_stats *stats_h)
     if (h.hard_fail)
         return set_error(SLW_E_WALK, std::to_string(h.hard_fail) + " walks exceeded the hard step limit");
     return SLW_OK;
-}
-
-bool field_ok(const slw_field *f) { return f && f->kind >= 0 && f->kind <= 4; }
-
-FieldDev to_dev(const slw_field *f)
-{
-    FieldDev d{};
-    if (f) {
-        d.kind = f->kind;
-        for (int i = 0; i < 8; ++i)
-            d.p[i] = f->p[i];
-    }
-    return d;
 }
 
 }  // namespace
@@ -322,16 +306,26 @@ slw_status slw_locate_feet(slw_mesh *mesh, const slw_field *field, double t_np1,
         return set_error(SLW_E_ARG, "feet (SLW_FEET_IN) or a valid field is required");
     if (scheme != SLW_EULER && scheme != SLW_RK2)
         return set_error(SLW_E_ARG, "unknown scheme");
-    if (start_mode < SLW_START_STEERED || start_mode > SLW_START_FIXED)
+    if (start_mode < SLW_START_STEERED || start_mode > SLW_START_LEARNED)
         return set_error(SLW_E_ARG, "unknown start mode");
     if ((start_mode == SLW_START_GIVEN || start_mode == SLW_START_FIXED) && !start)
         return set_error(SLW_E_ARG, "start array required for this start mode");
+    if (start_mode == SLW_START_LEARNED && (!mesh->m.mlp || !mesh->m.learned_start))
+        return set_error(SLW_E_ARG, "SLW_START_LEARNED needs a network attached (slw_mesh_attach_mlp)");
     slw_ctx *ctx = mesh->ctx;
     DeviceGuard g(ctx->device);
     slw_status st = begin_stats(ctx, stats_h);
     if (st != SLW_OK)
         return st;
     FieldDev fd = to_dev(field);
+    if (start_mode == SLW_START_LEARNED) {
+        st = hip_check(launch_learned_start(mesh->m, ctx->stream, fd, t_np1, dt, scheme, feet_in ? feet : nullptr,
+                                            mesh->m.n_dofs, mesh->m.learned_start),
+                       "learned start");
+        if (st != SLW_OK)
+            return st;
+        start = mesh->m.learned_start;
+    }
     st = hip_check(launch_locate_feet(mesh->m, ctx->stream, feet_in ? nullptr : &fd, t_np1, dt, scheme, start_mode,
                                       start, feet_in, feet, elem, bary, steps, stats_h ? ctx->stats : nullptr),
                    "slw_locate_feet");
@@ -372,10 +366,12 @@ slw_status slw_step(slw_mesh *mesh, const slw_field *field, double t_n, double d
         return set_error(SLW_E_ARG, "unknown scheme");
     if (vdtype != SLW_F64 && vdtype != SLW_F32)
         return set_error(SLW_E_ARG, "unknown vdtype");
-    if (start_mode < SLW_START_STEERED || start_mode > SLW_START_FIXED)
+    if (start_mode < SLW_START_STEERED || start_mode > SLW_START_LEARNED)
         return set_error(SLW_E_ARG, "unknown start mode");
     if ((start_mode == SLW_START_GIVEN || start_mode == SLW_START_FIXED) && !start)
         return set_error(SLW_E_ARG, "start array required for this start mode");
+    if (start_mode == SLW_START_LEARNED && (!mesh->m.mlp || !mesh->m.learned_start))
+        return set_error(SLW_E_ARG, "SLW_START_LEARNED needs a network attached (slw_mesh_attach_mlp)");
     const DevMesh &m = mesh->m;
     // P1 uses the vertex DOFs only (the first n_nodes of either order)
     const int64_t rows = order == 1 ? m.n_nodes : m.n_dofs;
@@ -404,6 +400,13 @@ slw_status slw_step(slw_mesh *mesh, const slw_field *field, double t_n, double d
     }
     const bool write_prev = start_mode == SLW_START_PREV;
     FieldDev fd = to_dev(field);
+    if (start_mode == SLW_START_LEARNED) {
+        st = hip_check(launch_learned_start(m, ctx->stream, fd, t_n + dt, dt, scheme, nullptr, rows, m.learned_start),
+                       "learned start");
+        if (st != SLW_OK)
+            return st;
+        start = m.learned_start;
+    }
     st = hip_check(launch_step(m, ctx->stream, fd, t_n, dt, scheme, order, start_mode, start, vin_int, vdtype, k,
                                v_out, outside_value, write_prev, out_map, stats_h ? ctx->stats : nullptr),
                    "slw_step");

@@ -50,6 +50,13 @@ struct DevMesh {
     int32_t *prev_elem = nullptr; // [n_dofs] internal tri of the last location (strategy b)
     int32_t *jump = nullptr;      // [jump_g * jump_g] bucket grid of start triangles (internal)
     int jump_g = 1;
+    // learned start proposal: chart coordinates of triangle centroids, the
+    // chart's start table, the attached network and a start workspace
+    float2 *chart_uv = nullptr;       // [n_tris]
+    int32_t *chart_table = nullptr;   // [chart_g * chart_g] internal triangle ids
+    int chart_g = 0;
+    int32_t *learned_start = nullptr; // [n_dofs]
+    struct slw_mlp *mlp = nullptr;    // borrowed
     // host copies kept for queries about the mesh
     std::vector<double> dof_xy_user_h;  // n_dofs x 2, user order
     std::vector<int32_t> dof_user_h;    // internal -> user
@@ -79,10 +86,49 @@ struct slw_mesh {
     slw::DevMesh m;
 };
 
+// The start-proposal network 5 -> 64 -> 64 -> 2 (ReLU hidden layers):
+// FP32 master parameters, Adam moments, gradient buffers, input
+// normalisation, and the weights repacked as bfloat16 in the per-lane
+// operand layout of the matrix-core forward pass.
+struct slw_mlp {
+    slw_ctx *ctx = nullptr;
+    float *params = nullptr;   // [kMlpParams]
+    float *adam_m = nullptr, *adam_v = nullptr;
+    float *grad = nullptr;     // [kMlpParams]
+    float *partial = nullptr;  // [kMlpPartials * (kMlpParams + 2)]
+    float *norm = nullptr;     // [10]: shift[5], scale[5]
+    uint16_t *wpack = nullptr; // bfloat16 operands, see the forward kernel
+    float *bias = nullptr;     // [64 + 64 + 16] biases in accumulator order
+    int64_t adam_t = 0;
+};
+
 namespace slw {
 slw_status set_error(slw_status s, const std::string &msg);
 slw_status hip_check(hipError_t e, const char *what);
 slw_status ensure_work(slw_ctx *ctx, size_t bytes);
+bool field_ok(const slw_field *f);
+struct FieldDev;
+FieldDev to_dev(const slw_field *f);
+
+// makes a device current for the lifetime of the guard
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess)
+            prev = -1;
+        if (prev != dev)
+            (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0)
+            (void)hipSetDevice(prev);
+    }
+};
+
+constexpr int kMlpParams = 5 * 64 + 64 + 64 * 64 + 64 + 64 * 2 + 2;  // 4674
+constexpr int kMlpPartials = 1024;                                   // workgroups per gradient pass
 
 // mesh construction (slw_mesh.cpp)
 slw_status build_mesh(slw_ctx *ctx, const double *xy, int64_t n, const int32_t *tri, int64_t nt, uint32_t flags,
@@ -140,6 +186,11 @@ hipError_t launch_step(const DevMesh &m, hipStream_t st, const FieldDev &f, doub
                        int order, int start_mode, const int32_t *start, const void *v_in, int vdtype, int k,
                        void *v_out, double outside, bool write_prev, const int32_t *out_map, DevStats *stats);
 hipError_t launch_zero_stats(hipStream_t st, DevStats *p);
+// learned start proposal (the mesh needs a chart and an attached network)
+hipError_t launch_learned_start(const DevMesh &m, hipStream_t st, const FieldDev &f, double t_np1, double dt,
+                                int scheme, const void *feet_in, int64_t n_iter, int32_t *start);
+hipError_t launch_learned_gather(const DevMesh &m, hipStream_t st, const FieldDev &f, double t_np1, double dt,
+                                 int scheme, const int32_t *dofs, int64_t cnt, float *X, float *Y);
 
 // one mesh of a batch (device table; see slw_batch_* in slwalk.h)
 struct BatchItem {

@@ -14,6 +14,7 @@
 #include <type_traits>
 
 #include "slw_internal.h"
+#include "slw_mlp.h"
 #include "slw_predicates.h"
 
 namespace slw {
@@ -154,6 +155,11 @@ __device__ inline int32_t start_for(const MeshView &mv, int64_t d, int64_t api, 
         const int32_t pe = mv.prev[d];
         if (pe >= 0)
             return pe;
+    }
+    if (mode == SLW_START_LEARNED) {  // internal ids proposed by the network
+        const int32_t j = start[d];
+        if (j >= 0 && j < mv.n_tris)
+            return j;
     }
     return quadrant_start(mv.qstart[d], dx, dy);
 }
@@ -878,6 +884,88 @@ __global__ void k_permute_rows(const uint32_t *__restrict__ src, uint32_t *__res
     }
 }
 
+// ---------------------------------------------------------------------------
+// learned start proposal: the network maps a foot to chart coordinates and
+// the chart table to a start triangle; the walk above finishes the search
+
+// raw network inputs of a foot: node position, displacement to the foot, time
+template <typename R>
+__device__ inline void raw_features(R x, R y, R qx, R qy, double t, float f[5])
+{
+    f[0] = (float)x;
+    f[1] = (float)y;
+    f[2] = (float)(qx - x);
+    f[3] = (float)(qy - y);
+    f[4] = (float)t;
+}
+
+// start[d] for the DOFs [0, n_iter) (internal order); feet either computed
+// from the field or read from feet_in (indexed like slw_locate_feet's feet)
+template <bool F32>
+__global__ void __launch_bounds__(kBlock)
+    k_learned_start(MeshView mv, FieldDev f, double dt, double t_np1, int scheme,
+                    const typename CT<F32>::R2 *__restrict__ feet_in, const uint16_t *__restrict__ wpack,
+                    const float *__restrict__ bias, const float *__restrict__ norm,
+                    const int32_t *__restrict__ table, int g, int64_t n_iter, int32_t *__restrict__ start)
+{
+    using R = typename CT<F32>::R;
+    using R2 = typename CT<F32>::R2;
+    const int64_t d = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    float feat[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    if (d < n_iter) {
+        const R2 x = ((const R2 *)mv.dof_xy)[d];
+        R qx, qy;
+        if (feet_in) {
+            const int64_t api = mv.internal_order ? d : mv.dof_user[d];
+            qx = feet_in[api].x;
+            qy = feet_in[api].y;
+        } else {
+            foot_of<R>(f, scheme, x.x, x.y, (R)dt, qx, qy);
+        }
+        raw_features<R>(x.x, x.y, qx, qy, t_np1, feat);
+        mlp_normalise(norm, feat);
+    }
+    const float2 uv = mlp_forward_wave(wpack, bias, feat);  // every lane
+    if (d < n_iter)
+        start[d] = chart_lookup(table, g, uv);
+}
+
+// Training pairs: for the DOFs dofs[i] (internal positions) the plain walk
+// (strategy (a) start) locates the foot; X[i] = raw features, Y[i] = chart
+// coordinates of the element found, (-1, -1) when the foot is outside.
+template <bool F32>
+__global__ void __launch_bounds__(kBlock)
+    k_gather(MeshView mv, FieldDev f, double dt, double t_np1, int scheme, const int32_t *__restrict__ dofs,
+             int64_t m, const float2 *__restrict__ chart_uv, float *__restrict__ X, float2 *__restrict__ Y)
+{
+    using R = typename CT<F32>::R;
+    using R2 = typename CT<F32>::R2;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= m)
+        return;
+    const int64_t d = dofs[i];
+    if (d < 0 || d >= mv.n_dofs) {
+        for (int c = 0; c < 5; ++c)
+            X[5 * i + c] = 0.f;
+        Y[i] = make_float2(-1.f, -1.f);
+        return;
+    }
+    const R2 x = ((const R2 *)mv.dof_xy)[d];
+    R qx, qy;
+    foot_of<R>(f, scheme, x.x, x.y, (R)dt, qx, qy);
+    int32_t e = -1;
+    if (in_box<R>(qx, qy, mv.bb)) {
+        Counters c;
+        const int32_t j0 = quadrant_start(mv.qstart[d], (float)(qx - x.x), (float)(qy - x.y));
+        e = walk<F32>(mv, j0, qx, qy, (uint32_t)d * 2654435761u, c).elem;
+    }
+    float feat[5];
+    raw_features<R>(x.x, x.y, qx, qy, t_np1, feat);
+    for (int c = 0; c < 5; ++c)
+        X[5 * i + c] = feat[c];
+    Y[i] = e >= 0 ? chart_uv[e] : make_float2(-1.f, -1.f);
+}
+
 __global__ void k_zero_u64(unsigned long long *p, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1065,6 +1153,49 @@ hipError_t launch_permute_rows(hipStream_t st, const void *src, void *dst, int64
     g = g < 1 ? 1 : (g > ((int64_t)1 << 20) ? ((int64_t)1 << 20) : g);
     hipLaunchKernelGGL(k_permute_rows, dim3((unsigned)g), dim3(kBlock), 0, st, (const uint32_t *)src,
                        (uint32_t *)dst, rows, words, map, scatter);
+    return hipGetLastError();
+}
+
+hipError_t launch_learned_start(const DevMesh &m, hipStream_t st, const FieldDev &f0, double t_np1, double dt,
+                                int scheme, const void *feet_in, int64_t n_iter, int32_t *start)
+{
+    const slw_mlp *n = m.mlp;
+    if (!n || !m.chart_table || n_iter <= 0)
+        return n_iter <= 0 ? hipSuccess : hipErrorInvalidValue;
+    unsigned g;
+    if (!tiles_for(n_iter, g))
+        return hipErrorInvalidValue;
+    MeshView mv = view_of(m);
+    FieldDev f = f0;
+    field_time_factors(f, t_np1, dt);
+    if (m.coords_f32)
+        hipLaunchKernelGGL(k_learned_start<true>, dim3(g), dim3(kBlock), 0, st, mv, f, dt, t_np1, scheme,
+                           (const float2 *)feet_in, n->wpack, n->bias, n->norm, m.chart_table, m.chart_g, n_iter,
+                           start);
+    else
+        hipLaunchKernelGGL(k_learned_start<false>, dim3(g), dim3(kBlock), 0, st, mv, f, dt, t_np1, scheme,
+                           (const double2 *)feet_in, n->wpack, n->bias, n->norm, m.chart_table, m.chart_g, n_iter,
+                           start);
+    return hipGetLastError();
+}
+
+hipError_t launch_learned_gather(const DevMesh &m, hipStream_t st, const FieldDev &f0, double t_np1, double dt,
+                                 int scheme, const int32_t *dofs, int64_t cnt, float *X, float *Y)
+{
+    if (cnt <= 0)
+        return hipSuccess;
+    unsigned g;
+    if (!tiles_for(cnt, g))
+        return hipErrorInvalidValue;
+    MeshView mv = view_of(m);
+    FieldDev f = f0;
+    field_time_factors(f, t_np1, dt);
+    if (m.coords_f32)
+        hipLaunchKernelGGL(k_gather<true>, dim3(g), dim3(kBlock), 0, st, mv, f, dt, t_np1, scheme, dofs, cnt,
+                           m.chart_uv, X, (float2 *)Y);
+    else
+        hipLaunchKernelGGL(k_gather<false>, dim3(g), dim3(kBlock), 0, st, mv, f, dt, t_np1, scheme, dofs, cnt,
+                           m.chart_uv, X, (float2 *)Y);
     return hipGetLastError();
 }
 

@@ -32,7 +32,7 @@ _lib = ctypes.CDLL(str(LIB_PATH))
 SLW_OK = 0
 SLW_F64, SLW_F32 = 0, 1
 SLW_EULER, SLW_RK2 = 0, 1
-START_STEERED, START_GIVEN, START_PREV, START_FIXED = 0, 1, 2, 3
+START_STEERED, START_GIVEN, START_PREV, START_FIXED, START_LEARNED = 0, 1, 2, 3, 4
 COORDS_F32, P2, NO_REORDER, INTERNAL_ORDER = 0x1, 0x2, 0x4, 0x8
 FEET_IN = 0x1
 
@@ -119,6 +119,24 @@ _sig("slw_graph_launch", ctypes.c_int, [_vp])
 _sig("slw_graph_free", ctypes.c_int, [_vp])
 _sig("slw_batch_autotune", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int),
                                           ctypes.POINTER(ctypes.c_int)])
+_sig("slw_chart_build", ctypes.c_int, [_vp, ctypes.c_int])
+_sig("slw_chart_coords", ctypes.c_int, [_vp, _vp])
+_sig("slw_mlp_create", ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(_vp)])
+_sig("slw_mlp_free", ctypes.c_int, [_vp])
+_sig("slw_mlp_set_params", ctypes.c_int, [_vp, _vp])
+_sig("slw_mlp_get_params", ctypes.c_int, [_vp, _vp])
+_sig("slw_mlp_set_normalization", ctypes.c_int, [_vp, _vp])
+_sig("slw_mlp_get_normalization", ctypes.c_int, [_vp, _vp])
+_sig("slw_mlp_fit_normalization", ctypes.c_int, [_vp, _vp, _i64])
+_sig("slw_learned_gather", ctypes.c_int, [_vp, ctypes.POINTER(slw_field), _dbl, _dbl, ctypes.c_int, _vp, _i64, _vp,
+                                          _vp])
+_sig("slw_mlp_grad", ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, ctypes.POINTER(ctypes.c_float)])
+_sig("slw_mlp_train", ctypes.c_int, [_vp, _vp, _vp, _i64, ctypes.c_int, _i64, ctypes.c_float, ctypes.c_uint64,
+                                     ctypes.POINTER(ctypes.c_float)])
+_sig("slw_mlp_forward", ctypes.c_int, [_vp, _vp, _i64, _vp])
+_sig("slw_mesh_attach_mlp", ctypes.c_int, [_vp, _vp])
+
+MLP_PARAMS = 5 * 64 + 64 + 64 * 64 + 64 + 64 * 2 + 2
 
 EXPORTED = ["slw_status_string", "slw_last_error", "slw_ctx_create", "slw_ctx_set_stream", "slw_ctx_destroy",
             "slw_mesh_upload", "slw_mesh_check", "slw_mesh_free", "slw_mesh_get_info", "slw_mesh_dof_coords", "slw_mesh_dof_order",
@@ -126,7 +144,11 @@ EXPORTED = ["slw_status_string", "slw_last_error", "slw_ctx_create", "slw_ctx_se
             "slw_permute_rows", "slw_orient_sign_host",
             "slw_float_filter_host", "slw_batch_create", "slw_batch_free", "slw_batch_set_fields",
             "slw_batch_set_values", "slw_batch_set_step", "slw_batch_get_step", "slw_batch_set_schedule",
-            "slw_batch_step", "slw_batch_graph_capture", "slw_graph_launch", "slw_graph_free", "slw_batch_autotune"]
+            "slw_batch_step", "slw_batch_graph_capture", "slw_graph_launch", "slw_graph_free", "slw_batch_autotune",
+            "slw_chart_build", "slw_chart_coords", "slw_mlp_create", "slw_mlp_free", "slw_mlp_set_params",
+            "slw_mlp_get_params", "slw_mlp_set_normalization", "slw_mlp_get_normalization",
+            "slw_mlp_fit_normalization", "slw_learned_gather", "slw_mlp_grad", "slw_mlp_train", "slw_mlp_forward",
+            "slw_mesh_attach_mlp"]
 
 
 def _check(rc: int, where: str):
@@ -178,7 +200,7 @@ import weakref  # noqa: E402
 
 _live_meshes = weakref.WeakSet()
 _live_ctxs = weakref.WeakSet()
-_live_other = weakref.WeakSet()  # batches and graphs
+_live_other = weakref.WeakSet()  # batches, graphs and networks
 
 
 @atexit.register
@@ -278,6 +300,37 @@ class Mesh:
             self.free()
         except Exception:
             pass
+
+    # -- learned start
+    def chart_build(self, g: int = 2048):
+        _check(_lib.slw_chart_build(self.h, int(g)), "slw_chart_build")
+        self.chart_g = int(g)
+
+    def chart_coords(self) -> np.ndarray:
+        out = np.empty((self.n_tris, 2), dtype=np.float32)
+        _check(_lib.slw_chart_coords(self.h, out.ctypes.data_as(_vp)), "slw_chart_coords")
+        return out
+
+    def learned_gather(self, field, t_np1, dt, scheme, dofs, X=None, Y=None):
+        """Training pairs for the DOFs `dofs` (int32 device tensor, internal positions)."""
+        torch = _torch()
+        dev = self.ctx.device
+        m = dofs.shape[0]
+        if X is None:
+            X = torch.empty((m, 5), dtype=torch.float32, device=f"cuda:{dev}")
+        if Y is None:
+            Y = torch.empty((m, 2), dtype=torch.float32, device=f"cuda:{dev}")
+        if X.shape != (m, 5) or Y.shape != (m, 2):
+            raise ValueError("X must be m x 5 and Y m x 2")
+        f = make_field(field)
+        _check(_lib.slw_learned_gather(self.h, ctypes.byref(f), float(t_np1), float(dt), int(scheme),
+                                       _ptr(dofs, torch.int32, dev, "dofs"), m, _ptr(X, torch.float32, dev, "X"),
+                                       _ptr(Y, torch.float32, dev, "Y")), "slw_learned_gather")
+        return X, Y
+
+    def attach_mlp(self, net):
+        _check(_lib.slw_mesh_attach_mlp(self.h, None if net is None else net.h), "slw_mesh_attach_mlp")
+        self.mlp = net  # keeps the borrowed network alive while attached
 
     # -- calls
     def locate(self, q, start=None, elem=None, bary=None, steps=None, want_bary=True, want_steps=False):
@@ -445,6 +498,88 @@ class Batch:
     def free(self):
         if getattr(self, "h", None) and getattr(self.ctx, "h", None):
             _lib.slw_batch_free(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Mlp:
+    """The start-proposal network (slw_mlp_*)."""
+
+    def __init__(self, ctx: Context, seed: int = 0):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        _check(_lib.slw_mlp_create(ctx.h, ctypes.c_uint64(seed), ctypes.byref(h)), "slw_mlp_create")
+        self.h = h
+        _live_other.add(self)
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(MLP_PARAMS, dtype=np.float32)
+        _check(_lib.slw_mlp_get_params(self.h, out.ctypes.data_as(_vp)), "slw_mlp_get_params")
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        if p.size != MLP_PARAMS:
+            raise ValueError(f"{MLP_PARAMS} parameters expected")
+        _check(_lib.slw_mlp_set_params(self.h, p.ctypes.data_as(_vp)), "slw_mlp_set_params")
+
+    def get_normalization(self) -> np.ndarray:
+        out = np.empty(10, dtype=np.float32)
+        _check(_lib.slw_mlp_get_normalization(self.h, out.ctypes.data_as(_vp)), "slw_mlp_get_normalization")
+        return out
+
+    def set_normalization(self, norm):
+        norm = np.ascontiguousarray(norm, dtype=np.float32)
+        if norm.size != 10:
+            raise ValueError("10 numbers expected (shift[5], scale[5])")
+        _check(_lib.slw_mlp_set_normalization(self.h, norm.ctypes.data_as(_vp)), "slw_mlp_set_normalization")
+
+    def _xy(self, X, Y=None):
+        torch = _torch()
+        dev = self.ctx.device
+        if X.ndim != 2 or X.shape[1] != 5:
+            raise ValueError("X must be m x 5")
+        if Y is not None and tuple(Y.shape) != (X.shape[0], 2):
+            raise ValueError("Y must be m x 2")
+        return (_ptr(X, torch.float32, dev, "X"),
+                None if Y is None else _ptr(Y, torch.float32, dev, "Y"))
+
+    def fit_normalization(self, X):
+        px, _ = self._xy(X)
+        _check(_lib.slw_mlp_fit_normalization(self.h, px, X.shape[0]), "slw_mlp_fit_normalization")
+
+    def grad(self, X, Y):
+        px, py = self._xy(X, Y)
+        g = np.empty(MLP_PARAMS, dtype=np.float32)
+        loss = ctypes.c_float()
+        _check(_lib.slw_mlp_grad(self.h, px, py, X.shape[0], g.ctypes.data_as(_vp), ctypes.byref(loss)),
+               "slw_mlp_grad")
+        return g, float(loss.value)
+
+    def train(self, X, Y, epochs=1, batch=65536, lr=1e-3, seed=0):
+        px, py = self._xy(X, Y)
+        loss = ctypes.c_float()
+        _check(_lib.slw_mlp_train(self.h, px, py, X.shape[0], int(epochs), int(batch), ctypes.c_float(lr),
+                                  ctypes.c_uint64(seed), ctypes.byref(loss)), "slw_mlp_train")
+        return float(loss.value)
+
+    def forward(self, X, out=None):
+        torch = _torch()
+        px, _ = self._xy(X)
+        if out is None:
+            out = torch.empty((X.shape[0], 2), dtype=torch.float32, device=f"cuda:{self.ctx.device}")
+        _check(_lib.slw_mlp_forward(self.h, px, X.shape[0], _ptr(out, torch.float32, self.ctx.device, "out")),
+               "slw_mlp_forward")
+        return out
+
+    def free(self):
+        if getattr(self, "h", None) and getattr(self.ctx, "h", None):
+            _lib.slw_mlp_free(self.h)
         self.h = None
 
     def __del__(self):

@@ -333,3 +333,51 @@ def test_full_turn_error_decreases_under_refinement(orc):
         errs.append(np.abs(v[:, 0] - I.gaussian_hill(xy)).max())
     assert errs[0] > errs[1] > errs[2]
     assert errs[2] < 0.2 * errs[0]
+
+
+# ---------------------------------------------------------------------------
+# learned start proposal: the network oracle
+
+def test_mlp_gradient_matches_central_differences():
+    from oracle import mlp
+    rng = np.random.default_rng(21)
+    p = mlp.he_uniform(3).astype(np.float64)
+    X = rng.uniform(-1, 1, (37, 5))
+    Y = rng.uniform(0, 1, (37, 2))
+    g = mlp.grad(p, X, Y)
+    assert g.shape == (mlp.n_params(),) == (4674,)
+    idx = rng.choice(p.size, 300, replace=False)
+    eps = 1e-6
+    for i in idx:
+        e = np.zeros_like(p)
+        e[i] = eps
+        fd = (mlp.loss(p + e, X, Y) - mlp.loss(p - e, X, Y)) / (2 * eps)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, g[i])
+
+
+def test_mlp_forward_by_hand_on_a_tiny_case():
+    from oracle import mlp
+    # only one path is live: input 0 -> hidden unit 0 -> hidden unit 0 -> outputs
+    p = np.zeros(mlp.n_params())
+    layers = mlp.unpack(p.copy())
+    W1, b1 = np.zeros((5, 64)), np.zeros(64)
+    W2, b2 = np.zeros((64, 64)), np.zeros(64)
+    W3, b3 = np.zeros((64, 2)), np.array([0.25, -1.0])
+    W1[0, 0], b1[0] = 2.0, -1.0          # h1 = relu(2 x0 - 1)
+    W2[0, 0], b2[0] = -3.0, 4.0          # h2 = relu(-3 h1 + 4)
+    W3[0, 0], W3[0, 1] = 0.5, 1.0
+    p = mlp.pack([(W1, b1), (W2, b2), (W3, b3)])
+    X = np.array([[0.0, 9, 9, 9, 9], [1.0, 0, 0, 0, 0], [3.0, 0, 0, 0, 0]])
+    out, _ = mlp.forward(p, X)
+    # x0 = 0: h1 = 0, h2 = 4 -> (2.25, 3); x0 = 1: h1 = 1, h2 = 1 -> (0.75, 0); x0 = 3: h1 = 5, h2 = 0 -> b3
+    assert np.allclose(out, [[2.25, 3.0], [0.75, 0.0], [0.25, -1.0]], atol=0, rtol=0)
+
+
+def test_bf16_rounding_and_adam_first_step():
+    from oracle import mlp
+    x = np.array([1.0, 1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, -2.5, 3.0e38, 1e-40], dtype=np.float32)
+    assert mlp.bf16(x)[:4].tolist() == [1.0, 1.0, 1 + 2.0 ** -6, -2.5]
+    # Adam's first step moves each parameter by lr * g / (|g| + eps)
+    g = np.array([0.3, -2.0, 1e-3])
+    p1, m, v = mlp.adam(np.zeros(3), g, np.zeros(3), np.zeros(3), 1, lr=0.01)
+    assert np.allclose(p1, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12)
