@@ -98,8 +98,10 @@ enum {
                               SLW_START_PREV call on this mesh (steered when there is none) */
     SLW_START_FIXED = 3,   /* every walk starts at user triangle start[0] (the paper's
                               fixed-start baseline, Section 2.2 complexity) */
-    SLW_START_LEARNED = 4  /* the triangle proposed by the network attached with
+    SLW_START_LEARNED = 4, /* the triangle proposed by the network attached with
                               slw_mesh_attach_mlp (learned start; see below) */
+    SLW_START_CHART = 5    /* the start-table triangle of the foot's own chart cell
+                              (exact chart lookup, no network; needs slw_chart_build) */
 };
 /* slw_mesh_upload flags */
 #define SLW_COORDS_F32 0x1u     /* store coordinates as float (FP32 walk, FP64/exact fallback) */
@@ -265,7 +267,8 @@ slw_status slw_batch_autotune(slw_batch *b, int scheme, const char *cache_path, 
 /* ------------------------------------------------------------------------
  * Learned start proposal.  A network (x, y, dx, dy, t) -> 64 -> 64 -> 2 with
  * ReLU maps a foot (node x, y; displacement dx, dy to the foot; time t =
- * t_{n+1}) to chart coordinates (u, v) of the mesh; a G x G table maps
+ * t_{n+1}) to its displacement (du, dv) in a chart of the mesh; the node's
+ * own chart coordinates plus (du, dv) give (u, v), a G x G table maps
  * (floor(u G), floor(v G)) to a start triangle, and the exact walk finishes
  * the search.  This follows the hybrid idea that closes the numerical
  * section (Section 4) of the paper: the start comes from local information
@@ -274,6 +277,9 @@ slw_status slw_batch_autotune(slw_batch *b, int scheme, const char *cache_path, 
  * steps).  The chart is the Rosenblatt transform of the triangle-centroid
  * distribution: u = rank of the centroid's x among all centroids (in (0,1)),
  * v = rank of its y among the centroids of its u slab (slab = floor(u G)).
+ * SLW_START_CHART finds the foot's chart cell exactly instead (binary
+ * searches in the slabs' x and y quantiles): the same start without the
+ * network, kept as the reference point for the learned one.
  *
  * Parameters: one float vector of 4674 numbers, W1 (5 x 64, input-major:
  * W1[i][j] at i * 64 + j), b1 (64), W2 (64 x 64), b2 (64), W3 (64 x 2), b3
@@ -282,12 +288,12 @@ slw_status slw_batch_autotune(slw_batch *b, int scheme, const char *cache_path, 
  * (own forward/backward kernels, Adam); inference uses bfloat16 operands
  * (round to nearest even) on the matrix cores with FP32 accumulation.
  * Sample arrays: X (device, m x 5 floats: x, y, dx, dy, t), Y (device, m x 2
- * floats: target u, v; a negative u marks a sample without target, which
+ * floats: target du, dv; a NaN du marks a sample without target, which
  * counts in the batch size but not in the loss). */
 
 /* Builds (or rebuilds) the chart of a mesh with a g x g start table
  * (1 <= g <= 8192), on the host from the device records; synchronous.
- * Device memory: 8 B per triangle + 4 g^2 B. */
+ * Device memory: 8 B per triangle, 12 B per DOF, 8 g^2 + 4 g B. */
 slw_status slw_chart_build(slw_mesh *mesh, int g);
 /* Chart coordinates of every triangle's centroid, user triangle order:
  * uv_h[2 t], uv_h[2 t + 1] (host, n_tris x 2); synchronous. */
@@ -309,8 +315,9 @@ slw_status slw_mlp_fit_normalization(slw_mlp *n, const float *X, int64_t m);
 /* Training samples from the plain walk: for the DOFs dofs[i] (device, m
  * ints, internal positions 0 .. n_dofs-1) the foot of the step ending at
  * t_np1 is computed and located with the strategy (a) start; X[i] gets the
- * foot's inputs, Y[i] the chart coordinates of the element found ((-1, -1)
- * when outside; out-of-range ids give zeros and (-1, -1)).  Needs a chart. */
+ * foot's inputs, Y[i] the chart coordinates of the element found minus
+ * those of the DOF (NaN when outside; out-of-range ids give zeros and NaN).
+ * Needs a chart. */
 slw_status slw_learned_gather(slw_mesh *mesh, const slw_field *field, double t_np1, double dt, int scheme,
                               const int32_t *dofs, int64_t m, float *X, float *Y);
 /* Gradient of the loss = mean over the m samples of |out - Y|^2 (FP32,

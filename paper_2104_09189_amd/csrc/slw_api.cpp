@@ -306,22 +306,24 @@ slw_status slw_locate_feet(slw_mesh *mesh, const slw_field *field, double t_np1,
         return set_error(SLW_E_ARG, "feet (SLW_FEET_IN) or a valid field is required");
     if (scheme != SLW_EULER && scheme != SLW_RK2)
         return set_error(SLW_E_ARG, "unknown scheme");
-    if (start_mode < SLW_START_STEERED || start_mode > SLW_START_LEARNED)
+    if (start_mode < SLW_START_STEERED || start_mode > SLW_START_CHART)
         return set_error(SLW_E_ARG, "unknown start mode");
     if ((start_mode == SLW_START_GIVEN || start_mode == SLW_START_FIXED) && !start)
         return set_error(SLW_E_ARG, "start array required for this start mode");
-    if (start_mode == SLW_START_LEARNED && (!mesh->m.mlp || !mesh->m.learned_start))
+    if (start_mode == SLW_START_LEARNED && !mesh->m.mlp)
         return set_error(SLW_E_ARG, "SLW_START_LEARNED needs a network attached (slw_mesh_attach_mlp)");
+    if (start_mode == SLW_START_CHART && !mesh->m.chart_table)
+        return set_error(SLW_E_ARG, "SLW_START_CHART needs a chart (slw_chart_build)");
     slw_ctx *ctx = mesh->ctx;
     DeviceGuard g(ctx->device);
     slw_status st = begin_stats(ctx, stats_h);
     if (st != SLW_OK)
         return st;
     FieldDev fd = to_dev(field);
-    if (start_mode == SLW_START_LEARNED) {
-        st = hip_check(launch_learned_start(mesh->m, ctx->stream, fd, t_np1, dt, scheme, feet_in ? feet : nullptr,
-                                            mesh->m.n_dofs, mesh->m.learned_start),
-                       "learned start");
+    if (start_mode == SLW_START_LEARNED || start_mode == SLW_START_CHART) {
+        st = hip_check(launch_chart_start(mesh->m, ctx->stream, fd, t_np1, dt, scheme, feet_in ? feet : nullptr,
+                                          mesh->m.n_dofs, start_mode == SLW_START_LEARNED, mesh->m.learned_start),
+                       "chart start");
         if (st != SLW_OK)
             return st;
         start = mesh->m.learned_start;
@@ -366,12 +368,14 @@ slw_status slw_step(slw_mesh *mesh, const slw_field *field, double t_n, double d
         return set_error(SLW_E_ARG, "unknown scheme");
     if (vdtype != SLW_F64 && vdtype != SLW_F32)
         return set_error(SLW_E_ARG, "unknown vdtype");
-    if (start_mode < SLW_START_STEERED || start_mode > SLW_START_LEARNED)
+    if (start_mode < SLW_START_STEERED || start_mode > SLW_START_CHART)
         return set_error(SLW_E_ARG, "unknown start mode");
     if ((start_mode == SLW_START_GIVEN || start_mode == SLW_START_FIXED) && !start)
         return set_error(SLW_E_ARG, "start array required for this start mode");
-    if (start_mode == SLW_START_LEARNED && (!mesh->m.mlp || !mesh->m.learned_start))
+    if (start_mode == SLW_START_LEARNED && !mesh->m.mlp)
         return set_error(SLW_E_ARG, "SLW_START_LEARNED needs a network attached (slw_mesh_attach_mlp)");
+    if (start_mode == SLW_START_CHART && !mesh->m.chart_table)
+        return set_error(SLW_E_ARG, "SLW_START_CHART needs a chart (slw_chart_build)");
     const DevMesh &m = mesh->m;
     // P1 uses the vertex DOFs only (the first n_nodes of either order)
     const int64_t rows = order == 1 ? m.n_nodes : m.n_dofs;
@@ -400,9 +404,10 @@ slw_status slw_step(slw_mesh *mesh, const slw_field *field, double t_n, double d
     }
     const bool write_prev = start_mode == SLW_START_PREV;
     FieldDev fd = to_dev(field);
-    if (start_mode == SLW_START_LEARNED) {
-        st = hip_check(launch_learned_start(m, ctx->stream, fd, t_n + dt, dt, scheme, nullptr, rows, m.learned_start),
-                       "learned start");
+    if (start_mode == SLW_START_LEARNED || start_mode == SLW_START_CHART) {
+        st = hip_check(launch_chart_start(m, ctx->stream, fd, t_n + dt, dt, scheme, nullptr, rows,
+                                          start_mode == SLW_START_LEARNED, m.learned_start),
+                       "chart start");
         if (st != SLW_OK)
             return st;
         start = m.learned_start;

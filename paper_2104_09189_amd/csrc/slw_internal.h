@@ -50,10 +50,14 @@ struct DevMesh {
     int32_t *prev_elem = nullptr; // [n_dofs] internal tri of the last location (strategy b)
     int32_t *jump = nullptr;      // [jump_g * jump_g] bucket grid of start triangles (internal)
     int jump_g = 1;
-    // learned start proposal: chart coordinates of triangle centroids, the
-    // chart's start table, the attached network and a start workspace
+    // chart starts (learned and exact): chart coordinates of triangle
+    // centroids and of DOFs, the start table, the quantile tables that give
+    // a point's chart cell, the attached network and a start workspace
     float2 *chart_uv = nullptr;       // [n_tris]
+    float2 *chart_node = nullptr;     // [n_dofs]
     int32_t *chart_table = nullptr;   // [chart_g * chart_g] internal triangle ids
+    float *chart_qx = nullptr;        // [chart_g] smallest centroid x of each u slab
+    float *chart_qy = nullptr;        // [chart_g * chart_g] smallest centroid y of each cell of a slab
     int chart_g = 0;
     int32_t *learned_start = nullptr; // [n_dofs]
     struct slw_mlp *mlp = nullptr;    // borrowed
@@ -186,9 +190,10 @@ hipError_t launch_step(const DevMesh &m, hipStream_t st, const FieldDev &f, doub
                        int order, int start_mode, const int32_t *start, const void *v_in, int vdtype, int k,
                        void *v_out, double outside, bool write_prev, const int32_t *out_map, DevStats *stats);
 hipError_t launch_zero_stats(hipStream_t st, DevStats *p);
-// learned start proposal (the mesh needs a chart and an attached network)
-hipError_t launch_learned_start(const DevMesh &m, hipStream_t st, const FieldDev &f, double t_np1, double dt,
-                                int scheme, const void *feet_in, int64_t n_iter, int32_t *start);
+// chart starts (the mesh needs a chart; use_net: the attached network, else
+// the exact chart cell of the foot)
+hipError_t launch_chart_start(const DevMesh &m, hipStream_t st, const FieldDev &f, double t_np1, double dt,
+                              int scheme, const void *feet_in, int64_t n_iter, bool use_net, int32_t *start);
 hipError_t launch_learned_gather(const DevMesh &m, hipStream_t st, const FieldDev &f, double t_np1, double dt,
                                  int scheme, const int32_t *dofs, int64_t cnt, float *X, float *Y);
 

@@ -156,7 +156,7 @@ __device__ inline int32_t start_for(const MeshView &mv, int64_t d, int64_t api, 
         if (pe >= 0)
             return pe;
     }
-    if (mode == SLW_START_LEARNED) {  // internal ids proposed by the network
+    if (mode == SLW_START_LEARNED || mode == SLW_START_CHART) {  // internal ids from the chart
         const int32_t j = start[d];
         if (j >= 0 && j < mv.n_tris)
             return j;
@@ -888,33 +888,51 @@ __global__ void k_permute_rows(const uint32_t *__restrict__ src, uint32_t *__res
 // learned start proposal: the network maps a foot to chart coordinates and
 // the chart table to a start triangle; the walk above finishes the search
 
-// raw network inputs of a foot: node position, displacement to the foot, time
+// raw network inputs of a foot: the node's position (in chart coordinates),
+// its displacement to the foot, time
 template <typename R>
-__device__ inline void raw_features(R x, R y, R qx, R qy, double t, float f[5])
+__device__ inline void raw_features(float2 node_uv, R x, R y, R qx, R qy, double t, float f[5])
 {
-    f[0] = (float)x;
-    f[1] = (float)y;
+    f[0] = node_uv.x;
+    f[1] = node_uv.y;
     f[2] = (float)(qx - x);
     f[3] = (float)(qy - y);
     f[4] = (float)t;
 }
 
-// start[d] for the DOFs [0, n_iter) (internal order); feet either computed
-// from the field or read from feet_in (indexed like slw_locate_feet's feet)
-template <bool F32>
+// largest i in [0, n) with tab[i] <= x (0 when there is none; tab sorted);
+// the trip count depends on n only
+__device__ inline int upper_index(const float *__restrict__ tab, int n, float x)
+{
+    int lo = 0;
+    while (n > 1) {
+        const int half = n >> 1;
+        lo = tab[lo + half] <= x ? lo + half : lo;
+        n -= half;
+    }
+    return lo;
+}
+
+// start[d] for the DOFs [0, n_iter) (internal order) from the chart: NET,
+// the table cell of chart(node) + network output; else the cell that holds
+// the foot (quantile tables); then whichever of that proposal and the
+// node's steered start lies nearer the foot.  Feet are computed from the
+// field or read from feet_in (indexed like slw_locate_feet's feet).
+template <bool F32, bool NET>
 __global__ void __launch_bounds__(kBlock)
-    k_learned_start(MeshView mv, FieldDev f, double dt, double t_np1, int scheme,
-                    const typename CT<F32>::R2 *__restrict__ feet_in, const uint16_t *__restrict__ wpack,
-                    const float *__restrict__ bias, const float *__restrict__ norm,
-                    const int32_t *__restrict__ table, int g, int64_t n_iter, int32_t *__restrict__ start)
+    k_chart_start(MeshView mv, FieldDev f, double dt, double t_np1, int scheme,
+                  const typename CT<F32>::R2 *__restrict__ feet_in, const uint16_t *__restrict__ wpack,
+                  const float *__restrict__ bias, const float *__restrict__ norm, const float2 *__restrict__ node,
+                  const float *__restrict__ qx_tab, const float *__restrict__ qy_tab,
+                  const int32_t *__restrict__ table, int g, int64_t n_iter, int32_t *__restrict__ start)
 {
     using R = typename CT<F32>::R;
     using R2 = typename CT<F32>::R2;
     const int64_t d = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     float feat[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    R qx = 0, qy = 0;
     if (d < n_iter) {
         const R2 x = ((const R2 *)mv.dof_xy)[d];
-        R qx, qy;
         if (feet_in) {
             const int64_t api = mv.internal_order ? d : mv.dof_user[d];
             qx = feet_in[api].x;
@@ -922,21 +940,50 @@ __global__ void __launch_bounds__(kBlock)
         } else {
             foot_of<R>(f, scheme, x.x, x.y, (R)dt, qx, qy);
         }
-        raw_features<R>(x.x, x.y, qx, qy, t_np1, feat);
-        mlp_normalise(norm, feat);
+        if (NET) {
+            raw_features<R>(node[d], x.x, x.y, qx, qy, t_np1, feat);
+            mlp_normalise(norm, feat);
+        }
     }
-    const float2 uv = mlp_forward_wave(wpack, bias, feat);  // every lane
-    if (d < n_iter)
-        start[d] = chart_lookup(table, g, uv);
+    int32_t j = -1;
+    if (NET) {
+        const float2 duv = mlp_forward_wave(wpack, bias, feat);  // every lane
+        if (d < n_iter) {
+            const float2 c = node[d];
+            j = chart_lookup(table, g, make_float2(c.x + duv.x, c.y + duv.y));
+        }
+    }
+    if (d >= n_iter)
+        return;
+    // the foot in the records' float frame, as the chart was built
+    const float fx = F32 ? (float)qx : (float)((double)qx - mv.fc.cx);
+    const float fy = F32 ? (float)qy : (float)((double)qy - mv.fc.cy);
+    if (!NET) {
+        const int bu = upper_index(qx_tab, g, fx);
+        const int bv = upper_index(qy_tab + (int64_t)bu * g, g, fy);
+        j = table[(int64_t)bu * g + bv];
+    }
+    // Per-foot choice between the proposal and the node's own steered start
+    // (strategy (a)): the triangle whose centroid is nearer the foot.
+    const R2 x = ((const R2 *)mv.dof_xy)[d];
+    const int32_t js = quadrant_start(mv.qstart[d], (float)(qx - x.x), (float)(qy - x.y));
+    const GeoRec rs = mv.geo[js], rp = mv.geo[j];
+    const float sx = (rs.p[0].x + rs.p[1].x + rs.p[2].x) * (1.f / 3.f) - fx;
+    const float sy = (rs.p[0].y + rs.p[1].y + rs.p[2].y) * (1.f / 3.f) - fy;
+    const float px = (rp.p[0].x + rp.p[1].x + rp.p[2].x) * (1.f / 3.f) - fx;
+    const float py = (rp.p[0].y + rp.p[1].y + rp.p[2].y) * (1.f / 3.f) - fy;
+    start[d] = px * px + py * py < sx * sx + sy * sy ? j : js;
 }
 
 // Training pairs: for the DOFs dofs[i] (internal positions) the plain walk
 // (strategy (a) start) locates the foot; X[i] = raw features, Y[i] = chart
-// coordinates of the element found, (-1, -1) when the foot is outside.
+// coordinates of the element found minus those of the DOF, NaN when the foot
+// is outside.
 template <bool F32>
 __global__ void __launch_bounds__(kBlock)
     k_gather(MeshView mv, FieldDev f, double dt, double t_np1, int scheme, const int32_t *__restrict__ dofs,
-             int64_t m, const float2 *__restrict__ chart_uv, float *__restrict__ X, float2 *__restrict__ Y)
+             int64_t m, const float2 *__restrict__ chart_uv, const float2 *__restrict__ node, float *__restrict__ X,
+             float2 *__restrict__ Y)
 {
     using R = typename CT<F32>::R;
     using R2 = typename CT<F32>::R2;
@@ -947,7 +994,7 @@ __global__ void __launch_bounds__(kBlock)
     if (d < 0 || d >= mv.n_dofs) {
         for (int c = 0; c < 5; ++c)
             X[5 * i + c] = 0.f;
-        Y[i] = make_float2(-1.f, -1.f);
+        Y[i] = make_float2(NAN, NAN);
         return;
     }
     const R2 x = ((const R2 *)mv.dof_xy)[d];
@@ -960,10 +1007,15 @@ __global__ void __launch_bounds__(kBlock)
         e = walk<F32>(mv, j0, qx, qy, (uint32_t)d * 2654435761u, c).elem;
     }
     float feat[5];
-    raw_features<R>(x.x, x.y, qx, qy, t_np1, feat);
+    raw_features<R>(node[d], x.x, x.y, qx, qy, t_np1, feat);
     for (int c = 0; c < 5; ++c)
         X[5 * i + c] = feat[c];
-    Y[i] = e >= 0 ? chart_uv[e] : make_float2(-1.f, -1.f);
+    if (e >= 0) {
+        const float2 c = chart_uv[e], o = node[d];
+        Y[i] = make_float2(c.x - o.x, c.y - o.y);
+    } else {
+        Y[i] = make_float2(NAN, NAN);
+    }
 }
 
 __global__ void k_zero_u64(unsigned long long *p, int n)
@@ -1156,26 +1208,32 @@ hipError_t launch_permute_rows(hipStream_t st, const void *src, void *dst, int64
     return hipGetLastError();
 }
 
-hipError_t launch_learned_start(const DevMesh &m, hipStream_t st, const FieldDev &f0, double t_np1, double dt,
-                                int scheme, const void *feet_in, int64_t n_iter, int32_t *start)
+hipError_t launch_chart_start(const DevMesh &m, hipStream_t st, const FieldDev &f0, double t_np1, double dt,
+                              int scheme, const void *feet_in, int64_t n_iter, bool use_net, int32_t *start)
 {
+    if (n_iter <= 0)
+        return hipSuccess;
     const slw_mlp *n = m.mlp;
-    if (!n || !m.chart_table || n_iter <= 0)
-        return n_iter <= 0 ? hipSuccess : hipErrorInvalidValue;
+    if (!m.chart_table || (use_net && !n))
+        return hipErrorInvalidValue;
     unsigned g;
     if (!tiles_for(n_iter, g))
         return hipErrorInvalidValue;
     MeshView mv = view_of(m);
     FieldDev f = f0;
     field_time_factors(f, t_np1, dt);
-    if (m.coords_f32)
-        hipLaunchKernelGGL(k_learned_start<true>, dim3(g), dim3(kBlock), 0, st, mv, f, dt, t_np1, scheme,
-                           (const float2 *)feet_in, n->wpack, n->bias, n->norm, m.chart_table, m.chart_g, n_iter,
-                           start);
-    else
-        hipLaunchKernelGGL(k_learned_start<false>, dim3(g), dim3(kBlock), 0, st, mv, f, dt, t_np1, scheme,
-                           (const double2 *)feet_in, n->wpack, n->bias, n->norm, m.chart_table, m.chart_g, n_iter,
-                           start);
+    const uint16_t *wp = n ? n->wpack : nullptr;
+    const float *bi = n ? n->bias : nullptr, *no = n ? n->norm : nullptr;
+#define SLW_CSTART(F32, NET, R2)                                                                                  \
+    hipLaunchKernelGGL((k_chart_start<F32, NET>), dim3(g), dim3(kBlock), 0, st, mv, f, dt, t_np1, scheme,        \
+                       (const R2 *)feet_in, wp, bi, no, m.chart_node, m.chart_qx, m.chart_qy, m.chart_table,     \
+                       m.chart_g, n_iter, start)
+    if (m.coords_f32) {
+        if (use_net) SLW_CSTART(true, true, float2); else SLW_CSTART(true, false, float2);
+    } else {
+        if (use_net) SLW_CSTART(false, true, double2); else SLW_CSTART(false, false, double2);
+    }
+#undef SLW_CSTART
     return hipGetLastError();
 }
 
@@ -1192,10 +1250,10 @@ hipError_t launch_learned_gather(const DevMesh &m, hipStream_t st, const FieldDe
     field_time_factors(f, t_np1, dt);
     if (m.coords_f32)
         hipLaunchKernelGGL(k_gather<true>, dim3(g), dim3(kBlock), 0, st, mv, f, dt, t_np1, scheme, dofs, cnt,
-                           m.chart_uv, X, (float2 *)Y);
+                           m.chart_uv, m.chart_node, X, (float2 *)Y);
     else
         hipLaunchKernelGGL(k_gather<false>, dim3(g), dim3(kBlock), 0, st, mv, f, dt, t_np1, scheme, dofs, cnt,
-                           m.chart_uv, X, (float2 *)Y);
+                           m.chart_uv, m.chart_node, X, (float2 *)Y);
     return hipGetLastError();
 }
 

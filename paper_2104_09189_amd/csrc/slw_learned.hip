@@ -13,7 +13,11 @@
 // centroid is nearest the cell centre (empty cells: the nearest filled cell).
 //
 // Network: (x, y, dx, dy, t) -> 64 -> 64 -> 2 with ReLU, regressing the chart
-// coordinates of the element that contains the foot (dx, dy = foot - node).
+// displacement from the node to the element that contains its foot (dx, dy =
+// foot - node): the proposal is chart(node) + output, so the network never
+// has to rebuild the chart itself, only how far the foot moves in it.
+// The exact chart cell of a foot (two binary searches in quantile tables,
+// no network) is the non-learned form of the same start.
 // Training: FP32 forward and backward kernels, per-workgroup partial
 // gradients summed in a fixed order (bit-reproducible), Adam.  Inference:
 // bfloat16 operands on the matrix cores, FP32 accumulation (slw_mlp.h).
@@ -48,7 +52,7 @@ __device__ inline int64_t perm_index(int64_t i, int64_t m, uint64_t a, uint64_t 
 // activations and deltas staged in LDS, then each lane accumulates the
 // gradient entries it owns over the 64 samples (dW1[.][t], db1[t], dW2[.][t],
 // db2[t], two entries of dW3, db3[t] for t < 2).  Samples whose target is
-// negative (foot outside) count in the batch size but carry no error.
+// NaN (foot outside) count in the batch size but carry no error.
 __global__ void __launch_bounds__(64)
     k_mlp_partial(const float *__restrict__ P, const float *__restrict__ norm, const float *__restrict__ X,
                   const float2 *__restrict__ Y, int64_t m, int64_t first, int64_t count, uint64_t pa, uint64_t pc,
@@ -76,7 +80,7 @@ __global__ void __launch_bounds__(64)
                 x[c] = X[5 * s + c];
             mlp_normalise(norm, x);
             const float2 yy = Y[s];
-            if (yy.x >= 0.f) {
+            if (yy.x == yy.x) {  // NaN: no target
                 y0 = yy.x;
                 y1 = yy.y;
                 w = 1.f;
@@ -353,37 +357,71 @@ slw_status slw_chart_build(slw_mesh *mesh, int g)
         return set_error(SLW_E_ARG, "slw_chart_build: null mesh or g outside [1, 8192]");
     DevMesh &m = mesh->m;
     DeviceGuard gd(mesh->ctx->device);
-    const int64_t nt = m.n_tris;
+    const int64_t nt = m.n_tris, nd = m.n_dofs;
     std::vector<GeoRec> geo(nt);
     slw_status st = hip_check(hipStreamSynchronize(mesh->ctx->stream), "hipStreamSynchronize");
     if (st == SLW_OK)
         st = hip_check(hipMemcpy(geo.data(), m.geo, nt * sizeof(GeoRec), hipMemcpyDeviceToHost), "copy records");
     if (st != SLW_OK)
         return st;
-    // centroids from the records (shifted float coordinates: ranks are unaffected)
-    std::vector<double> cx(nt), cy(nt);
+    // Everything in the records' float frame (coordinates minus the centre
+    // used at upload): centroids, DOF positions, and the feet of the lookup.
+    std::vector<float> cx(nt), cy(nt);
     for (int64_t t = 0; t < nt; ++t) {
-        cx[t] = ((double)geo[t].p[0].x + geo[t].p[1].x + geo[t].p[2].x) / 3.0;
-        cy[t] = ((double)geo[t].p[0].y + geo[t].p[1].y + geo[t].p[2].y) / 3.0;
+        cx[t] = (float)(((double)geo[t].p[0].x + geo[t].p[1].x + geo[t].p[2].x) / 3.0);
+        cy[t] = (float)(((double)geo[t].p[0].y + geo[t].p[1].y + geo[t].p[2].y) / 3.0);
     }
+    // u: rank of the centroid's x; slab = floor(u g); v: rank of y in the slab
     std::vector<int32_t> ord(nt);
     std::iota(ord.begin(), ord.end(), 0);
     std::sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return cx[a] != cx[b] ? cx[a] < cx[b] : a < b; });
     std::vector<float2> uv(nt);
     std::vector<std::vector<int32_t>> slab(g);
+    std::vector<float> qx(g, INFINITY);  // smallest centroid x of each slab
     for (int64_t r = 0; r < nt; ++r) {
         const double u = ((double)r + 0.5) / (double)nt;
+        const int s = (int)std::min<int64_t>(g - 1, (int64_t)(u * g));
         uv[ord[r]].x = (float)u;
-        slab[std::min<int64_t>(g - 1, (int64_t)(u * g))].push_back(ord[r]);
+        if (slab[s].empty())
+            qx[s] = cx[ord[r]];
+        slab[s].push_back(ord[r]);
     }
+    std::vector<float> qy((size_t)g * g, INFINITY);  // smallest centroid y of each cell of a slab
+    std::vector<std::vector<float>> ys(g);           // sorted centroid y of each slab
     for (int s = 0; s < g; ++s) {
         auto &v = slab[s];
         std::sort(v.begin(), v.end(), [&](int32_t a, int32_t b) { return cy[a] != cy[b] ? cy[a] < cy[b] : a < b; });
-        for (size_t r = 0; r < v.size(); ++r)
-            uv[v[r]].y = (float)(((double)r + 0.5) / (double)v.size());
+        ys[s].resize(v.size());
+        for (size_t r = 0; r < v.size(); ++r) {
+            const double vv = ((double)r + 0.5) / (double)v.size();
+            const int j = (int)std::min<int64_t>(g - 1, (int64_t)(vv * g));
+            uv[v[r]].y = (float)vv;
+            ys[s][r] = cy[v[r]];
+            float &q = qy[(size_t)s * g + j];
+            q = std::min(q, cy[v[r]]);
+        }
+    }
+    // empty slabs / cells take the next threshold, so the tables stay sorted
+    for (int s = g - 2; s >= 0; --s)
+        qx[s] = std::min(qx[s], qx[s + 1]);
+    for (int s = 0; s < g; ++s)
+        for (int j = g - 2; j >= 0; --j)
+            qy[(size_t)s * g + j] = std::min(qy[(size_t)s * g + j], qy[(size_t)s * g + j + 1]);
+    // chart coordinates of the DOFs: the same ranks for their positions
+    std::vector<float> sx(nt);
+    for (int64_t r = 0; r < nt; ++r)
+        sx[r] = cx[ord[r]];
+    std::vector<float2> node(std::max<int64_t>(nd, 1));
+    for (int64_t d = 0; d < nd; ++d) {
+        const int64_t du = m.dof_user_h[d];
+        const float px = (float)(m.dof_xy_user_h[2 * du] - m.fc.cx), py = (float)(m.dof_xy_user_h[2 * du + 1] - m.fc.cy);
+        const double u = (double)(std::lower_bound(sx.begin(), sx.end(), px) - sx.begin()) / (double)nt;
+        const int s = (int)std::min<int64_t>(g - 1, (int64_t)(u * g));
+        const auto &y = ys[s];
+        const double v = y.empty() ? 0.5 : (double)(std::lower_bound(y.begin(), y.end(), py) - y.begin()) / y.size();
+        node[d] = make_float2((float)u, (float)v);
     }
     // cell -> triangle whose chart centroid is nearest the cell centre
-    // (the cell index computed as the device lookup computes it)
     std::vector<int32_t> table((size_t)g * g, -1);
     std::vector<float> best((size_t)g * g, INFINITY);
     for (int64_t t = 0; t < nt; ++t) {
@@ -417,31 +455,51 @@ slw_status slw_chart_build(slw_mesh *mesh, int g)
             }
         }
     }
-    float2 *uv_d = nullptr;
-    int32_t *tab_d = nullptr;
-    if (hipMalloc((void **)&uv_d, std::max<int64_t>(nt, 1) * sizeof(float2)) != hipSuccess ||
-        hipMalloc((void **)&tab_d, table.size() * sizeof(int32_t)) != hipSuccess) {
-        if (uv_d)
-            (void)hipFree(uv_d);
-        return set_error(SLW_E_NOMEM, "chart arrays");
+    // device copies (the old chart is replaced only when all succeeded)
+    const size_t gg = (size_t)g * g;
+    float2 *uv_d = nullptr, *node_d = nullptr;
+    int32_t *tab_d = nullptr, *start_d = nullptr;
+    float *qx_d = nullptr, *qy_d = nullptr;
+    bool ok = hipMalloc((void **)&uv_d, std::max<int64_t>(nt, 1) * sizeof(float2)) == hipSuccess &&
+              hipMalloc((void **)&node_d, node.size() * sizeof(float2)) == hipSuccess &&
+              hipMalloc((void **)&tab_d, gg * sizeof(int32_t)) == hipSuccess &&
+              hipMalloc((void **)&qx_d, g * sizeof(float)) == hipSuccess &&
+              hipMalloc((void **)&qy_d, gg * sizeof(float)) == hipSuccess &&
+              (m.learned_start ||
+               hipMalloc((void **)&start_d, std::max<int64_t>(nd, 1) * sizeof(int32_t)) == hipSuccess);
+    if (ok) {
+        ok = hipMemcpy(uv_d, uv.data(), nt * sizeof(float2), hipMemcpyHostToDevice) == hipSuccess &&
+             hipMemcpy(node_d, node.data(), node.size() * sizeof(float2), hipMemcpyHostToDevice) == hipSuccess &&
+             hipMemcpy(tab_d, table.data(), gg * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
+             hipMemcpy(qx_d, qx.data(), g * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
+             hipMemcpy(qy_d, qy.data(), gg * sizeof(float), hipMemcpyHostToDevice) == hipSuccess;
+        if (!ok)
+            st = set_error(SLW_E_HIP, "slw_chart_build: copy to the device");
+    } else {
+        st = set_error(SLW_E_NOMEM, "slw_chart_build: chart arrays");
     }
-    st = hip_check(hipMemcpy(uv_d, uv.data(), nt * sizeof(float2), hipMemcpyHostToDevice), "copy chart");
-    if (st == SLW_OK)
-        st = hip_check(hipMemcpy(tab_d, table.data(), table.size() * sizeof(int32_t), hipMemcpyHostToDevice),
-                       "copy table");
-    if (st != SLW_OK) {
-        (void)hipFree(uv_d);
-        (void)hipFree(tab_d);
+    if (!ok) {
+        void *p[] = {uv_d, node_d, tab_d, qx_d, qy_d, start_d};
+        for (void *q : p)
+            if (q)
+                (void)hipFree(q);
         return st;
     }
-    if (m.chart_uv)
-        (void)hipFree(m.chart_uv);
-    if (m.chart_table)
-        (void)hipFree(m.chart_table);
-    m.device_bytes += (m.chart_uv ? 0 : nt * (int64_t)sizeof(float2)) +
-                      ((int64_t)table.size() - (int64_t)m.chart_g * m.chart_g) * (int64_t)sizeof(int32_t);
+    void *old[] = {m.chart_uv, m.chart_node, m.chart_table, m.chart_qx, m.chart_qy};
+    for (void *q : old)
+        if (q)
+            (void)hipFree(q);
+    const int64_t old_bytes = m.chart_g ? nt * 8 + nd * 8 + (int64_t)m.chart_g * (8 * m.chart_g + 4) : 0;
+    m.device_bytes += nt * 8 + nd * 8 + (int64_t)g * (8 * g + 4) - old_bytes;
+    if (start_d) {
+        m.learned_start = start_d;
+        m.device_bytes += std::max<int64_t>(nd, 1) * 4;
+    }
     m.chart_uv = uv_d;
+    m.chart_node = node_d;
     m.chart_table = tab_d;
+    m.chart_qx = qx_d;
+    m.chart_qy = qy_d;
     m.chart_g = g;
     return SLW_OK;
 }
@@ -687,14 +745,7 @@ slw_status slw_mesh_attach_mlp(slw_mesh *mesh, slw_mlp *n)
         return set_error(SLW_E_ARG, "slw_mesh_attach_mlp: network from another context");
     if (n && !mesh->m.chart_table)
         return set_error(SLW_E_ARG, "slw_mesh_attach_mlp: no chart (slw_chart_build)");
-    DeviceGuard gd(mesh->ctx->device);
-    if (n && !mesh->m.learned_start) {
-        const int64_t bytes = std::max<int64_t>(mesh->m.n_dofs, 1) * (int64_t)sizeof(int32_t);
-        if (hipMalloc((void **)&mesh->m.learned_start, bytes) != hipSuccess)
-            return set_error(SLW_E_NOMEM, "learned start workspace");
-        mesh->m.device_bytes += bytes;
-    }
-    mesh->m.mlp = n;
+    mesh->m.mlp = n;  // the chart allocated the start workspace
     return SLW_OK;
 }
 

@@ -133,7 +133,8 @@ FilterConst filter_constants(bool f32, double cx, double cy, double cmax)
 void free_mesh(DevMesh &m)
 {
     void *ptrs[] = {m.geo, m.tri_uf, m.tedge, m.dof_xy, m.qstart, m.vmin, m.dof_user,
-                    m.dof_int, m.tri_int, m.prev_elem, m.jump, m.chart_uv, m.chart_table, m.learned_start};
+                    m.dof_int, m.tri_int, m.prev_elem, m.jump, m.chart_uv, m.chart_node, m.chart_table,
+                    m.chart_qx, m.chart_qy, m.learned_start};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);

@@ -67,9 +67,9 @@ def test_gradient_ignores_samples_without_target(S, C):
     p = mlp.he_uniform(12)
     net.set_params(p)
     X, Y = _samples(3000, 77)
-    Y[::3] = -1.0                                   # feet outside: no target
+    Y[::3] = np.nan                                 # feet outside: no target
     g, loss = net.grad(dev(X), dev(Y))
-    keep = Y[:, 0] >= 0
+    keep = ~np.isnan(Y[:, 0])
     Xk, Yk = X[keep].astype(np.float64), Y[keep].astype(np.float64)
     # mean over all 3000 samples of the error of the kept ones
     g_ref = mlp.grad(p.astype(np.float64), Xk, Yk) * keep.sum() / 3000.0
@@ -134,6 +134,18 @@ def _swirl_case(n=120, alpha=20.0, seed=901):
     return xy, tri, I.swirl(10.0), alpha * h   # slowly varying: walks of about alpha / 2 steps
 
 
+def test_chart_of_a_regular_grid(S, C):
+    """On an unjittered grid the chart is (up to the rank offsets) the
+    identity, and the DOFs' chart coordinates are their own ranks."""
+    xy, tri = I.jittered_grid(17, 1, jitter=0.0)
+    mesh = S.Mesh(C, xy, tri)
+    mesh.chart_build(16)
+    uv = mesh.chart_coords()
+    c = xy[tri].mean(axis=1)
+    assert np.abs(uv[:, 0] - c[:, 0]).max() < 0.04
+    assert np.abs(uv[:, 1] - c[:, 1]).max() < 0.04
+
+
 def test_chart_is_a_rank_transform(S, C):
     xy, tri = I.permute_mesh(*I.jittered_grid(60, 31), 8)
     mesh = S.Mesh(C, xy, tri)
@@ -174,7 +186,7 @@ def test_learned_start_finds_the_oracles_elements(S, C, orc, flags):
     for s in range(4):
         sl = slice(s * mesh.n_dofs, (s + 1) * mesh.n_dofs)
         mesh.learned_gather(fld, (s + 1) * dt, dt, S.SLW_RK2, ids, X[sl], Y[sl])
-    assert (host(Y)[:, 0] >= 0).mean() > 0.9
+    assert (~np.isnan(host(Y)[:, 0])).mean() > 0.9
     net.fit_normalization(X)
     net.train(X, Y, epochs=40, batch=256, lr=3e-3, seed=3)
     mesh.attach_mlp(net)
@@ -188,8 +200,13 @@ def test_learned_start_finds_the_oracles_elements(S, C, orc, flags):
     out_l = mesh.locate_feet(t_np1=t_np1, dt=dt, feet=dev(feet[perm]), feet_in=True, start_mode=S.START_LEARNED,
                              want_steps=True, stats=True)
     out_s = mesh.locate_feet(feet=dev(feet[perm]), feet_in=True, want_steps=True, stats=True)
+    out_c = mesh.locate_feet(feet=dev(feet[perm]), feet_in=True, start_mode=S.START_CHART, want_steps=True,
+                             stats=True)
     assert np.array_equal(host(out_l["elem"]), e_ref[perm])
     assert np.array_equal(host(out_s["elem"]), e_ref[perm])
+    assert np.array_equal(host(out_c["elem"]), e_ref[perm])
+    # the exact chart cell starts within a few steps of the foot
+    assert out_c["stats"]["walk_steps"] < 0.2 * out_s["stats"]["walk_steps"], (out_c["stats"], out_s["stats"])
     if not flags & 0x1:
         inside = e_ref[perm] >= 0
         assert np.abs(host(out_l["bary"])[inside] - b_ref[perm][inside]).max() < 1e-12
@@ -199,7 +216,9 @@ def test_learned_start_finds_the_oracles_elements(S, C, orc, flags):
     v0 = I.gaussian_hill(xy)[perm][:, None]
     a = host(mesh.step(fld, 1.5 * dt, dt, S.SLW_RK2, dev(v0), start_mode=S.START_LEARNED))
     b = host(mesh.step(fld, 1.5 * dt, dt, S.SLW_RK2, dev(v0)))
+    c = host(mesh.step(fld, 1.5 * dt, dt, S.SLW_RK2, dev(v0), start_mode=S.START_CHART))
     assert np.array_equal(a, b)
+    assert np.array_equal(c, b)
 
 
 def test_untrained_network_is_still_exact(S, C, orc):
@@ -212,6 +231,8 @@ def test_untrained_network_is_still_exact(S, C, orc):
     v0 = I.gaussian_hill(p2.xy)[:, None]
     v = host(mesh.step(fld, 0.0, dt, S.SLW_EULER, dev(v0), order=2, start_mode=S.START_LEARNED))
     ref, _, _, _ = orc.sl_step(xy, tri, v0, fld, 0.0, dt, I.SCHEME_EULER, order=2, p2=p2)
+    assert np.abs(v - ref).max() <= 1e-12 * np.abs(v0).max()
+    v = host(mesh.step(fld, 0.0, dt, S.SLW_EULER, dev(v0), order=2, start_mode=S.START_CHART))
     assert np.abs(v - ref).max() <= 1e-12 * np.abs(v0).max()
     mesh.attach_mlp(None)
     with pytest.raises(S.SlwError):
