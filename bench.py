@@ -216,6 +216,87 @@ def measure_batch(steps=100):
             "plain_one_launch_per_mesh_ms_per_step": plain_ms, "speedup_vs_plain": plain_ms / graph_ms}
 
 
+def _walk_histogram(steps: np.ndarray) -> dict:
+    """Walk steps per foot: percentiles and counts in power-of-two bins."""
+    edges = [0, 1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 1 << 30]
+    counts, _ = np.histogram(steps, bins=edges)
+    wave = steps[: steps.size // 64 * 64].reshape(-1, 64).max(axis=1)
+    return {"mean": float(steps.mean()), "p50": float(np.percentile(steps, 50)),
+            "p90": float(np.percentile(steps, 90)), "p99": float(np.percentile(steps, 99)),
+            "max": int(steps.max()), "mean_wavefront_max": float(wave.mean()),
+            "bins": {f"[{a},{b})": int(c) for a, b, c in zip(edges[:-1], edges[1:], counts)}}
+
+
+def measure_learned(alpha=50.0, n=1415, k=16, steps=10, samples_per_step=200_000, train_steps=50, seed=5005):
+    """Learned start on the graded mesh at a large Courant number: the network
+    is trained on the GPU on feet that the plain walk locates over 50 steps
+    (10M samples), then steps with the learned start (per-foot choice between
+    the network's proposal and the steered start) are timed beside the plain
+    steered walk and the exact chart-cell start (no network); all three must
+    give identical bits."""
+    import torch
+    from paper_2104_09189_amd import inputs as I
+    from paper_2104_09189_amd import slwalk as S
+    w = I.graded_swirl(alpha=alpha, n=n, k_fields=k)
+    ctx = S.Context(0)
+    mesh = S.Mesh(ctx, w.xy, w.tri, S.INTERNAL_ORDER)
+    t0 = time.perf_counter()
+    mesh.chart_build(2048)
+    chart_s = time.perf_counter() - t0
+    nd = mesh.n_dofs
+    rng = np.random.default_rng(seed)
+    m = samples_per_step * train_steps
+    X = torch.empty((m, 5), dtype=torch.float32, device="cuda:0")
+    Y = torch.empty((m, 2), dtype=torch.float32, device="cuda:0")
+    t0 = time.perf_counter()
+    for s in range(train_steps):
+        ids = torch.from_numpy(rng.integers(0, nd, samples_per_step).astype(np.int32)).to("cuda:0")
+        sl = slice(s * samples_per_step, (s + 1) * samples_per_step)
+        mesh.learned_gather(w.field, (s + 1) * w.dt, w.dt, w.scheme, ids, X[sl], Y[sl])
+    torch.cuda.synchronize()
+    gather_s = time.perf_counter() - t0
+    net = S.Mlp(ctx, seed=0)
+    net.fit_normalization(X)
+    t0 = time.perf_counter()
+    plan = [(3e-3, 4096, 8), (1e-3, 4096, 4)]
+    for i, (lr, bs, ep) in enumerate(plan):
+        loss = net.train(X, Y, epochs=ep, batch=bs, lr=lr, seed=seed + i)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    mesh.attach_mlp(net)
+    del X, Y
+    v0 = torch.from_numpy(np.ascontiguousarray(w.v0[mesh.dof_order()])).to("cuda:0")
+    stream = torch.cuda.current_stream()
+    t_n = 7 * w.dt
+    res = {}
+    outs = {}
+    for name, mode in (("plain_steered", S.START_STEERED), ("learned", S.START_LEARNED),
+                       ("chart_exact", S.START_CHART)):
+        vo = torch.empty_like(v0)
+        mesh.step(w.field, t_n, w.dt, w.scheme, v0, vo, start_mode=mode)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            mesh.step(w.field, t_n, w.dt, w.scheme, v0, vo, start_mode=mode)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        outs[name] = vo.cpu().numpy()
+        loc = mesh.locate_feet(w.field, t_n + w.dt, w.dt, w.scheme, start_mode=mode, want_steps=True,
+                               want_bary=False)
+        hist = _walk_histogram(loc["steps"].cpu().numpy().astype(np.int64))
+        res[name] = {"ms_per_step": ms, "feet_per_s": mesh.n_nodes / (ms * 1e-3), "walk_steps": hist}
+    identical = all(np.array_equal(outs["plain_steered"], outs[x]) for x in ("learned", "chart_exact"))
+    base = res["plain_steered"]["ms_per_step"]
+    return {"workload": w.name, "n_nodes": int(mesh.n_nodes), "n_tris": int(mesh.n_tris), "alpha": alpha,
+            "k_fields": k, "chart_g": 2048, "chart_build_s": chart_s, "training_samples": m,
+            "gather_s": gather_s, "train_s": train_s, "train_plan": plan, "final_minibatch_loss": loss,
+            "starts": res, "identical_bits": identical,
+            "speedup_learned_vs_plain": base / res["learned"]["ms_per_step"],
+            "speedup_chart_vs_plain": base / res["chart_exact"]["ms_per_step"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -227,6 +308,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--only-a", action="store_true", help="measure strategy (a) only")
     ap.add_argument("--no-batch", action="store_true", help="skip the multi-mesh batch measurement")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-start measurement")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times (to scale HBM counters)")
@@ -303,6 +385,8 @@ def main():
         out["k_field_reuse"] = measure_k_reuse(mesh, w, v0)
     if not args.no_batch and not args.only_a:
         out["batch"] = measure_batch()
+    if not args.no_learned and not args.only_a:
+        out["learned"] = measure_learned()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(out), flush=True)
