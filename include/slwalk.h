@@ -100,8 +100,11 @@ enum {
                               fixed-start baseline, Section 2.2 complexity) */
     SLW_START_LEARNED = 4, /* the triangle proposed by the network attached with
                               slw_mesh_attach_mlp (learned start; see below) */
-    SLW_START_CHART = 5    /* the start-table triangle of the foot's own chart cell
+    SLW_START_CHART = 5,   /* the start-table triangle of the foot's own chart cell
                               (exact chart lookup, no network; needs slw_chart_build) */
+    SLW_START_NEIGHBOR = 6 /* strategy (c): the element found for the preceding node of a
+                              chain of consecutive internal-order nodes (slw_step only;
+                              see slw_mesh_set_chain) */
 };
 /* slw_mesh_upload flags */
 #define SLW_COORDS_F32 0x1u     /* store coordinates as float (FP32 walk, FP64/exact fallback) */
@@ -180,6 +183,21 @@ slw_status slw_mesh_dof_order(const slw_mesh *mesh, int32_t *user_of_internal_h)
  * (default 4096), and the hard limit that fails with SLW_E_WALK
  * (default 1 << 22).  Either value <= 0 keeps the current one. */
 slw_status slw_mesh_set_walk_limits(slw_mesh *mesh, int32_t step_cap, int32_t hard_limit);
+/* Lane schedule of slw_step: with feet_per_lane = 1 every lane of a
+ * wavefront walks one foot and the wavefront ends with its longest walk;
+ * with 2, 4 or 8 each wavefront owns 64 x feet_per_lane consecutive DOFs and
+ * a lane whose walk ends starts the next unstarted one (lane repacking), so
+ * the wavefront's time follows the sum of its walks rather than their
+ * maximum.  Results are identical for every setting.  0 selects the
+ * library's default. */
+slw_status slw_mesh_set_repack(slw_mesh *mesh, int feet_per_lane);
+/* Strategy (c) of Section 3 (SLW_START_NEIGHBOR) starts a walk from the
+ * element that contains an adjacent node's foot.  The spanning forest used
+ * here is made of chains of `length` consecutive nodes of the internal
+ * (Morton) order, one chain per lane: the first foot of a chain starts as
+ * strategy (a), each later one from the element found for its predecessor.
+ * length in {2, 4, 8, 16}; default 4. */
+slw_status slw_mesh_set_chain(slw_mesh *mesh, int length);
 
 /* General point location, the analogue of the paper's [I, B] =
  * pointLocationBW(TBW, Q, s): m query points q (m x 2, mesh coordinate type)

@@ -281,6 +281,26 @@ slw_status slw_mesh_set_walk_limits(slw_mesh *mesh, int32_t step_cap, int32_t ha
     return SLW_OK;
 }
 
+slw_status slw_mesh_set_repack(slw_mesh *mesh, int feet_per_lane)
+{
+    if (!mesh)
+        return set_error(SLW_E_ARG, "mesh is NULL");
+    if (feet_per_lane != 0 && feet_per_lane != 1 && feet_per_lane != 2 && feet_per_lane != 4 && feet_per_lane != 8)
+        return set_error(SLW_E_ARG, "slw_mesh_set_repack: feet per lane must be 1, 2, 4 or 8");
+    mesh->m.repack = feet_per_lane <= 1 ? 0 : feet_per_lane;
+    return SLW_OK;
+}
+
+slw_status slw_mesh_set_chain(slw_mesh *mesh, int length)
+{
+    if (!mesh)
+        return set_error(SLW_E_ARG, "mesh is NULL");
+    if (length != 2 && length != 4 && length != 8 && length != 16)
+        return set_error(SLW_E_ARG, "slw_mesh_set_chain: length must be 2, 4, 8 or 16");
+    mesh->m.chain = length;
+    return SLW_OK;
+}
+
 slw_status slw_locate(slw_mesh *mesh, const void *q, int64_t m, const int32_t *start, int32_t *elem, void *bary,
                       int32_t *steps)
 {
@@ -307,7 +327,7 @@ slw_status slw_locate_feet(slw_mesh *mesh, const slw_field *field, double t_np1,
     if (scheme != SLW_EULER && scheme != SLW_RK2)
         return set_error(SLW_E_ARG, "unknown scheme");
     if (start_mode < SLW_START_STEERED || start_mode > SLW_START_CHART)
-        return set_error(SLW_E_ARG, "unknown start mode");
+        return set_error(SLW_E_ARG, "unknown start mode (SLW_START_NEIGHBOR is for slw_step)");
     if ((start_mode == SLW_START_GIVEN || start_mode == SLW_START_FIXED) && !start)
         return set_error(SLW_E_ARG, "start array required for this start mode");
     if (start_mode == SLW_START_LEARNED && !mesh->m.mlp)
@@ -368,7 +388,7 @@ slw_status slw_step(slw_mesh *mesh, const slw_field *field, double t_n, double d
         return set_error(SLW_E_ARG, "unknown scheme");
     if (vdtype != SLW_F64 && vdtype != SLW_F32)
         return set_error(SLW_E_ARG, "unknown vdtype");
-    if (start_mode < SLW_START_STEERED || start_mode > SLW_START_CHART)
+    if (start_mode < SLW_START_STEERED || start_mode > SLW_START_NEIGHBOR)
         return set_error(SLW_E_ARG, "unknown start mode");
     if ((start_mode == SLW_START_GIVEN || start_mode == SLW_START_FIXED) && !start)
         return set_error(SLW_E_ARG, "start array required for this start mode");
@@ -404,14 +424,6 @@ slw_status slw_step(slw_mesh *mesh, const slw_field *field, double t_n, double d
     }
     const bool write_prev = start_mode == SLW_START_PREV;
     FieldDev fd = to_dev(field);
-    if (start_mode == SLW_START_LEARNED || start_mode == SLW_START_CHART) {
-        st = hip_check(launch_chart_start(m, ctx->stream, fd, t_n + dt, dt, scheme, nullptr, rows,
-                                          start_mode == SLW_START_LEARNED, m.learned_start),
-                       "chart start");
-        if (st != SLW_OK)
-            return st;
-        start = m.learned_start;
-    }
     st = hip_check(launch_step(m, ctx->stream, fd, t_n, dt, scheme, order, start_mode, start, vin_int, vdtype, k,
                                v_out, outside_value, write_prev, out_map, stats_h ? ctx->stats : nullptr),
                    "slw_step");

@@ -67,6 +67,8 @@ struct DevMesh {
     int64_t device_bytes = 0;
     int32_t step_cap = 4096;
     int32_t hard_limit = 1 << 22;
+    int repack = 0;  // step kernel: 0 one foot per lane; 2, 4, 8: chunks of 64 x repack feet per wavefront
+    int chain = 4;   // strategy (c): Morton chain length per lane (2, 4, 8, 16)
 };
 
 // Device counters accumulated by the kernels (all int64, see slw_stats).
@@ -164,6 +166,13 @@ struct MeshView {
     double bb[4];
     FilterConst fc;
     int32_t step_cap, hard_limit;
+    // chart starts (null without a chart / network)
+    const float2 *chart_node;
+    const float *chart_qx, *chart_qy;
+    const int32_t *chart_table;
+    int chart_g;
+    const uint16_t *mlp_wpack;
+    const float *mlp_bias, *mlp_norm;
 };
 MeshView view_of(const DevMesh &m);
 

@@ -126,6 +126,14 @@ MeshView view_of(const DevMesh &m)
     v.fc = m.fc;
     v.step_cap = m.step_cap;
     v.hard_limit = m.hard_limit;
+    v.chart_node = m.chart_node;
+    v.chart_qx = m.chart_qx;
+    v.chart_qy = m.chart_qy;
+    v.chart_table = m.chart_table;
+    v.chart_g = m.chart_g;
+    v.mlp_wpack = m.mlp ? m.mlp->wpack : nullptr;
+    v.mlp_bias = m.mlp ? m.mlp->bias : nullptr;
+    v.mlp_norm = m.mlp ? m.mlp->norm : nullptr;
     return v;
 }
 
@@ -139,6 +147,22 @@ namespace {
 __device__ inline int32_t quadrant_start(const int4 qs, float dx, float dy)
 {
     return dx >= 0.0f ? (dy >= 0.0f ? qs.x : qs.w) : (dy >= 0.0f ? qs.y : qs.z);
+}
+
+// Of two candidate start triangles, the one whose centroid lies nearer the
+// foot q (float frame of the records)
+template <bool F32>
+__device__ inline int32_t nearer_start(const MeshView &mv, int32_t ja, int32_t jb, typename CT<F32>::R qx,
+                                       typename CT<F32>::R qy)
+{
+    const float fx = F32 ? (float)qx : (float)((double)qx - mv.fc.cx);
+    const float fy = F32 ? (float)qy : (float)((double)qy - mv.fc.cy);
+    const GeoRec ra = mv.geo[ja], rb = mv.geo[jb];
+    const float ax = (ra.p[0].x + ra.p[1].x + ra.p[2].x) * (1.f / 3.f) - fx;
+    const float ay = (ra.p[0].y + ra.p[1].y + ra.p[2].y) * (1.f / 3.f) - fy;
+    const float bx = (rb.p[0].x + rb.p[1].x + rb.p[2].x) * (1.f / 3.f) - fx;
+    const float by = (rb.p[0].y + rb.p[1].y + rb.p[2].y) * (1.f / 3.f) - fy;
+    return ax * ax + ay * ay < bx * bx + by * by ? ja : jb;
 }
 
 template <bool F32>
@@ -266,62 +290,73 @@ __device__ inline WalkResult<R> outside_result(int32_t steps, int32_t flags)
     return w;
 }
 
-// Barycentric walk of Section 2.2 from triangle j to the foot q, then the tie
-// rule (smallest user id among the closed containers), then the weights on
-// the exact coordinates.
+// One move of the barycentric walk of Section 2.2 from triangle j towards
+// the foot q: 0 = moved (j is the next triangle), 1 = stopped (every
+// coordinate >= 0: r is j's record, zmask has bit k set when s_k = 0),
+// 2 = outside (a negative coordinate across a boundary edge, or the hard
+// step limit: then flags gets bits 0 and 1).
 template <bool F32>
-__device__ WalkResult<typename CT<F32>::R> walk(const MeshView &mv, int32_t j, typename CT<F32>::R qx,
-                                                 typename CT<F32>::R qy, uint32_t seed, Counters &c)
+__device__ inline int walk_move(const MeshView &mv, int32_t &j, GeoRec &r, int &zmask, float qfx, float qfy,
+                                typename CT<F32>::R qx, typename CT<F32>::R qy, uint32_t seed, int32_t &steps,
+                                int32_t &flags, Counters &c)
 {
-    using R = typename CT<F32>::R;
-    const float qfx = F32 ? (float)qx : (float)((double)qx - mv.fc.cx);
-    const float qfy = F32 ? (float)qy : (float)((double)qy - mv.fc.cy);
-    GeoRec r;
     float o[3];
     int s[3];
-    int32_t steps = 0, flags = 0;
-    for (;;) {
-        r = mv.geo[j];
-        edge_signs<F32>(mv, r, qfx, qfy, qx, qy, o, s, c);
-        const bool n0 = s[0] < 0, n1 = s[1] < 0, n2 = s[2] < 0;
-        if (!(n0 | n1 | n2))
-            break;
-        // a negative side on the boundary: the foot is outside the (convex) domain
-        if ((n0 && r.nb[0] < 0) || (n1 && r.nb[1] < 0) || (n2 && r.nb[2] < 0))
-            return outside_result<R>(steps, flags);
-        if (steps >= mv.hard_limit)
-            return outside_result<R>(steps, flags | 3);
-        int k;
-        if (steps < mv.step_cap) {
-            // most negative barycentric coordinate, lowest index on ties
-            // (selects rather than indexing, so the record stays in registers)
-            const float m0 = n0 ? o[0] : INFINITY, m1 = n1 ? o[1] : INFINITY, m2 = n2 ? o[2] : INFINITY;
-            k = (m1 < m0) ? ((m2 < m1) ? 2 : 1) : ((m2 < m0) ? 2 : 0);
-        } else {
-            // randomised visibility walk: a uniformly chosen separating edge
-            // (terminates with probability 1 on any triangulation)
-            flags |= 1;
-            const int cnt = (int)n0 + (int)n1 + (int)n2;
-            const int pick = (int)(hash32(seed ^ hash32((uint32_t)steps)) % (uint32_t)cnt);
-            // the pick-th negative edge
-            const int first = n0 ? 0 : (n1 ? 1 : 2);
-            const int second = (n0 && n1) ? 1 : 2;
-            k = pick == 0 ? first : (pick == 1 ? second : 2);
-        }
-        j = sel3(k, r.nb[0], r.nb[1], r.nb[2]);
-        ++steps;
+    r = mv.geo[j];
+    edge_signs<F32>(mv, r, qfx, qfy, qx, qy, o, s, c);
+    const bool n0 = s[0] < 0, n1 = s[1] < 0, n2 = s[2] < 0;
+    if (!(n0 | n1 | n2)) {
+        zmask = (int)(s[0] == 0) | ((int)(s[1] == 0) << 1) | ((int)(s[2] == 0) << 2);
+        return 1;
     }
-    // tie rule on the closed containers
-    const int z = (s[0] == 0) + (s[1] == 0) + (s[2] == 0);
+    // a negative side on the boundary: the foot is outside the (convex) domain
+    if ((n0 && r.nb[0] < 0) || (n1 && r.nb[1] < 0) || (n2 && r.nb[2] < 0))
+        return 2;
+    if (steps >= mv.hard_limit) {
+        flags |= 3;
+        return 2;
+    }
+    int k;
+    if (steps < mv.step_cap) {
+        // most negative barycentric coordinate, lowest index on ties
+        // (selects rather than indexing, so the record stays in registers)
+        const float m0 = n0 ? o[0] : INFINITY, m1 = n1 ? o[1] : INFINITY, m2 = n2 ? o[2] : INFINITY;
+        k = (m1 < m0) ? ((m2 < m1) ? 2 : 1) : ((m2 < m0) ? 2 : 0);
+    } else {
+        // randomised visibility walk: a uniformly chosen separating edge
+        // (terminates with probability 1 on any triangulation)
+        flags |= 1;
+        const int cnt = (int)n0 + (int)n1 + (int)n2;
+        const int pick = (int)(hash32(seed ^ hash32((uint32_t)steps)) % (uint32_t)cnt);
+        // the pick-th negative edge
+        const int first = n0 ? 0 : (n1 ? 1 : 2);
+        const int second = (n0 && n1) ? 1 : 2;
+        k = pick == 0 ? first : (pick == 1 ? second : 2);
+    }
+    j = sel3(k, r.nb[0], r.nb[1], r.nb[2]);
+    ++steps;
+    return 0;
+}
+
+// End of a walk that stopped in triangle j (record r, zero-sign mask zmask):
+// the tie rule (smallest user id among the closed containers), then the
+// weights on the exact coordinates.
+template <bool F32>
+__device__ inline WalkResult<typename CT<F32>::R> finish_walk(const MeshView &mv, int32_t j, GeoRec r, int zmask,
+                                                              int32_t steps, int32_t flags,
+                                                              typename CT<F32>::R qx, typename CT<F32>::R qy)
+{
+    using R = typename CT<F32>::R;
+    const int z = (zmask & 1) + ((zmask >> 1) & 1) + ((zmask >> 2) & 1);
     int32_t e = j;
     if (z == 1) {
-        const int k = s[0] == 0 ? 0 : (s[1] == 0 ? 1 : 2);
+        const int k = (zmask & 1) ? 0 : ((zmask & 2) ? 1 : 2);
         const int32_t nbk = sel3(k, r.nb[0], r.nb[1], r.nb[2]);
         flags |= 4;
         if (nbk >= 0 && (mv.tri_uf[nbk] & kUidMask) < (mv.tri_uf[j] & kUidMask))
             e = nbk;
     } else if (z == 2) {
-        const int cidx = s[0] != 0 ? 0 : (s[1] != 0 ? 1 : 2);
+        const int cidx = !(zmask & 1) ? 0 : (!(zmask & 2) ? 1 : 2);
         flags |= 8;
         e = mv.vmin[sel3(cidx, r.v[0], r.v[1], r.v[2])];
     }
@@ -364,8 +399,27 @@ __device__ WalkResult<typename CT<F32>::R> walk(const MeshView &mv, int32_t j, t
     return w;
 }
 
-// ---------------------------------------------------------------------------
-// statistics: one atomic per wavefront
+// Barycentric walk of Section 2.2 from triangle j to the foot q, then the tie
+// rule, then the weights.
+template <bool F32>
+__device__ WalkResult<typename CT<F32>::R> walk(const MeshView &mv, int32_t j, typename CT<F32>::R qx,
+                                                 typename CT<F32>::R qy, uint32_t seed, Counters &c)
+{
+    using R = typename CT<F32>::R;
+    const float qfx = F32 ? (float)qx : (float)((double)qx - mv.fc.cx);
+    const float qfy = F32 ? (float)qy : (float)((double)qy - mv.fc.cy);
+    GeoRec r;
+    int zmask = 0;
+    int32_t steps = 0, flags = 0;
+    for (;;) {
+        const int st = walk_move<F32>(mv, j, r, zmask, qfx, qfy, qx, qy, seed, steps, flags, c);
+        if (st == 1)
+            break;
+        if (st == 2)
+            return outside_result<R>(steps, flags);
+    }
+    return finish_walk<F32>(mv, j, r, zmask, steps, flags, qx, qy);
+}
 
 __device__ inline unsigned long long wave_sum(unsigned long long v)
 {
@@ -398,6 +452,21 @@ struct LaneStats {
         hard += (w.flags & 2) != 0;
         edge += (w.flags & 4) != 0;
         vertex += (w.flags & 8) != 0;
+    }
+    // a walk's end (inside or outside) and, separately, its tie flags
+    __device__ void add_walk(bool inside, int32_t st, int32_t flags)
+    {
+        ++feet;
+        outside += !inside;
+        steps += st;
+        max_steps = max_steps > (uint32_t)st ? max_steps : (uint32_t)st;
+        fallback += (flags & 1) != 0;
+        hard += (flags & 2) != 0;
+    }
+    __device__ void add_ties(int32_t flags)
+    {
+        edge += (flags & 4) != 0;
+        vertex += (flags & 8) != 0;
     }
 };
 
@@ -776,6 +845,103 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // ---------------------------------------------------------------------------
+// strategy (c): the start is the element found for a neighbouring node
+
+// orders the LDS accesses of the lanes of one wavefront around it (the
+// wavefront's LDS operations complete in issue order)
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Strategy (c) of Section 3 starts node i's walk from the element that
+// contains the foot of an adjacent node (its parent in a spanning tree), so
+// that the walk covers about the distance between two neighbouring feet.  A
+// breadth-first tree has about sqrt(N) sequential levels, each a global
+// round trip on a GPU; here the spanning forest is made of chains of L
+// consecutive Morton-ordered nodes (neighbours or near neighbours): lane t of
+// a wavefront walks the chain [base + L t, base + L t + L) in order, the
+// first foot from its steered start (strategy (a)), every later foot from
+// the element found for the previous one, unless its own steered start lies
+// nearer (the Z curve jumps between blocks now and then: a jump would cost a
+// walk across the mesh).  Rows and weights are staged in
+// LDS, then the wavefront interpolates 64 consecutive DOFs at a time
+// (contiguous stores).  One wavefront per workgroup.
+template <bool F32, typename V, int NA, int L>
+__global__ void __launch_bounds__(kWave)
+    k_step_chain(MeshView mv, FieldDev f, double dt, int scheme, const V *__restrict__ vin, int k,
+                 V *__restrict__ vout, double outside, const int32_t *__restrict__ out_map, int64_t n_iter,
+                 DevStats *st)
+{
+    using R = typename CT<F32>::R;
+    using R2 = typename CT<F32>::R2;
+    constexpr int C = kWave * L;
+    __shared__ int32_t srow[C * NA];
+    __shared__ V swgt[C * NA];
+    const int lane = threadIdx.x;
+    const int64_t base = xcd_tile(blockIdx.x, gridDim.x) * (int64_t)C;
+    LaneStats ls;
+    int32_t prev = -1;  // element of the previous foot of this lane's chain
+#pragma unroll 1
+    for (int r = 0; r < L; ++r) {
+        const int o = lane * L + r;
+        const int64_t d = base + o;
+        int32_t row[NA];
+        V wgt[NA];
+        row[0] = -1;
+#pragma unroll
+        for (int a = 1; a < NA; ++a)
+            row[a] = 0;
+#pragma unroll
+        for (int a = 0; a < NA; ++a)
+            wgt[a] = (V)0;
+        if (d < n_iter) {
+            const R2 x = ((const R2 *)mv.dof_xy)[d];
+            R qx, qy;
+            foot_of<R>(f, scheme, x.x, x.y, (R)dt, qx, qy);
+            WalkResult<R> w = outside_result<R>(0, 0);
+            if (in_box<R>(qx, qy, mv.bb)) {
+                int32_t j0 = quadrant_start(mv.qstart[d], (float)(qx - x.x), (float)(qy - x.y));
+                if (prev >= 0)
+                    j0 = nearer_start<F32>(mv, prev, j0, qx, qy);
+                w = walk<F32>(mv, j0, qx, qy, (uint32_t)d * 2654435761u, ls.c);
+            }
+            if (st)
+                ls.add(w);
+            prev = w.elem;
+            if (w.elem >= 0)
+                lagrange<R, V, NA>(mv, w.elem, w.v, w.th, row, wgt);
+        }
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+            srow[o * NA + a] = row[a];
+            swgt[o * NA + a] = wgt[a];
+        }
+    }
+    wave_lds_sync();
+#pragma unroll 1
+    for (int b = 0; b < L; ++b) {
+        const int64_t gb = base + (int64_t)b * kWave;
+        if (gb >= n_iter)
+            break;
+        const int o = b * kWave + lane;
+        int32_t row[NA];
+        V wgt[NA];
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+            row[a] = srow[o * NA + a];
+            wgt[a] = swgt[o * NA + a];
+        }
+        const int nf = (int)min<int64_t>(kWave, n_iter - gb);
+        wave_interp<V, NA>(row, wgt, nf, vin, k, vout, out_map, gb, (V)outside);
+    }
+    if (st)
+        flush_stats(ls, st);
+}
+
+// ---------------------------------------------------------------------------
 // batches: every mesh of a batch advanced by one step in one launch
 
 // time factors of a field on the device (per workgroup; uniform values)
@@ -913,26 +1079,62 @@ __device__ inline int upper_index(const float *__restrict__ tab, int n, float x)
     return lo;
 }
 
-// start[d] for the DOFs [0, n_iter) (internal order) from the chart: NET,
-// the table cell of chart(node) + network output; else the cell that holds
-// the foot (quantile tables); then whichever of that proposal and the
-// node's steered start lies nearer the foot.  Feet are computed from the
-// field or read from feet_in (indexed like slw_locate_feet's feet).
+// Chart start of DOF d (internal order; valid: d is a DOF whose foot q lies
+// in the bounding box): NET, the table cell of chart(node) + network output;
+// else the cell that holds the foot (quantile tables); then whichever of that
+// proposal and the node's steered start lies nearer the foot.  With NET every
+// lane of the wavefront must call it (the network runs on the whole
+// wavefront); the result is meaningful on valid lanes only.
+template <bool F32, bool NET>
+__device__ inline int32_t chart_start(const MeshView &mv, bool valid, int64_t d, typename CT<F32>::R2 x,
+                                      typename CT<F32>::R qx, typename CT<F32>::R qy, double t_np1)
+{
+    using R = typename CT<F32>::R;
+    int32_t j = 0;
+    if (NET) {
+        float feat[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+        float2 c = make_float2(0.f, 0.f);
+        if (valid) {
+            c = mv.chart_node[d];
+            raw_features<R>(c, x.x, x.y, qx, qy, t_np1, feat);
+            mlp_normalise(mv.mlp_norm, feat);
+        }
+        const float2 duv = mlp_forward_wave(mv.mlp_wpack, mv.mlp_bias, feat);  // every lane
+        if (valid)
+            j = chart_lookup(mv.chart_table, mv.chart_g, make_float2(c.x + duv.x, c.y + duv.y));
+    }
+    if (!valid)
+        return -1;
+    // the foot in the records' float frame, as the chart was built
+    const float fx = F32 ? (float)qx : (float)((double)qx - mv.fc.cx);
+    const float fy = F32 ? (float)qy : (float)((double)qy - mv.fc.cy);
+    if (!NET) {
+        const int g = mv.chart_g;
+        const int bu = upper_index(mv.chart_qx, g, fx);
+        const int bv = upper_index(mv.chart_qy + (int64_t)bu * g, g, fy);
+        j = mv.chart_table[(int64_t)bu * g + bv];
+    }
+    const int32_t js = quadrant_start(mv.qstart[d], (float)(qx - x.x), (float)(qy - x.y));
+    return nearer_start<F32>(mv, j, js, qx, qy);
+}
+
+// start[d] for the DOFs [0, n_iter) (internal order) by chart_start; feet
+// computed from the field or read from feet_in (indexed like
+// slw_locate_feet's feet)
 template <bool F32, bool NET>
 __global__ void __launch_bounds__(kBlock)
     k_chart_start(MeshView mv, FieldDev f, double dt, double t_np1, int scheme,
-                  const typename CT<F32>::R2 *__restrict__ feet_in, const uint16_t *__restrict__ wpack,
-                  const float *__restrict__ bias, const float *__restrict__ norm, const float2 *__restrict__ node,
-                  const float *__restrict__ qx_tab, const float *__restrict__ qy_tab,
-                  const int32_t *__restrict__ table, int g, int64_t n_iter, int32_t *__restrict__ start)
+                  const typename CT<F32>::R2 *__restrict__ feet_in, int64_t n_iter, int32_t *__restrict__ start)
 {
     using R = typename CT<F32>::R;
     using R2 = typename CT<F32>::R2;
     const int64_t d = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    float feat[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    R2 x;
+    x.x = (R)0;
+    x.y = (R)0;
     R qx = 0, qy = 0;
     if (d < n_iter) {
-        const R2 x = ((const R2 *)mv.dof_xy)[d];
+        x = ((const R2 *)mv.dof_xy)[d];
         if (feet_in) {
             const int64_t api = mv.internal_order ? d : mv.dof_user[d];
             qx = feet_in[api].x;
@@ -940,39 +1142,172 @@ __global__ void __launch_bounds__(kBlock)
         } else {
             foot_of<R>(f, scheme, x.x, x.y, (R)dt, qx, qy);
         }
-        if (NET) {
-            raw_features<R>(node[d], x.x, x.y, qx, qy, t_np1, feat);
-            mlp_normalise(norm, feat);
-        }
     }
-    int32_t j = -1;
-    if (NET) {
-        const float2 duv = mlp_forward_wave(wpack, bias, feat);  // every lane
+    // outside the box the walk does not run; the steered start is written
+    const bool valid = d < n_iter && in_box<R>(qx, qy, mv.bb);
+    const int32_t j = chart_start<F32, NET>(mv, valid, d, x, qx, qy, t_np1);
+    if (d < n_iter)
+        start[d] = valid ? j : mv.qstart[d].x;
+}
+
+// ---------------------------------------------------------------------------
+// the step with lane repacking
+
+
+// The fused step for a chunk of 64 RP consecutive DOFs [base, base + 64 RP)
+// owned by one wavefront.  Walk lengths differ from foot to foot; instead of
+// holding every lane until the longest walk of its 64 ends, a lane whose walk
+// ends takes the next unstarted foot of the chunk (ballot + prefix count),
+// so the wavefront's time follows the chunk's total walk length.  Feet and
+// start triangles are computed first and staged in LDS (sq, sj); a finished
+// walk leaves its triangle and zero-sign mask there (sj, sz); the tie rule,
+// the weights and the cooperative interpolation then run 64 feet at a time.
+// Every lane of the wavefront calls it.
+template <bool F32, typename V, int NA, int RP, bool NET>
+__device__ inline void step_chunk(const MeshView &mv, const FieldDev &f, double dt, double t_np1, int scheme, int mode,
+                                  const int32_t *__restrict__ start, const V *__restrict__ vin, int k,
+                                  V *__restrict__ vout, double outside, int write_prev,
+                                  const int32_t *__restrict__ out_map, int64_t n_iter, int64_t base,
+                                  typename CT<F32>::R2 *sq, int32_t *sj, int8_t *sz, DevStats *st)
+{
+    using R = typename CT<F32>::R;
+    using R2 = typename CT<F32>::R2;
+    constexpr int C = kWave * RP;
+    const int lane = threadIdx.x & (kWave - 1);
+    LaneStats ls;
+    // 1. feet and start triangles (-1: outside the bounding box; -2: no DOF);
+    // chart starts (learned or exact) are computed here, for the whole
+    // wavefront at once
+#pragma unroll
+    for (int rr = 0; rr < RP; ++rr) {
+        const int slot = rr * kWave + lane;
+        const int64_t d = base + slot;
+        int32_t j0 = -2;
+        R2 q, x;
+        q.x = q.y = x.x = x.y = (R)0;
         if (d < n_iter) {
-            const float2 c = node[d];
-            j = chart_lookup(table, g, make_float2(c.x + duv.x, c.y + duv.y));
+            x = ((const R2 *)mv.dof_xy)[d];
+            foot_of<R>(f, scheme, x.x, x.y, (R)dt, q.x, q.y);
+            j0 = -1;
+        }
+        const bool valid = d < n_iter && in_box<R>(q.x, q.y, mv.bb);
+        if constexpr (NET) {  // the learned start (kernels instantiated for it alone)
+            const int32_t jc = chart_start<F32, true>(mv, valid, d, x, q.x, q.y, t_np1);
+            j0 = valid ? jc : j0;
+        } else if (mode == SLW_START_CHART) {
+            const int32_t jc = chart_start<F32, false>(mv, valid, d, x, q.x, q.y, t_np1);
+            j0 = valid ? jc : j0;
+        } else if (valid) {
+            const int64_t api = (mode == SLW_START_GIVEN && !mv.internal_order) ? mv.dof_user[d] : d;
+            j0 = start_for<F32>(mv, d, api, mode, start, (float)(q.x - x.x), (float)(q.y - x.y));
+        }
+        sq[slot] = q;
+        sj[slot] = j0;
+    }
+    wave_lds_sync();
+    // 2. walks, one move per iteration for every busy lane; idle lanes refill
+    int slot = -1;
+    int32_t j = 0, steps = 0, flags = 0;
+    R qx = (R)0, qy = (R)0;
+    float qfx = 0.f, qfy = 0.f;
+    uint32_t seed = 0;
+    int next = 0;  // first unstarted foot of the chunk (uniform)
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (;;) {
+        const bool idle = slot < 0;
+        const unsigned long long need = __ballot(idle);
+        if (need != 0ull && next < C) {
+            if (idle) {
+                const int cand = next + __popcll(need & below);
+                if (cand < C) {
+                    const int32_t j0 = sj[cand];
+                    if (j0 >= 0) {
+                        const R2 q = sq[cand];
+                        slot = cand;
+                        j = j0;
+                        qx = q.x;
+                        qy = q.y;
+                        qfx = F32 ? (float)qx : (float)((double)qx - mv.fc.cx);
+                        qfy = F32 ? (float)qy : (float)((double)qy - mv.fc.cy);
+                        steps = 0;
+                        flags = 0;
+                        seed = (uint32_t)(base + cand) * 2654435761u;
+                    } else if (j0 == -1) {
+                        ls.add_walk(false, 0, 0);
+                    }
+                }
+            }
+            next += __popcll(need);
+        }
+        if (__ballot(slot >= 0) == 0ull) {
+            if (next >= C)
+                break;
+            continue;
+        }
+        if (slot >= 0) {
+            GeoRec r;
+            int zmask = 0;
+            const int res = walk_move<F32>(mv, j, r, zmask, qfx, qfy, qx, qy, seed, steps, flags, ls.c);
+            if (res != 0) {
+                sj[slot] = res == 1 ? j : -1;
+                sz[slot] = (int8_t)zmask;
+                ls.add_walk(res == 1, steps, flags);
+                slot = -1;
+            }
         }
     }
-    if (d >= n_iter)
-        return;
-    // the foot in the records' float frame, as the chart was built
-    const float fx = F32 ? (float)qx : (float)((double)qx - mv.fc.cx);
-    const float fy = F32 ? (float)qy : (float)((double)qy - mv.fc.cy);
-    if (!NET) {
-        const int bu = upper_index(qx_tab, g, fx);
-        const int bv = upper_index(qy_tab + (int64_t)bu * g, g, fy);
-        j = table[(int64_t)bu * g + bv];
+    wave_lds_sync();
+    // 3. tie rule, weights, values
+#pragma unroll
+    for (int rr = 0; rr < RP; ++rr) {
+        const int64_t gbase = base + rr * kWave;
+        if (gbase >= n_iter)
+            break;
+        const int sl = rr * kWave + lane;
+        const int64_t d = gbase + lane;
+        int32_t row[NA];
+        V wgt[NA];
+        row[0] = -1;
+#pragma unroll
+        for (int a = 1; a < NA; ++a)
+            row[a] = 0;
+#pragma unroll
+        for (int a = 0; a < NA; ++a)
+            wgt[a] = (V)0;
+        if (d < n_iter) {
+            const int32_t e0 = sj[sl];
+            int32_t elem = -1;
+            if (e0 >= 0) {
+                const R2 q = sq[sl];
+                const WalkResult<R> w = finish_walk<F32>(mv, e0, mv.geo[e0], (int)sz[sl], 0, 0, q.x, q.y);
+                ls.add_ties(w.flags);
+                elem = w.elem;
+                lagrange<R, V, NA>(mv, w.elem, w.v, w.th, row, wgt);
+            }
+            if (write_prev)
+                mv.prev[d] = elem;
+        }
+        const int nf = (int)min<int64_t>(kWave, n_iter - gbase);
+        wave_interp<V, NA>(row, wgt, nf, vin, k, vout, out_map, gbase, (V)outside);
     }
-    // Per-foot choice between the proposal and the node's own steered start
-    // (strategy (a)): the triangle whose centroid is nearer the foot.
-    const R2 x = ((const R2 *)mv.dof_xy)[d];
-    const int32_t js = quadrant_start(mv.qstart[d], (float)(qx - x.x), (float)(qy - x.y));
-    const GeoRec rs = mv.geo[js], rp = mv.geo[j];
-    const float sx = (rs.p[0].x + rs.p[1].x + rs.p[2].x) * (1.f / 3.f) - fx;
-    const float sy = (rs.p[0].y + rs.p[1].y + rs.p[2].y) * (1.f / 3.f) - fy;
-    const float px = (rp.p[0].x + rp.p[1].x + rp.p[2].x) * (1.f / 3.f) - fx;
-    const float py = (rp.p[0].y + rp.p[1].y + rp.p[2].y) * (1.f / 3.f) - fy;
-    start[d] = px * px + py * py < sx * sx + sy * sy ? j : js;
+    if (st)
+        flush_stats(ls, st);
+}
+
+template <bool F32, typename V, int NA, int RP, bool NET>
+__global__ void __launch_bounds__(kBlock)
+    k_step_rp(MeshView mv, FieldDev f, double dt, double t_np1, int scheme, int mode, const int32_t *__restrict__ start,
+              const V *__restrict__ vin, int k, V *__restrict__ vout, double outside, int write_prev,
+              const int32_t *__restrict__ out_map, int64_t n_iter, DevStats *st)
+{
+    constexpr int W = kBlock / kWave, C = kWave * RP;
+    __shared__ typename CT<F32>::R2 sq[W][C];
+    __shared__ int32_t sj[W][C];
+    __shared__ int8_t sz[W][C];
+    const int w = threadIdx.x / kWave;
+    const int64_t base = xcd_tile(blockIdx.x, gridDim.x) * (int64_t)(kBlock * RP) + (int64_t)w * C;
+    step_chunk<F32, V, NA, RP, NET>(mv, f, dt, t_np1, scheme, mode, start, vin, k, vout, outside, write_prev, out_map,
+                               n_iter, base, sq[w], sj[w], sz[w], st);
 }
 
 // Training pairs: for the DOFs dofs[i] (internal positions) the plain walk
@@ -1129,9 +1464,80 @@ hipError_t launch_step(const DevMesh &m, hipStream_t st, const FieldDev &f0, dou
     unsigned g;
     if (!tiles_for(n_iter, g))
         return hipErrorInvalidValue;
-#define SLW_STEP(F32, V, NA)                                                                                   \
-    hipLaunchKernelGGL((k_step<F32, V, NA>), dim3(g), dim3(kBlock), 0, st, mv, f, dt, scheme, mode, start,    \
+    const int rp = m.repack;
+    if ((mode == SLW_START_LEARNED || mode == SLW_START_CHART) && rp == 0) {
+        // one foot per lane: the proposals come from their own kernel
+        hipError_t e = launch_chart_start(m, st, f0, t_n + dt, dt, scheme, nullptr, n_iter,
+                                          mode == SLW_START_LEARNED, m.learned_start);
+        if (e != hipSuccess)
+            return e;
+        start = m.learned_start;
+    }
+    if (mode == SLW_START_NEIGHBOR) {
+        const int L = m.chain;
+        const int64_t t = (n_iter + (int64_t)kWave * L - 1) / ((int64_t)kWave * L);
+        if (t > (int64_t)INT32_MAX)
+            return hipErrorInvalidValue;
+        const unsigned gc = (unsigned)(t < 1 ? 1 : t);
+#define SLW_CHAIN_L(F32, V, NA, LL)                                                                               \
+    hipLaunchKernelGGL((k_step_chain<F32, V, NA, LL>), dim3(gc), dim3(kWave), 0, st, mv, f, dt, scheme,           \
+                       (const V *)v_in, k, (V *)v_out, outside, out_map, n_iter, stats)
+#define SLW_CHAIN(F32, V, NA)                                \
+    do {                                                     \
+        switch (L) {                                         \
+        case 2: SLW_CHAIN_L(F32, V, NA, 2); break;           \
+        case 8: SLW_CHAIN_L(F32, V, NA, 8); break;           \
+        case 16: SLW_CHAIN_L(F32, V, NA, 16); break;         \
+        default: SLW_CHAIN_L(F32, V, NA, 4); break;          \
+        }                                                    \
+    } while (0)
+        if (m.coords_f32) {
+            if (vdtype == SLW_F32) {
+                if (order == 1) SLW_CHAIN(true, float, 3); else SLW_CHAIN(true, float, 6);
+            } else {
+                if (order == 1) SLW_CHAIN(true, double, 3); else SLW_CHAIN(true, double, 6);
+            }
+        } else {
+            if (vdtype == SLW_F32) {
+                if (order == 1) SLW_CHAIN(false, float, 3); else SLW_CHAIN(false, float, 6);
+            } else {
+                if (order == 1) SLW_CHAIN(false, double, 3); else SLW_CHAIN(false, double, 6);
+            }
+        }
+#undef SLW_CHAIN
+#undef SLW_CHAIN_L
+        return hipGetLastError();
+    }
+    // the learned start's fused kernel has one chunk size: 4 feet per lane
+    const int64_t t4 = (n_iter + (int64_t)kBlock * 4 - 1) / ((int64_t)kBlock * 4);
+    const unsigned g4 = (unsigned)(t4 < 1 ? 1 : t4);
+    if (rp > 0) {
+        const int64_t t = (n_iter + (int64_t)kBlock * rp - 1) / ((int64_t)kBlock * rp);
+        if (t > (int64_t)INT32_MAX)
+            return hipErrorInvalidValue;
+        g = (unsigned)(t < 1 ? 1 : t);
+    }
+#define SLW_STEP_RP(F32, V, NA, RP)                                                                             \
+    hipLaunchKernelGGL((k_step_rp<F32, V, NA, RP, false>), dim3(g), dim3(kBlock), 0, st, mv, f, dt, t_n + dt, scheme,   \
+                       mode, start,                                                                             \
                        (const V *)v_in, k, (V *)v_out, outside, (int)write_prev, out_map, n_iter, stats)
+#define SLW_STEP(F32, V, NA)                                                                                   \
+    do {                                                                                                       \
+    if (rp > 0 && mode == SLW_START_LEARNED) {                                                                 \
+        hipLaunchKernelGGL((k_step_rp<F32, V, NA, 4, true>), dim3(g4), dim3(kBlock), 0, st, mv, f, dt, t_n + dt, \
+                           scheme, mode, start, (const V *)v_in, k, (V *)v_out, outside, (int)write_prev,      \
+                           out_map, n_iter, stats);                                                            \
+        break;                                                                                                 \
+    }                                                                                                          \
+    switch (rp) {                                                                                              \
+    case 2: SLW_STEP_RP(F32, V, NA, 2); break;                                                                 \
+    case 4: SLW_STEP_RP(F32, V, NA, 4); break;                                                                 \
+    case 8: SLW_STEP_RP(F32, V, NA, 8); break;                                                                 \
+    default:                                                                                                   \
+        hipLaunchKernelGGL((k_step<F32, V, NA>), dim3(g), dim3(kBlock), 0, st, mv, f, dt, scheme, mode, start, \
+                           (const V *)v_in, k, (V *)v_out, outside, (int)write_prev, out_map, n_iter, stats);  \
+    }                                                                                                          \
+    } while (0)
     if (m.coords_f32) {
         if (vdtype == SLW_F32) {
             if (order == 1) SLW_STEP(true, float, 3); else SLW_STEP(true, float, 6);
@@ -1146,6 +1552,7 @@ hipError_t launch_step(const DevMesh &m, hipStream_t st, const FieldDev &f0, dou
         }
     }
 #undef SLW_STEP
+#undef SLW_STEP_RP
     return hipGetLastError();
 }
 
@@ -1213,8 +1620,7 @@ hipError_t launch_chart_start(const DevMesh &m, hipStream_t st, const FieldDev &
 {
     if (n_iter <= 0)
         return hipSuccess;
-    const slw_mlp *n = m.mlp;
-    if (!m.chart_table || (use_net && !n))
+    if (!m.chart_table || (use_net && !m.mlp))
         return hipErrorInvalidValue;
     unsigned g;
     if (!tiles_for(n_iter, g))
@@ -1222,12 +1628,9 @@ hipError_t launch_chart_start(const DevMesh &m, hipStream_t st, const FieldDev &
     MeshView mv = view_of(m);
     FieldDev f = f0;
     field_time_factors(f, t_np1, dt);
-    const uint16_t *wp = n ? n->wpack : nullptr;
-    const float *bi = n ? n->bias : nullptr, *no = n ? n->norm : nullptr;
 #define SLW_CSTART(F32, NET, R2)                                                                                  \
     hipLaunchKernelGGL((k_chart_start<F32, NET>), dim3(g), dim3(kBlock), 0, st, mv, f, dt, t_np1, scheme,        \
-                       (const R2 *)feet_in, wp, bi, no, m.chart_node, m.chart_qx, m.chart_qy, m.chart_table,     \
-                       m.chart_g, n_iter, start)
+                       (const R2 *)feet_in, n_iter, start)
     if (m.coords_f32) {
         if (use_net) SLW_CSTART(true, true, float2); else SLW_CSTART(true, false, float2);
     } else {

@@ -32,7 +32,7 @@ _lib = ctypes.CDLL(str(LIB_PATH))
 SLW_OK = 0
 SLW_F64, SLW_F32 = 0, 1
 SLW_EULER, SLW_RK2 = 0, 1
-START_STEERED, START_GIVEN, START_PREV, START_FIXED, START_LEARNED, START_CHART = 0, 1, 2, 3, 4, 5
+START_STEERED, START_GIVEN, START_PREV, START_FIXED, START_LEARNED, START_CHART, START_NEIGHBOR = 0, 1, 2, 3, 4, 5, 6
 COORDS_F32, P2, NO_REORDER, INTERNAL_ORDER = 0x1, 0x2, 0x4, 0x8
 FEET_IN = 0x1
 
@@ -95,6 +95,8 @@ _sig("slw_mesh_get_info", ctypes.c_int, [_vp, ctypes.POINTER(slw_mesh_info)])
 _sig("slw_mesh_dof_coords", ctypes.c_int, [_vp, _vp])
 _sig("slw_mesh_dof_order", ctypes.c_int, [_vp, _vp])
 _sig("slw_mesh_set_walk_limits", ctypes.c_int, [_vp, _i32, _i32])
+_sig("slw_mesh_set_repack", ctypes.c_int, [_vp, ctypes.c_int])
+_sig("slw_mesh_set_chain", ctypes.c_int, [_vp, ctypes.c_int])
 _sig("slw_locate", ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, _vp, _vp])
 _sig("slw_locate_feet", ctypes.c_int, [_vp, ctypes.POINTER(slw_field), _dbl, _dbl, ctypes.c_int, ctypes.c_int, _vp,
                                        _u32, _vp, _vp, _vp, _vp, ctypes.POINTER(slw_stats)])
@@ -140,7 +142,7 @@ MLP_PARAMS = 5 * 64 + 64 + 64 * 64 + 64 + 64 * 2 + 2
 
 EXPORTED = ["slw_status_string", "slw_last_error", "slw_ctx_create", "slw_ctx_set_stream", "slw_ctx_destroy",
             "slw_mesh_upload", "slw_mesh_check", "slw_mesh_free", "slw_mesh_get_info", "slw_mesh_dof_coords", "slw_mesh_dof_order",
-            "slw_mesh_set_walk_limits", "slw_locate", "slw_locate_feet", "slw_interpolate", "slw_step",
+            "slw_mesh_set_walk_limits", "slw_mesh_set_repack", "slw_mesh_set_chain", "slw_locate", "slw_locate_feet", "slw_interpolate", "slw_step",
             "slw_permute_rows", "slw_orient_sign_host",
             "slw_float_filter_host", "slw_batch_create", "slw_batch_free", "slw_batch_set_fields",
             "slw_batch_set_values", "slw_batch_set_step", "slw_batch_get_step", "slw_batch_set_schedule",
@@ -289,6 +291,12 @@ class Mesh:
 
     def set_walk_limits(self, step_cap: int = 0, hard_limit: int = 0):
         _check(_lib.slw_mesh_set_walk_limits(self.h, step_cap, hard_limit), "slw_mesh_set_walk_limits")
+
+    def set_repack(self, feet_per_lane: int):
+        _check(_lib.slw_mesh_set_repack(self.h, int(feet_per_lane)), "slw_mesh_set_repack")
+
+    def set_chain(self, length: int):
+        _check(_lib.slw_mesh_set_chain(self.h, int(length)), "slw_mesh_set_chain")
 
     def free(self):
         if getattr(self, "h", None) and getattr(self.ctx, "h", None):

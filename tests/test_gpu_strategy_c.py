@@ -1,0 +1,65 @@
+"""Strategy (c) of Section 3 (start from the element found for a
+neighbouring node, along Morton chains): the oracle's values, the steered
+start's bits, every chain length, ragged tails; and shorter walks than
+strategy (a) once the Courant number is large."""
+import numpy as np
+import pytest
+
+from paper_2104_09189_amd import inputs as I
+from gpu_util import ctx as _ctx, dev, host, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2104_09189_amd import slwalk
+    return slwalk
+
+
+@pytest.fixture(scope="module")
+def C(S):
+    return _ctx()
+
+
+@pytest.mark.parametrize("flags", [0, 0x8, 0x1])
+def test_neighbor_start_same_bits_every_chain(S, C, orc, flags):
+    xy, tri = I.permute_mesh(*I.jittered_grid(61, 701), 5)   # 3,721 nodes: ragged chains
+    fld, dt = I.swirl(1.0), 8.0 / 60
+    mesh = S.Mesh(C, xy, tri, flags)
+    perm = mesh.dof_order() if flags & 0x8 else np.arange(mesh.n_dofs)
+    v0 = np.stack([I.gaussian_hill(xy), xy[:, 0] * xy[:, 1]], axis=1)[perm].astype(np.float32)
+    ref, st_a = mesh.step(fld, 0.1, dt, S.SLW_RK2, dev(v0), stats=True)
+    ref = host(ref).copy()
+    for L in (2, 4, 8, 16):
+        mesh.set_chain(L)
+        v, st = mesh.step(fld, 0.1, dt, S.SLW_RK2, dev(v0), start_mode=S.START_NEIGHBOR, stats=True)
+        assert np.array_equal(host(v), ref), L
+        assert st["feet"] == st_a["feet"] and st["outside"] == st_a["outside"]
+        assert st["walk_steps"] < st_a["walk_steps"], (L, st["walk_steps"], st_a["walk_steps"])
+    if not flags & 0x1:
+        o, _, _, _ = orc.sl_step(xy, tri, v0[np.argsort(perm)].astype(np.float64), fld, 0.1, dt, I.SCHEME_RK2)
+        assert rel_err(ref, o[perm], np.abs(v0).max()) < 1e-5
+
+
+def test_neighbor_start_p2_fp64_and_outside(S, C, orc):
+    xy, tri = I.jittered_grid(29, 702)
+    p2 = orc.P2Dofs(xy, tri)
+    mesh = S.Mesh(C, xy, tri, S.P2)
+    fld = I.constant(-0.25, 0.15)
+    v0 = I.gaussian_hill(p2.xy)[:, None]
+    mesh.set_chain(8)
+    v = host(mesh.step(fld, 0.0, 0.2, S.SLW_EULER, dev(v0), order=2, start_mode=S.START_NEIGHBOR,
+                       outside_value=3.0))
+    ref, _, _, _ = orc.sl_step(xy, tri, v0, fld, 0.0, 0.2, I.SCHEME_EULER, order=2, p2=p2, outside_value=3.0)
+    assert rel_err(v, ref, 1.0) < 1e-12
+    assert (v == 3.0).sum() > 50
+
+
+def test_neighbor_start_rejected_by_locate_feet(S, C):
+    xy, tri = I.jittered_grid(10, 703)
+    mesh = S.Mesh(C, xy, tri)
+    with pytest.raises(S.SlwError):
+        mesh.locate_feet(I.swirl(1.0), 0.1, 0.1, S.SLW_EULER, start_mode=S.START_NEIGHBOR)
+    with pytest.raises(S.SlwError):
+        mesh.set_chain(3)
