@@ -199,14 +199,68 @@ def interp(order: int, tri, elem, bary, v, n_vert: int, tri_edges=None, outside_
 
 
 # --------------------------------------------------------------------------
+# variable step at the boundary (remark after eq. (eulero)): a characteristic
+# that leaves the domain stops on the boundary, where Dirichlet data apply
+
+def boundary_edges(xy, tri) -> np.ndarray:
+    """Boundary edges (a, b), each directed with the domain on its left: the
+    edges that belong to one triangle only, taken in that triangle's
+    counter-clockwise order."""
+    xy, t = _f64(xy), np.array(tri, dtype=np.int64)
+    a, b, c = xy[t[:, 0]], xy[t[:, 1]], xy[t[:, 2]]
+    cw = (b[:, 0] - a[:, 0]) * (c[:, 1] - a[:, 1]) - (b[:, 1] - a[:, 1]) * (c[:, 0] - a[:, 0]) < 0
+    t[cw] = t[cw][:, [0, 2, 1]]
+    e = np.concatenate([t[:, [0, 1]], t[:, [1, 2]], t[:, [2, 0]]])
+    _, inv, cnt = np.unique(np.sort(e, axis=1), axis=0, return_inverse=True, return_counts=True)
+    return e[cnt[inv.ravel()] == 1]
+
+
+def boundary_crossing(xy, edges, x, q):
+    """theta in [0, 1] such that p = x + theta (q - x) is where the segment
+    from x (in the closed domain) to q leaves the domain, and p; found as the
+    smallest parameter over every boundary edge that the segment crosses
+    from inside to outside (edge parameter lambda in [0, 1]).  NaN where
+    there is none."""
+    xy, x, q = _f64(xy), _f64(x).reshape(-1, 2), _f64(q).reshape(-1, 2)
+    A, B = xy[edges[:, 0]], xy[edges[:, 1]]
+    e = B - A                                        # (nb, 2)
+    w = q - x                                        # (m, 2)
+    r = A[None, :, :] - x[:, None, :]                # (m, nb, 2)
+    den = w[:, None, 0] * e[None, :, 1] - w[:, None, 1] * e[None, :, 0]     # w x e > 0: outwards
+    with np.errstate(divide="ignore", invalid="ignore"):
+        th = (r[..., 0] * e[None, :, 1] - r[..., 1] * e[None, :, 0]) / den
+        la = (r[..., 0] * w[:, None, 1] - r[..., 1] * w[:, None, 0]) / den
+    ok = (den > 0) & (la >= 0) & (la <= 1) & (th >= -1e-12) & (th <= 1 + 1e-12)
+    th = np.where(ok, np.clip(th, 0.0, 1.0), np.inf)
+    theta = th.min(axis=1)
+    theta[~np.isfinite(theta)] = np.nan
+    p = x + theta[:, None] * w
+    return theta, p
+
+
+def boundary_value(bc, px, py, t):
+    """Dirichlet data: bc = (kind, params), kind 1 constant p0, kind 2
+    p0 + p1 x + p2 y + p3 t."""
+    kind, p = bc
+    p = list(p) + [0.0] * (4 - len(p))
+    if kind == 1:
+        return np.full_like(px, p[0])
+    return p[0] + p[1] * px + p[2] * py + p[3] * t
+
+
+# --------------------------------------------------------------------------
 # one step and a run of eq. (schema_trasp) / Algorithm 2
 
 def sl_step(xy, tri, v, fld, t_n: float, dt: float, scheme: int, order: int = 1,
-            p2: P2Dofs | None = None, outside_value: float = 0.0, q=None):
+            p2: P2Dofs | None = None, outside_value: float = 0.0, q=None, bc=None):
     """v^{n+1}_i = I[V^n](X^Delta(x_i, t_{n+1}; t_n)); returns (v_new, q, elem, bary).
 
     For order 2, `p2` gives the DOFs; feet are taken at every DOF.  If q is
     given it replaces the computed feet (index parity on identical points).
+    With boundary data bc = (kind, params), a DOF whose foot is outside the
+    domain gets g(p, t_{n+1} - theta dt) at the point p where the segment
+    from the DOF to its foot leaves the domain (for every field); else
+    outside_value.
     """
     pts = xy if order == 1 else p2.xy
     if q is None:
@@ -214,6 +268,13 @@ def sl_step(xy, tri, v, fld, t_n: float, dt: float, scheme: int, order: int = 1,
     elem, bary = locate(xy, tri, q)
     te = None if order == 1 else p2.tri_edges
     v_new = interp(order, tri, elem, bary, v, xy.shape[0], te, outside_value)
+    if bc is not None and bc[0] != 0:
+        out = np.nonzero((elem < 0) & np.isfinite(q).all(axis=1))[0]
+        if out.size:
+            theta, p = boundary_crossing(xy, boundary_edges(xy, tri), _f64(pts)[out], _f64(q)[out])
+            g = boundary_value(bc, p[:, 0], p[:, 1], t_n + dt - theta * dt)
+            hit = np.isfinite(theta)
+            v_new[out[hit]] = g[hit][:, None]
     return v_new, q, elem, bary
 
 

@@ -381,3 +381,75 @@ def test_bf16_rounding_and_adam_first_step():
     g = np.array([0.3, -2.0, 1e-3])
     p1, m, v = mlp.adam(np.zeros(3), g, np.zeros(3), np.zeros(3), 1, lr=0.01)
     assert np.allclose(p1, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# variable step at the boundary
+
+def test_boundary_crossing_closed_form_on_the_square(orc):
+    """The exit point of a segment from inside the unit square: for each side
+    the segment heads to, theta = (side - x) / (q - x); the exit is the
+    smallest of these."""
+    xy, tri = I.jittered_grid(9, 5)
+    e = orc.boundary_edges(xy, tri)
+    assert e.shape[0] == 4 * 8
+    A, B = xy[e[:, 0]], xy[e[:, 1]]
+    # every boundary edge lies on one side and runs counter-clockwise
+    mid = 0.5 * (A + B)
+    out_normal = np.stack([B[:, 1] - A[:, 1], A[:, 0] - B[:, 0]], axis=1)   # right of a -> b
+    assert ((out_normal * (mid - 0.5)).sum(axis=1) > 0).all()
+    rng = np.random.default_rng(17)
+    x = rng.uniform(0.05, 0.95, (400, 2))
+    q = x + rng.normal(0, 0.6, (400, 2))
+    outside = ((q < 0) | (q > 1)).any(axis=1)
+    x, q = x[outside], q[outside]
+    theta, p = orc.boundary_crossing(xy, e, x, q)
+    w = q - x
+    with np.errstate(divide="ignore"):
+        cand = np.stack([np.where(w[:, 0] > 0, (1 - x[:, 0]) / w[:, 0], np.inf),
+                         np.where(w[:, 0] < 0, (0 - x[:, 0]) / w[:, 0], np.inf),
+                         np.where(w[:, 1] > 0, (1 - x[:, 1]) / w[:, 1], np.inf),
+                         np.where(w[:, 1] < 0, (0 - x[:, 1]) / w[:, 1], np.inf)], axis=1)
+    ref = cand.min(axis=1)
+    assert np.abs(theta - ref).max() < 1e-12
+    assert np.abs(p - (x + ref[:, None] * w)).max() < 1e-12
+    # the crossing is on the boundary
+    assert (np.minimum(np.minimum(p[:, 0], 1 - p[:, 0]), np.minimum(p[:, 1], 1 - p[:, 1])) < 1e-12).all()
+
+
+def test_boundary_node_with_outward_foot_stops_at_once(orc):
+    xy, tri = I.jittered_grid(7, 6)
+    e = orc.boundary_edges(xy, tri)
+    b = np.unique(e[:, 0])
+    x = xy[b]
+    q = x + (x - 0.5) * 0.3                           # outwards from the centre
+    theta, p = orc.boundary_crossing(xy, e, x, q)
+    assert np.abs(theta).max() < 1e-12 and np.abs(p - x).max() < 1e-12
+    # a segment entering the interior from a boundary node is not an exit
+    theta_in, _ = orc.boundary_crossing(xy, e, x, x + (0.5 - x) * 0.5)
+    assert np.isnan(theta_in).all()
+
+
+@pytest.mark.parametrize("scheme", [I.SCHEME_EULER, I.SCHEME_RK2])
+def test_variable_step_reproduces_the_exact_solution(orc, scheme):
+    """Constant advection of affine data u(x, t) = U(x - a t) with the exact
+    solution as inflow data: inside, P1 reproduces the affine profile at the
+    exact foot; outside, the datum at the crossing point and crossing time is
+    u(x - theta a dt, t_{n+1} - theta dt) = u(x, t_{n+1}).  Every node gets
+    the exact value."""
+    xy, tri = I.jittered_grid(21, 8)
+    ax, ay = 0.3, -0.2
+    c0, c1, c2 = 0.7, -1.3, 2.1
+    t_n, dt = 0.4, 0.25
+
+    def u(x, y, t):
+        return c0 + c1 * (x - ax * t) + c2 * (y - ay * t)
+
+    bc = (2, (c0, c1, c2, -(c1 * ax + c2 * ay)))
+    v0 = u(xy[:, 0], xy[:, 1], t_n)[:, None]
+    v, q, elem, _ = orc.sl_step(xy, tri, v0, I.constant(ax, ay), t_n, dt, scheme, bc=bc)
+    assert (elem < 0).sum() > 50
+    assert np.abs(v[:, 0] - u(xy[:, 0], xy[:, 1], t_n + dt)).max() < 1e-13
+    # without boundary data those nodes get the outside value instead
+    v2, _, _, _ = orc.sl_step(xy, tri, v0, I.constant(ax, ay), t_n, dt, scheme, outside_value=-5.0)
+    assert (v2[elem < 0] == -5.0).all()
