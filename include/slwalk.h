@@ -191,6 +191,20 @@ slw_status slw_mesh_set_walk_limits(slw_mesh *mesh, int32_t step_cap, int32_t ha
  * maximum.  Results are identical for every setting.  0 selects the
  * library's default. */
 slw_status slw_mesh_set_repack(slw_mesh *mesh, int feet_per_lane);
+/* Boundary data for feet that leave the domain (slw_step).  The paper
+ * treats Dirichlet conditions by a variable step that stops characteristics
+ * on the boundary (remark after eq. eulero).  With kind != SLW_BC_NONE a
+ * DOF x whose foot q lies outside the domain gets the value
+ * g(p, t_{n+1} - theta dt), where p = x + theta (q - x), theta in [0, 1], is
+ * the point where the segment from x to q leaves the domain, and
+ * g = p[0] (SLW_BC_CONSTANT) or g = p[0] + p[1] px + p[2] py + p[3] t
+ * (SLW_BC_AFFINE), for every field.  SLW_BC_NONE (the default) gives such
+ * feet outside_value.  Applied by the one-foot-per-lane step kernel (the
+ * lane schedule is ignored while set); not available with
+ * SLW_START_NEIGHBOR (SLW_E_UNSUPPORTED).  p_h: 4 doubles (host), ignored for
+ * SLW_BC_NONE. */
+enum { SLW_BC_NONE = 0, SLW_BC_CONSTANT = 1, SLW_BC_AFFINE = 2 };
+slw_status slw_mesh_set_boundary(slw_mesh *mesh, int kind, const double *p_h);
 /* Strategy (c) of Section 3 (SLW_START_NEIGHBOR) starts a walk from the
  * element that contains an adjacent node's foot.  The spanning forest used
  * here is made of chains of `length` consecutive nodes of the internal

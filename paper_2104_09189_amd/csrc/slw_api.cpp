@@ -291,6 +291,18 @@ slw_status slw_mesh_set_repack(slw_mesh *mesh, int feet_per_lane)
     return SLW_OK;
 }
 
+slw_status slw_mesh_set_boundary(slw_mesh *mesh, int kind, const double *p_h)
+{
+    if (!mesh)
+        return set_error(SLW_E_ARG, "mesh is NULL");
+    if (kind < SLW_BC_NONE || kind > SLW_BC_AFFINE || (kind != SLW_BC_NONE && !p_h))
+        return set_error(SLW_E_ARG, "slw_mesh_set_boundary: unknown kind or missing parameters");
+    mesh->m.bc_kind = kind;
+    for (int i = 0; i < 4; ++i)
+        mesh->m.bc_p[i] = kind == SLW_BC_NONE ? 0.0 : p_h[i];
+    return SLW_OK;
+}
+
 slw_status slw_mesh_set_chain(slw_mesh *mesh, int length)
 {
     if (!mesh)
@@ -422,6 +434,8 @@ slw_status slw_step(slw_mesh *mesh, const slw_field *field, double t_n, double d
         vin_int = ctx->work;
         out_map = m.dof_user;
     }
+    if (m.bc_kind && start_mode == SLW_START_NEIGHBOR)
+        return set_error(SLW_E_UNSUPPORTED, "boundary data with SLW_START_NEIGHBOR");
     const bool write_prev = start_mode == SLW_START_PREV;
     FieldDev fd = to_dev(field);
     st = hip_check(launch_step(m, ctx->stream, fd, t_n, dt, scheme, order, start_mode, start, vin_int, vdtype, k,

@@ -50,6 +50,12 @@ struct DevMesh {
     int32_t *prev_elem = nullptr; // [n_dofs] internal tri of the last location (strategy b)
     int32_t *jump = nullptr;      // [jump_g * jump_g] bucket grid of start triangles (internal)
     int jump_g = 1;
+    int32_t *bnext = nullptr;     // [n_nodes] next boundary node, counter-clockwise (-1: interior node)
+    int32_t *bprev = nullptr;     // [n_nodes] previous boundary node
+    int64_t n_boundary = 0;
+    // boundary data for feet outside the domain (variable step); kind 0: none
+    int bc_kind = 0;
+    double bc_p[4] = {0, 0, 0, 0};
     // chart starts (learned and exact): chart coordinates of triangle
     // centroids and of DOFs, the start table, the quantile tables that give
     // a point's chart cell, the attached network and a start workspace
@@ -166,6 +172,11 @@ struct MeshView {
     double bb[4];
     FilterConst fc;
     int32_t step_cap, hard_limit;
+    // variable step at the boundary (bc_kind 0: off)
+    const int32_t *bnext, *bprev;
+    int64_t n_boundary;
+    int bc_kind;
+    double bc_p[4];
     // chart starts (null without a chart / network)
     const float2 *chart_node;
     const float *chart_qx, *chart_qy;

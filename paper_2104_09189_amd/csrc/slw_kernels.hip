@@ -126,6 +126,12 @@ MeshView view_of(const DevMesh &m)
     v.fc = m.fc;
     v.step_cap = m.step_cap;
     v.hard_limit = m.hard_limit;
+    v.bnext = m.bnext;
+    v.bprev = m.bprev;
+    v.n_boundary = m.n_boundary;
+    v.bc_kind = m.bc_kind;
+    for (int i = 0; i < 4; ++i)
+        v.bc_p[i] = m.bc_p[i];
     v.chart_node = m.chart_node;
     v.chart_qx = m.chart_qx;
     v.chart_qy = m.chart_qy;
@@ -273,7 +279,8 @@ template <typename R>
 struct WalkResult {
     int32_t elem;   // internal triangle id, -1 outside
     int32_t steps;  // element changes
-    int32_t flags;  // bit0 fallback walk, bit1 hard limit, bit2 edge tie, bit3 vertex tie
+    int32_t flags;  // bit0 fallback walk, bit1 hard limit, bit2 edge tie, bit3 vertex tie,
+                    // bit4 left the domain through the boundary edge v[0] -> v[1]
     int32_t v[3];   // internal vertex DOF ids of elem
     R th[3];        // barycentric coordinates in the internal (counter-clockwise) vertex order of elem
 };
@@ -293,8 +300,8 @@ __device__ inline WalkResult<R> outside_result(int32_t steps, int32_t flags)
 // One move of the barycentric walk of Section 2.2 from triangle j towards
 // the foot q: 0 = moved (j is the next triangle), 1 = stopped (every
 // coordinate >= 0: r is j's record, zmask has bit k set when s_k = 0),
-// 2 = outside (a negative coordinate across a boundary edge, or the hard
-// step limit: then flags gets bits 0 and 1).
+// 2 = outside (a negative coordinate across boundary edge zmask of r; or
+// the hard step limit: then zmask = -1 and flags gets bits 0 and 1).
 template <bool F32>
 __device__ inline int walk_move(const MeshView &mv, int32_t &j, GeoRec &r, int &zmask, float qfx, float qfy,
                                 typename CT<F32>::R qx, typename CT<F32>::R qy, uint32_t seed, int32_t &steps,
@@ -309,11 +316,16 @@ __device__ inline int walk_move(const MeshView &mv, int32_t &j, GeoRec &r, int &
         zmask = (int)(s[0] == 0) | ((int)(s[1] == 0) << 1) | ((int)(s[2] == 0) << 2);
         return 1;
     }
-    // a negative side on the boundary: the foot is outside the (convex) domain
-    if ((n0 && r.nb[0] < 0) || (n1 && r.nb[1] < 0) || (n2 && r.nb[2] < 0))
+    // a negative side on the boundary: the foot is outside the (convex) domain;
+    // zmask tells through which edge
+    const bool x0 = n0 && r.nb[0] < 0, x1 = n1 && r.nb[1] < 0, x2 = n2 && r.nb[2] < 0;
+    if (x0 || x1 || x2) {
+        zmask = x0 ? 0 : (x1 ? 1 : 2);
         return 2;
+    }
     if (steps >= mv.hard_limit) {
         flags |= 3;
+        zmask = -1;
         return 2;
     }
     int k;
@@ -415,8 +427,15 @@ __device__ WalkResult<typename CT<F32>::R> walk(const MeshView &mv, int32_t j, t
         const int st = walk_move<F32>(mv, j, r, zmask, qfx, qfy, qx, qy, seed, steps, flags, c);
         if (st == 1)
             break;
-        if (st == 2)
-            return outside_result<R>(steps, flags);
+        if (st == 2) {
+            WalkResult<R> w = outside_result<R>(steps, flags);
+            if (zmask >= 0) {  // the boundary edge opposite vertex zmask, counter-clockwise
+                w.v[0] = sel3(zmask, r.v[1], r.v[2], r.v[0]);
+                w.v[1] = sel3(zmask, r.v[2], r.v[0], r.v[1]);
+                w.flags |= 16;
+            }
+            return w;
+        }
     }
     return finish_walk<F32>(mv, j, r, zmask, steps, flags, qx, qy);
 }
@@ -721,7 +740,7 @@ __device__ inline void wave_interp(const int32_t row[NA], const V wgt[NA], int n
             if (vec) {
                 VV acc = vv_zero<VV>();
                 if (rr[0] < 0) {
-                    acc = vv_fill(outside);
+                    acc = vv_fill(rr[0] == -2 ? ww[0] : outside);  // -2: boundary value in the first weight
                 } else {
 #pragma unroll
                     for (int a = 0; a < NA; ++a)
@@ -729,7 +748,7 @@ __device__ inline void wave_interp(const int32_t row[NA], const V wgt[NA], int n
                 }
                 *((VV *)(vout + o * (int64_t)k) + c) = acc;
             } else {
-                V acc = outside;
+                V acc = rr[0] == -2 ? ww[0] : outside;
                 if (rr[0] >= 0) {
                     acc = (V)0;
 #pragma unroll
@@ -785,12 +804,66 @@ __global__ void __launch_bounds__(kBlock)
     wave_interp<V, NA>(row, wgt, nf, vin, k, vout, nullptr, base, (V)outside);
 }
 
+// Variable step at the boundary: a characteristic that leaves the domain is
+// stopped where it crosses the boundary (the treatment of Dirichlet
+// conditions mentioned after eq. (eulero)).  The segment x -> q from the DOF
+// to its foot is intersected with the boundary loop, starting at the edge
+// a -> b through which the walk left and moving along the loop until the
+// crossing lies on the current edge; the value is the boundary datum at the
+// crossing point and at the time the characteristic passes there,
+// t_{n+1} - theta dt.  Returns false (no crossing found) only on degenerate
+// input; the caller then keeps the outside value.
+__device__ inline bool boundary_value(const MeshView &mv, bool f32, double xx, double xy, double qx, double qy,
+                                      int32_t a, int32_t b, double t_np1, double dt, double &g)
+{
+    const double wx = qx - xx, wy = qy - xy;
+    for (int64_t it = 0; it <= mv.n_boundary + 1 && a >= 0 && b >= 0; ++it) {
+        double ax, ay, bx, by;
+        if (f32) {
+            const float2 A = ((const float2 *)mv.dof_xy)[a], B = ((const float2 *)mv.dof_xy)[b];
+            ax = A.x, ay = A.y, bx = B.x, by = B.y;
+        } else {
+            const double2 A = ((const double2 *)mv.dof_xy)[a], B = ((const double2 *)mv.dof_xy)[b];
+            ax = A.x, ay = A.y, bx = B.x, by = B.y;
+        }
+        const double ex = bx - ax, ey = by - ay, rx = ax - xx, ry = ay - xy;
+        const double den = wx * ey - wy * ex;  // w x e > 0: the segment leaves across this edge's line
+        if (den > 0.0) {
+            const double la = (rx * wy - ry * wx) / den;
+            if (la < 0.0) {
+                b = a;
+                a = mv.bprev[a];
+                continue;
+            }
+            if (la > 1.0) {
+                a = b;
+                b = mv.bnext[b];
+                continue;
+            }
+            double th = (rx * ey - ry * ex) / den;
+            th = th < 0.0 ? 0.0 : (th > 1.0 ? 1.0 : th);
+            const double px = xx + th * wx, py = xy + th * wy, t = t_np1 - th * dt;
+            g = mv.bc_kind == 1 ? mv.bc_p[0] : mv.bc_p[0] + mv.bc_p[1] * px + mv.bc_p[2] * py + mv.bc_p[3] * t;
+            return true;
+        }
+        // parallel to (or entering across) this edge's line: move towards q
+        if ((qx - ax) * ex + (qy - ay) * ey < 0.0) {
+            b = a;
+            a = mv.bprev[a];
+        } else {
+            a = b;
+            b = mv.bnext[b];
+        }
+    }
+    return false;
+}
+
 // The fused step (Algorithm 2, one pass of its loop) for the 64 DOFs
 // [base, base + 64) of one wavefront: one lane per foot for foot -> start ->
 // walk -> tie rule -> weights; then the wavefront computes its feet's values
 // cooperatively.  Every lane of the wavefront calls it.
 template <bool F32, typename V, int NA>
-__device__ inline void step_wave(const MeshView &mv, const FieldDev &f, double dt, int scheme, int mode,
+__device__ inline void step_wave(const MeshView &mv, const FieldDev &f, double dt, double t_np1, int scheme, int mode,
                                  const int32_t *__restrict__ start, const V *__restrict__ vin, int k,
                                  V *__restrict__ vout, double outside, int write_prev,
                                  const int32_t *__restrict__ out_map, int64_t n_iter, int64_t base, DevStats *st)
@@ -813,7 +886,9 @@ __device__ inline void step_wave(const MeshView &mv, const FieldDev &f, double d
         R qx, qy;
         foot_of<R>(f, scheme, x.x, x.y, (R)dt, qx, qy);
         WalkResult<R> w = outside_result<R>(0, 0);
-        if (in_box<R>(qx, qy, mv.bb)) {
+        // with boundary data every finite foot is walked (to learn where it leaves)
+        const bool run = mv.bc_kind ? (isfinite((double)qx) && isfinite((double)qy)) : in_box<R>(qx, qy, mv.bb);
+        if (run) {
             const int64_t api = (mode == SLW_START_GIVEN && !mv.internal_order) ? mv.dof_user[d] : d;
             const int32_t j0 = start_for<F32>(mv, d, api, mode, start, (float)(qx - x.x), (float)(qy - x.y));
             w = walk<F32>(mv, j0, qx, qy, (uint32_t)d * 2654435761u, ls.c);
@@ -822,8 +897,16 @@ __device__ inline void step_wave(const MeshView &mv, const FieldDev &f, double d
             mv.prev[d] = w.elem;
         if (st)
             ls.add(w);
-        if (w.elem >= 0)
+        if (w.elem >= 0) {
             lagrange<R, V, NA>(mv, w.elem, w.v, w.th, row, wgt);
+        } else if (mv.bc_kind && (w.flags & 16)) {
+            double gv;
+            if (boundary_value(mv, F32, (double)x.x, (double)x.y, (double)qx, (double)qy, w.v[0], w.v[1], t_np1,
+                               dt, gv)) {
+                row[0] = -2;  // value given in wgt[0]
+                wgt[0] = (V)gv;
+            }
+        }
     }
     if (st)
         flush_stats(ls, st);
@@ -835,13 +918,13 @@ __device__ inline void step_wave(const MeshView &mv, const FieldDev &f, double d
 
 template <bool F32, typename V, int NA>
 __global__ void __launch_bounds__(kBlock)
-    k_step(MeshView mv, FieldDev f, double dt, int scheme, int mode, const int32_t *__restrict__ start,
+    k_step(MeshView mv, FieldDev f, double dt, double t_np1, int scheme, int mode, const int32_t *__restrict__ start,
            const V *__restrict__ vin, int k, V *__restrict__ vout, double outside, int write_prev,
            const int32_t *__restrict__ out_map, int64_t n_iter, DevStats *st)
 {
     const int64_t base = xcd_tile(blockIdx.x, gridDim.x) * kBlock + (threadIdx.x & ~(kWave - 1));
-    step_wave<F32, V, NA>(mv, f, dt, scheme, mode, start, vin, k, vout, outside, write_prev, out_map, n_iter, base,
-                          st);
+    step_wave<F32, V, NA>(mv, f, dt, t_np1, scheme, mode, start, vin, k, vout, outside, write_prev, out_map, n_iter,
+                          base, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -975,8 +1058,8 @@ __device__ inline void batch_tile(const BatchItem *__restrict__ items, int n_ite
     const V *vin = (const V *)(even ? it.va : it.vb);
     V *vout = (V *)(even ? it.vb : it.va);
     const int64_t base = (tile - it.tile0) * BS + (threadIdx.x & ~(kWave - 1));
-    step_wave<F32, V, 3>(it.mv, f, it.dt, scheme, SLW_START_STEERED, nullptr, vin, k, vout, outside, 0, nullptr,
-                         it.n_iter, base, st);
+    step_wave<F32, V, 3>(it.mv, f, it.dt, it.t0 + (double)(step + 1) * it.dt, scheme, SLW_START_STEERED, nullptr,
+                         vin, k, vout, outside, 0, nullptr, it.n_iter, base, st);
 }
 
 // schedule 0: one workgroup per tile, XCD-contiguous ranges of the
@@ -1464,7 +1547,10 @@ hipError_t launch_step(const DevMesh &m, hipStream_t st, const FieldDev &f0, dou
     unsigned g;
     if (!tiles_for(n_iter, g))
         return hipErrorInvalidValue;
-    const int rp = m.repack;
+    // boundary data are applied by the one-foot-per-lane kernel only
+    const int rp = m.bc_kind ? 0 : m.repack;
+    if (m.bc_kind && mode == SLW_START_NEIGHBOR)
+        return hipErrorNotSupported;
     if ((mode == SLW_START_LEARNED || mode == SLW_START_CHART) && rp == 0) {
         // one foot per lane: the proposals come from their own kernel
         hipError_t e = launch_chart_start(m, st, f0, t_n + dt, dt, scheme, nullptr, n_iter,
@@ -1534,8 +1620,8 @@ hipError_t launch_step(const DevMesh &m, hipStream_t st, const FieldDev &f0, dou
     case 4: SLW_STEP_RP(F32, V, NA, 4); break;                                                                 \
     case 8: SLW_STEP_RP(F32, V, NA, 8); break;                                                                 \
     default:                                                                                                   \
-        hipLaunchKernelGGL((k_step<F32, V, NA>), dim3(g), dim3(kBlock), 0, st, mv, f, dt, scheme, mode, start, \
-                           (const V *)v_in, k, (V *)v_out, outside, (int)write_prev, out_map, n_iter, stats);  \
+        hipLaunchKernelGGL((k_step<F32, V, NA>), dim3(g), dim3(kBlock), 0, st, mv, f, dt, t_n + dt, scheme, mode, \
+                           start, (const V *)v_in, k, (V *)v_out, outside, (int)write_prev, out_map, n_iter, stats); \
     }                                                                                                          \
     } while (0)
     if (m.coords_f32) {

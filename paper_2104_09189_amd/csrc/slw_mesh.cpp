@@ -134,7 +134,7 @@ void free_mesh(DevMesh &m)
 {
     void *ptrs[] = {m.geo, m.tri_uf, m.tedge, m.dof_xy, m.qstart, m.vmin, m.dof_user,
                     m.dof_int, m.tri_int, m.prev_elem, m.jump, m.chart_uv, m.chart_node, m.chart_table,
-                    m.chart_qx, m.chart_qy, m.learned_start};
+                    m.chart_qx, m.chart_qy, m.learned_start, m.bnext, m.bprev};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -563,6 +563,18 @@ slw_status build_mesh(slw_ctx *ctx, const double *xy, int64_t n, const int32_t *
     std::vector<int32_t> prev(ndof, -1);
     UP(prev, m.prev_elem);
     UP(jump, m.jump);
+    {
+        // boundary loop (counter-clockwise, interior on the left) in internal node ids
+        std::vector<int32_t> bn(n, -1), bp(n, -1);
+        for (int64_t a = 0; a < n; ++a)
+            if (bnext[a] >= 0) {
+                bn[node_i[a]] = node_i[bnext[a]];
+                bp[node_i[bnext[a]]] = node_i[a];
+            }
+        UP(bn, m.bnext);
+        UP(bp, m.bprev);
+        m.n_boundary = n_bnd;
+    }
 #undef UP
     m.device_bytes = bytes;
     m.dof_xy_user_h = std::move(dof_user_xy);

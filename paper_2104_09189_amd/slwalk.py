@@ -33,6 +33,7 @@ SLW_OK = 0
 SLW_F64, SLW_F32 = 0, 1
 SLW_EULER, SLW_RK2 = 0, 1
 START_STEERED, START_GIVEN, START_PREV, START_FIXED, START_LEARNED, START_CHART, START_NEIGHBOR = 0, 1, 2, 3, 4, 5, 6
+BC_NONE, BC_CONSTANT, BC_AFFINE = 0, 1, 2
 COORDS_F32, P2, NO_REORDER, INTERNAL_ORDER = 0x1, 0x2, 0x4, 0x8
 FEET_IN = 0x1
 
@@ -97,6 +98,7 @@ _sig("slw_mesh_dof_order", ctypes.c_int, [_vp, _vp])
 _sig("slw_mesh_set_walk_limits", ctypes.c_int, [_vp, _i32, _i32])
 _sig("slw_mesh_set_repack", ctypes.c_int, [_vp, ctypes.c_int])
 _sig("slw_mesh_set_chain", ctypes.c_int, [_vp, ctypes.c_int])
+_sig("slw_mesh_set_boundary", ctypes.c_int, [_vp, ctypes.c_int, _vp])
 _sig("slw_locate", ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, _vp, _vp])
 _sig("slw_locate_feet", ctypes.c_int, [_vp, ctypes.POINTER(slw_field), _dbl, _dbl, ctypes.c_int, ctypes.c_int, _vp,
                                        _u32, _vp, _vp, _vp, _vp, ctypes.POINTER(slw_stats)])
@@ -142,7 +144,7 @@ MLP_PARAMS = 5 * 64 + 64 + 64 * 64 + 64 + 64 * 2 + 2
 
 EXPORTED = ["slw_status_string", "slw_last_error", "slw_ctx_create", "slw_ctx_set_stream", "slw_ctx_destroy",
             "slw_mesh_upload", "slw_mesh_check", "slw_mesh_free", "slw_mesh_get_info", "slw_mesh_dof_coords", "slw_mesh_dof_order",
-            "slw_mesh_set_walk_limits", "slw_mesh_set_repack", "slw_mesh_set_chain", "slw_locate", "slw_locate_feet", "slw_interpolate", "slw_step",
+            "slw_mesh_set_walk_limits", "slw_mesh_set_repack", "slw_mesh_set_chain", "slw_mesh_set_boundary", "slw_locate", "slw_locate_feet", "slw_interpolate", "slw_step",
             "slw_permute_rows", "slw_orient_sign_host",
             "slw_float_filter_host", "slw_batch_create", "slw_batch_free", "slw_batch_set_fields",
             "slw_batch_set_values", "slw_batch_set_step", "slw_batch_get_step", "slw_batch_set_schedule",
@@ -297,6 +299,13 @@ class Mesh:
 
     def set_chain(self, length: int):
         _check(_lib.slw_mesh_set_chain(self.h, int(length)), "slw_mesh_set_chain")
+
+    def set_boundary(self, kind: int, params=(0.0, 0.0, 0.0, 0.0)):
+        """Boundary data g for feet that leave the domain: BC_NONE, BC_CONSTANT
+        (g = p0) or BC_AFFINE (g = p0 + p1 x + p2 y + p3 t)."""
+        p = np.zeros(4, dtype=np.float64)
+        p[:len(params)] = params
+        _check(_lib.slw_mesh_set_boundary(self.h, int(kind), p.ctypes.data_as(_vp)), "slw_mesh_set_boundary")
 
     def free(self):
         if getattr(self, "h", None) and getattr(self.ctx, "h", None):
