@@ -9,8 +9,10 @@ fields sharing one location.  A step is one fused kernel launch over all
 nodes: foot, start element, barycentric walk, tie rule, weights, values.
 
 The headline is strategy (a) of the paper (the walk starts from the node's
-own incident triangle, here the one facing the foot).  Strategy (b) (start
-from the element found at the previous step) is measured beside it.
+own incident triangle, here the one facing the foot).  Strategies (b) (start
+from the element found at the previous step) and (c) (start from the element
+found for a neighbouring node) are measured beside it, then K-field reuse,
+the 64-mesh batch, and the learned start on the same mesh at Courant 50.
 
 Prints one JSON line: feet located+interpolated per second, the roofline
 position of the step kernel (HBM-bound; algorithmic bytes per launch over the
@@ -382,6 +384,14 @@ def main():
             "ms_per_step": rb["ms_per_step"], "kernel_ms": rb["kernel_ms"],
             "mean_walk_steps": stb["walk_steps"] / max(stb["feet"], 1),
             "roofline_frac": abytes / (rb["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        mesh.set_chain(2)
+        rc = measure(mesh, w, v0, args.steps, args.warmup, S.START_NEIGHBOR)
+        stc = rc["stats"]
+        out["strategy_c"] = {
+            "start": "element found for the preceding node of a 2-node Morton chain (nearer of it and the steered start)",
+            "value": n_feet / (rc["ms_per_step"] * 1e-3), "ms_per_step": rc["ms_per_step"],
+            "kernel_ms": rc["kernel_ms"], "mean_walk_steps": stc["walk_steps"] / max(stc["feet"], 1),
+            "roofline_frac": abytes / (rc["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
         out["k_field_reuse"] = measure_k_reuse(mesh, w, v0)
     if not args.no_batch and not args.only_a:
         out["batch"] = measure_batch()
