@@ -370,6 +370,24 @@ slw_status slw_mlp_forward(slw_mlp *n, const float *X, int64_t m, float *out);
  * detaches) to a mesh with a chart, for SLW_START_LEARNED. */
 slw_status slw_mesh_attach_mlp(slw_mesh *mesh, slw_mlp *n);
 
+/* ------------------------------------------------------------------------
+ * Quadtree locator (non-walking, the search of Section 2.1), kept as a
+ * comparator for the walks.  slw_quadtree_build splits the square around the
+ * mesh's bounding box at its centre while a node lists more than leaf_cap
+ * triangles (1 <= leaf_cap), is shallower than max_depth (<= 30) and the
+ * split separates something (no child keeps all of the node's triangles); a
+ * triangle is listed in every node its closed bounding box touches.  More
+ * than 16 list entries per triangle fails with SLW_E_NOMEM.  Synchronous
+ * (host build from the device records).  slw_locate_quadtree
+ * answers like slw_locate (user triangle ids, smallest id among closed
+ * containers, -1 and NaN outside, the same barycentric coordinates) by
+ * testing every triangle of the query's leaf with exact signs; stats_h
+ * (nullable) counts feet and outside points. */
+slw_status slw_quadtree_build(slw_mesh *mesh, int leaf_cap, int max_depth);
+slw_status slw_quadtree_info(const slw_mesh *mesh, int64_t *n_nodes_h, int64_t *n_list_h, int *depth_h);
+slw_status slw_locate_quadtree(slw_mesh *mesh, const void *q, int64_t m, int32_t *elem, void *bary,
+                               slw_stats *stats_h);
+
 /* The library's orientation predicate evaluated on the host, for testing:
  * out_h[i] = sign of orient(a, b, c) for the triple pts_h[6i .. 6i+5] =
  * (ax, ay, bx, by, cx, cy).  mode 0: FP64 filter then exact stage (what a

@@ -9,7 +9,7 @@ from pathlib import Path
 PKG = Path(__file__).resolve().parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libslwalk.so"
-SOURCES = ["slw_api.cpp", "slw_mesh.cpp", "slw_kernels.hip", "slw_learned.hip"]
+SOURCES = ["slw_api.cpp", "slw_mesh.cpp", "slw_kernels.hip", "slw_learned.hip", "slw_quadtree.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

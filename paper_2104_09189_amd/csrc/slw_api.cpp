@@ -325,6 +325,27 @@ slw_status slw_locate(slw_mesh *mesh, const void *q, int64_t m, const int32_t *s
     return hip_check(launch_locate(mesh->m, ctx->stream, q, m, start, elem, bary, steps, nullptr), "slw_locate");
 }
 
+slw_status slw_locate_quadtree(slw_mesh *mesh, const void *q, int64_t m, int32_t *elem, void *bary,
+                               slw_stats *stats_h)
+{
+    if (!mesh || m < 0 || (m > 0 && (!q || !elem)))
+        return set_error(SLW_E_ARG, "slw_locate_quadtree: null pointer or negative size");
+    if (m > ((int64_t)1 << 31) - 1)
+        return set_error(SLW_E_ARG, "slw_locate_quadtree: at most 2^31-1 points per call");
+    if (!mesh->m.qt_nodes)
+        return set_error(SLW_E_ARG, "slw_locate_quadtree: no quadtree (slw_quadtree_build)");
+    slw_ctx *ctx = mesh->ctx;
+    DeviceGuard g(ctx->device);
+    slw_status st = begin_stats(ctx, stats_h);
+    if (st != SLW_OK)
+        return st;
+    st = hip_check(launch_qt_locate(mesh->m, ctx->stream, q, m, elem, bary, stats_h ? ctx->stats : nullptr),
+                   "slw_locate_quadtree");
+    if (st != SLW_OK)
+        return st;
+    return end_stats(ctx, stats_h);
+}
+
 slw_status slw_locate_feet(slw_mesh *mesh, const slw_field *field, double t_np1, double dt, int scheme,
                            int start_mode, const int32_t *start, uint32_t flags, void *feet, int32_t *elem,
                            void *bary, int32_t *steps, slw_stats *stats_h)

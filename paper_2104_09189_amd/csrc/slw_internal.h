@@ -50,6 +50,13 @@ struct DevMesh {
     int32_t *prev_elem = nullptr; // [n_dofs] internal tri of the last location (strategy b)
     int32_t *jump = nullptr;      // [jump_g * jump_g] bucket grid of start triangles (internal)
     int jump_g = 1;
+    // quadtree (non-walking locator): nodes {first child or -1, list begin,
+    // list count, 0}, leaf lists of internal triangle ids, root square
+    int4 *qt_nodes = nullptr;
+    int32_t *qt_lists = nullptr;
+    double qt_box[3] = {0, 0, 0};  // x0, y0, side
+    int qt_depth = 0;              // deepest leaf
+    int64_t qt_n_nodes = 0, qt_n_list = 0;
     int32_t *bnext = nullptr;     // [n_nodes] next boundary node, counter-clockwise (-1: interior node)
     int32_t *bprev = nullptr;     // [n_nodes] previous boundary node
     int64_t n_boundary = 0;
@@ -200,6 +207,8 @@ void field_time_factors(FieldDev &f, double t_np1, double dt);
 
 hipError_t launch_locate(const DevMesh &m, hipStream_t st, const void *q, int64_t m_pts, const int32_t *start,
                          int32_t *elem, void *bary, int32_t *steps, DevStats *stats);
+hipError_t launch_qt_locate(const DevMesh &m, hipStream_t st, const void *q, int64_t m_pts, int32_t *elem, void *bary,
+                            DevStats *stats);
 hipError_t launch_locate_feet(const DevMesh &m, hipStream_t st, const FieldDev *f, double t_np1, double dt,
                               int scheme, int start_mode, const int32_t *start, bool feet_in, void *feet,
                               int32_t *elem, void *bary, int32_t *steps, DevStats *stats);

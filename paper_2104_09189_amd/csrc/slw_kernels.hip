@@ -350,6 +350,42 @@ __device__ inline int walk_move(const MeshView &mv, int32_t &j, GeoRec &r, int &
     return 0;
 }
 
+// Barycentric coordinates of q in the triangle of record r (internal
+// counter-clockwise vertex order) on the exact coordinates:
+// theta_k = o_k / (o_0 + o_1 + o_2), o_k = orient(x_{k+1}, x_{k+2}, q)
+template <bool F32>
+__device__ inline void exact_weights(const MeshView &mv, const GeoRec &r, typename CT<F32>::R qx,
+                                     typename CT<F32>::R qy, typename CT<F32>::R th[3])
+{
+    using R = typename CT<F32>::R;
+    R ex[3], ey[3];
+    if constexpr (F32) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            ex[k] = r.p[k].x - qx;
+            ey[k] = r.p[k].y - qy;
+        }
+    } else {
+        const double2 *X = (const double2 *)mv.dof_xy;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double2 p = X[r.v[k]];
+            ex[k] = p.x - qx;
+            ey[k] = p.y - qy;
+        }
+    }
+    R oo[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int a = (k + 1) % 3, b = (k + 2) % 3;
+        oo[k] = ex[a] * ey[b] - ey[a] * ex[b];
+    }
+    const R sum = oo[0] + oo[1] + oo[2];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        th[k] = oo[k] / sum;
+}
+
 // End of a walk that stopped in triangle j (record r, zero-sign mask zmask):
 // the tie rule (smallest user id among the closed containers), then the
 // weights on the exact coordinates.
@@ -381,33 +417,7 @@ __device__ inline WalkResult<typename CT<F32>::R> finish_walk(const MeshView &mv
 #pragma unroll
     for (int k = 0; k < 3; ++k)
         w.v[k] = r.v[k];
-    // weights on the exact coordinates: theta_k = o_k / (o_0 + o_1 + o_2)
-    R ex[3], ey[3];
-    if constexpr (F32) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            ex[k] = r.p[k].x - qx;
-            ey[k] = r.p[k].y - qy;
-        }
-    } else {
-        const double2 *X = (const double2 *)mv.dof_xy;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const double2 p = X[r.v[k]];
-            ex[k] = p.x - qx;
-            ey[k] = p.y - qy;
-        }
-    }
-    R oo[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const int a = (k + 1) % 3, b = (k + 2) % 3;
-        oo[k] = ex[a] * ey[b] - ey[a] * ex[b];
-    }
-    const R sum = oo[0] + oo[1] + oo[2];
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-        w.th[k] = oo[k] / sum;
+    exact_weights<F32>(mv, r, qx, qy, w.th);
     return w;
 }
 
@@ -591,6 +601,75 @@ __global__ void __launch_bounds__(kBlock) k_locate(MeshView mv, const typename C
         }
         if (steps)
             steps[i] = w.steps;
+    }
+    if (st)
+        flush_stats(ls, st);
+}
+
+// Non-walking locator for comparison (the quadtree of Section 2.1): descend
+// to the leaf that holds q (a point on a split line goes to the upper/right
+// child; triangles are listed in every leaf their closed bounding box
+// touches, so every closed container of q is in q's leaf), then test every
+// listed triangle with the walk's exact signs and keep the smallest user id
+// among the closed containers: the same answer as the walk, by definition.
+template <bool F32>
+__global__ void __launch_bounds__(kBlock)
+    k_qt_locate(MeshView mv, const int4 *__restrict__ nodes, const int32_t *__restrict__ lists, double ox,
+                double oy, double side, int max_depth, const typename CT<F32>::R2 *__restrict__ q, int64_t m,
+                int32_t *__restrict__ elem, typename CT<F32>::R *__restrict__ bary, DevStats *st)
+{
+    using R = typename CT<F32>::R;
+    LaneStats ls;
+    const int64_t i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (i < m) {
+        const R qx = q[i].x, qy = q[i].y;
+        int32_t best = -1, best_uid = 0x7fffffff;
+        GeoRec rb;
+        if (in_box<R>(qx, qy, mv.bb)) {
+            const float qfx = F32 ? (float)qx : (float)((double)qx - mv.fc.cx);
+            const float qfy = F32 ? (float)qy : (float)((double)qy - mv.fc.cy);
+            double bx = ox, by = oy, s = side;
+            int4 nd = nodes[0];
+            for (int depth = 0; nd.x >= 0 && depth < max_depth; ++depth) {
+                s *= 0.5;
+                const int right = (double)qx >= bx + s, top = (double)qy >= by + s;
+                bx += right ? s : 0.0;
+                by += top ? s : 0.0;
+                nd = nodes[nd.x + right + 2 * top];
+            }
+            for (int32_t c = 0; c < nd.z; ++c) {
+                const int32_t t = lists[nd.y + c];
+                const GeoRec r = mv.geo[t];
+                float o[3];
+                int sg[3];
+                edge_signs<F32>(mv, r, qfx, qfy, qx, qy, o, sg, ls.c);
+                if (sg[0] >= 0 && sg[1] >= 0 && sg[2] >= 0) {
+                    const int32_t uid = mv.tri_uf[t] & kUidMask;
+                    if (uid < best_uid) {
+                        best_uid = uid;
+                        best = t;
+                        rb = r;
+                    }
+                }
+            }
+        }
+        if (st) {
+            ++ls.feet;
+            ls.outside += best < 0;
+        }
+        elem[i] = best >= 0 ? best_uid : -1;
+        if (bary) {
+            if (best >= 0) {
+                R th[3], ub[3];
+                exact_weights<F32>(mv, rb, qx, qy, th);
+                user_bary<R>(mv.tri_uf[best], th, ub);
+                bary[3 * i] = ub[0];
+                bary[3 * i + 1] = ub[1];
+                bary[3 * i + 2] = ub[2];
+            } else {
+                bary[3 * i] = bary[3 * i + 1] = bary[3 * i + 2] = (R)NAN;
+            }
+        }
     }
     if (st)
         flush_stats(ls, st);
@@ -1484,6 +1563,26 @@ hipError_t launch_locate(const DevMesh &m, hipStream_t st, const void *q, int64_
     else
         hipLaunchKernelGGL(k_locate<false>, dim3(g), dim3(kBlock), 0, st, mv, (const double2 *)q, mp, start, elem,
                            (double *)bary, steps, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_qt_locate(const DevMesh &m, hipStream_t st, const void *q, int64_t mp, int32_t *elem, void *bary,
+                            DevStats *stats)
+{
+    if (mp == 0)
+        return hipSuccess;
+    if (!m.qt_nodes)
+        return hipErrorInvalidValue;
+    unsigned g;
+    if (!tiles_for(mp, g))
+        return hipErrorInvalidValue;
+    MeshView mv = view_of(m);
+    if (m.coords_f32)
+        hipLaunchKernelGGL(k_qt_locate<true>, dim3(g), dim3(kBlock), 0, st, mv, m.qt_nodes, m.qt_lists, m.qt_box[0],
+                           m.qt_box[1], m.qt_box[2], m.qt_depth, (const float2 *)q, mp, elem, (float *)bary, stats);
+    else
+        hipLaunchKernelGGL(k_qt_locate<false>, dim3(g), dim3(kBlock), 0, st, mv, m.qt_nodes, m.qt_lists, m.qt_box[0],
+                           m.qt_box[1], m.qt_box[2], m.qt_depth, (const double2 *)q, mp, elem, (double *)bary, stats);
     return hipGetLastError();
 }
 

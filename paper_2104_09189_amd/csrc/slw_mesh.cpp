@@ -134,7 +134,7 @@ void free_mesh(DevMesh &m)
 {
     void *ptrs[] = {m.geo, m.tri_uf, m.tedge, m.dof_xy, m.qstart, m.vmin, m.dof_user,
                     m.dof_int, m.tri_int, m.prev_elem, m.jump, m.chart_uv, m.chart_node, m.chart_table,
-                    m.chart_qx, m.chart_qy, m.learned_start, m.bnext, m.bprev};
+                    m.chart_qx, m.chart_qy, m.learned_start, m.bnext, m.bprev, m.qt_nodes, m.qt_lists};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);

@@ -139,6 +139,9 @@ _sig("slw_mlp_train", ctypes.c_int, [_vp, _vp, _vp, _i64, ctypes.c_int, _i64, ct
                                      ctypes.POINTER(ctypes.c_float)])
 _sig("slw_mlp_forward", ctypes.c_int, [_vp, _vp, _i64, _vp])
 _sig("slw_mesh_attach_mlp", ctypes.c_int, [_vp, _vp])
+_sig("slw_quadtree_build", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int])
+_sig("slw_quadtree_info", ctypes.c_int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_int)])
+_sig("slw_locate_quadtree", ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, ctypes.POINTER(slw_stats)])
 
 MLP_PARAMS = 5 * 64 + 64 + 64 * 64 + 64 + 64 * 2 + 2
 
@@ -152,7 +155,7 @@ EXPORTED = ["slw_status_string", "slw_last_error", "slw_ctx_create", "slw_ctx_se
             "slw_chart_build", "slw_chart_coords", "slw_mlp_create", "slw_mlp_free", "slw_mlp_set_params",
             "slw_mlp_get_params", "slw_mlp_set_normalization", "slw_mlp_get_normalization",
             "slw_mlp_fit_normalization", "slw_learned_gather", "slw_mlp_grad", "slw_mlp_train", "slw_mlp_forward",
-            "slw_mesh_attach_mlp"]
+            "slw_mesh_attach_mlp", "slw_quadtree_build", "slw_quadtree_info", "slw_locate_quadtree"]
 
 
 def _check(rc: int, where: str):
@@ -348,6 +351,30 @@ class Mesh:
     def attach_mlp(self, net):
         _check(_lib.slw_mesh_attach_mlp(self.h, None if net is None else net.h), "slw_mesh_attach_mlp")
         self.mlp = net  # keeps the borrowed network alive while attached
+
+    # -- quadtree comparator
+    def quadtree_build(self, leaf_cap: int = 8, max_depth: int = 24) -> dict:
+        _check(_lib.slw_quadtree_build(self.h, int(leaf_cap), int(max_depth)), "slw_quadtree_build")
+        nn, nl, dep = _i64(), _i64(), ctypes.c_int()
+        _check(_lib.slw_quadtree_info(self.h, ctypes.byref(nn), ctypes.byref(nl), ctypes.byref(dep)),
+               "slw_quadtree_info")
+        return {"nodes": int(nn.value), "list_entries": int(nl.value), "depth": int(dep.value)}
+
+    def locate_quadtree(self, q, elem=None, bary=None, want_bary=True, stats=False):
+        torch = _torch()
+        dev = self.ctx.device
+        m = q.shape[0]
+        if q.ndim != 2 or q.shape[1] != 2:
+            raise ValueError("q must be m x 2")
+        if elem is None:
+            elem = torch.empty(m, dtype=torch.int32, device=f"cuda:{dev}")
+        if bary is None and want_bary:
+            bary = torch.empty((m, 3), dtype=self.cdtype, device=f"cuda:{dev}")
+        st = slw_stats() if stats else None
+        _check(_lib.slw_locate_quadtree(self.h, _ptr(q, self.cdtype, dev, "q"), m, _ptr(elem, torch.int32, dev, "elem"),
+                                        _ptr(bary, self.cdtype, dev, "bary", True),
+                                        ctypes.byref(st) if st is not None else None), "slw_locate_quadtree")
+        return elem, bary, (st.as_dict() if st is not None else None)
 
     # -- calls
     def locate(self, q, start=None, elem=None, bary=None, steps=None, want_bary=True, want_steps=False):
