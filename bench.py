@@ -299,6 +299,47 @@ def measure_learned(alpha=50.0, n=1415, k=16, steps=10, samples_per_step=200_000
             "speedup_chart_vs_plain": base / res["chart_exact"]["ms_per_step"]}
 
 
+def measure_locators(mesh, w, reps=10):
+    """Point location alone on the feet of one step of the headline workload:
+    the steered walk (strategy (a)), the walk from a bucket-grid start
+    (slw_locate without starts), and the quadtree (no walk), all giving the
+    same elements."""
+    import torch
+    from paper_2104_09189_amd import slwalk as S
+    stream = torch.cuda.current_stream()
+    feet = mesh.locate_feet(w.field, 8 * w.dt, w.dt, w.scheme, want_feet=True, want_bary=False)["feet"]
+    info = None
+    for cap in (16, 32, 64, 128):
+        try:
+            info = mesh.quadtree_build(cap, 24)
+            info["leaf_cap"] = cap
+            break
+        except S.SlwError:
+            continue
+    out = {"points": int(feet.shape[0]), "quadtree": info}
+    elems = {}
+
+    def timed(name, fn):
+        r = fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out[name + "_ms"] = e0.elapsed_time(e1) / reps
+        elems[name] = r.cpu().numpy()
+
+    timed("walk_steered", lambda: mesh.locate_feet(feet=feet, feet_in=True, want_bary=False)["elem"])
+    timed("walk_bucket_start", lambda: mesh.locate(feet, want_bary=False)[0])
+    if info is not None:
+        timed("quadtree", lambda: mesh.locate_quadtree(feet, want_bary=False)[0])
+    # locate_feet reports user ids in DOF order; slw_locate in query order (the same here: internal order)
+    out["identical"] = all(np.array_equal(elems["walk_steered"], v) for v in elems.values())
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -393,6 +434,7 @@ def main():
             "kernel_ms": rc["kernel_ms"], "mean_walk_steps": stc["walk_steps"] / max(stc["feet"], 1),
             "roofline_frac": abytes / (rc["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
         out["k_field_reuse"] = measure_k_reuse(mesh, w, v0)
+        out["locators"] = measure_locators(mesh, w)
     if not args.no_batch and not args.only_a:
         out["batch"] = measure_batch()
     if not args.no_learned and not args.only_a:
