@@ -229,21 +229,26 @@ def _walk_histogram(steps: np.ndarray) -> dict:
             "bins": {f"[{a},{b})": int(c) for a, b, c in zip(edges[:-1], edges[1:], counts)}}
 
 
-def measure_learned(alpha=50.0, n=1415, k=16, steps=10, samples_per_step=200_000, train_steps=50, seed=5005):
-    """Learned start on the graded mesh at a large Courant number: the network
-    is trained on the GPU on feet that the plain walk locates over 50 steps
-    (10M samples), then steps with the learned start (per-foot choice between
-    the network's proposal and the steered start) are timed beside the plain
-    steered walk and the exact chart-cell start (no network); all three must
-    give identical bits."""
+def measure_learned(alpha=50.0, n=1415, k=16, steps=10, samples_per_step=200_000, train_steps=50, seed=5005,
+                    w=None):
+    """Learned start on the graded mesh at a large Courant number (or on the
+    workload w): the network is trained on the GPU on feet that the plain
+    walk locates over 50 steps (10M samples), then steps with the learned
+    start (per-foot choice between the network's proposal and the steered
+    start) are timed beside the plain steered walk and the exact chart-cell
+    start (no network); all three must give identical bits."""
     import torch
     from paper_2104_09189_amd import inputs as I
     from paper_2104_09189_amd import slwalk as S
-    w = I.graded_swirl(alpha=alpha, n=n, k_fields=k)
+    if w is None:
+        w = I.graded_swirl(alpha=alpha, n=n, k_fields=k)
+    k = w.v0.shape[1]
     ctx = S.Context(0)
     mesh = S.Mesh(ctx, w.xy, w.tri, S.INTERNAL_ORDER)
+    # about one triangle per chart cell
+    g = 1 << int(np.ceil(np.log2(np.sqrt(mesh.n_tris))))
     t0 = time.perf_counter()
-    mesh.chart_build(2048)
+    mesh.chart_build(g)
     chart_s = time.perf_counter() - t0
     nd = mesh.n_dofs
     rng = np.random.default_rng(seed)
@@ -291,8 +296,9 @@ def measure_learned(alpha=50.0, n=1415, k=16, steps=10, samples_per_step=200_000
         res[name] = {"ms_per_step": ms, "feet_per_s": mesh.n_nodes / (ms * 1e-3), "walk_steps": hist}
     identical = all(np.array_equal(outs["plain_steered"], outs[x]) for x in ("learned", "chart_exact"))
     base = res["plain_steered"]["ms_per_step"]
-    return {"workload": w.name, "n_nodes": int(mesh.n_nodes), "n_tris": int(mesh.n_tris), "alpha": alpha,
-            "k_fields": k, "chart_g": 2048, "chart_build_s": chart_s, "training_samples": m,
+    return {"workload": w.name, "n_nodes": int(mesh.n_nodes), "n_tris": int(mesh.n_tris),
+            "alpha": w.extra.get("alpha", alpha),
+            "k_fields": k, "chart_g": g, "chart_build_s": chart_s, "training_samples": m,
             "gather_s": gather_s, "train_s": train_s, "train_plan": plan, "final_minibatch_loss": loss,
             "starts": res, "identical_bits": identical,
             "speedup_learned_vs_plain": base / res["learned"]["ms_per_step"],
@@ -439,6 +445,7 @@ def main():
         out["batch"] = measure_batch()
     if not args.no_learned and not args.only_a:
         out["learned"] = measure_learned()
+        out["learned_uniform_mesh"] = measure_learned(w=I.swirl_500(alpha=20.0, order="morton"))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(out), flush=True)
