@@ -235,8 +235,10 @@ def measure_learned(alpha=50.0, n=1415, k=16, steps=10, samples_per_step=200_000
     workload w): the network is trained on the GPU on feet that the plain
     walk locates over 50 steps (10M samples), then steps with the learned
     start (per-foot choice between the network's proposal and the steered
-    start) are timed beside the plain steered walk and the exact chart-cell
-    start (no network); all three must give identical bits."""
+    start), with the learned index (the network's cell corrected by galloping
+    searches in the chart tables) and with the exact chart-cell start (binary
+    searches, no network) are timed beside the plain steered walk; all must
+    give identical bits."""
     import torch
     from paper_2104_09189_amd import inputs as I
     from paper_2104_09189_amd import slwalk as S
@@ -278,7 +280,7 @@ def measure_learned(alpha=50.0, n=1415, k=16, steps=10, samples_per_step=200_000
     res = {}
     outs = {}
     for name, mode in (("plain_steered", S.START_STEERED), ("learned", S.START_LEARNED),
-                       ("chart_exact", S.START_CHART)):
+                       ("learned_index", S.START_LEARNED_INDEX), ("chart_exact", S.START_CHART)):
         vo = torch.empty_like(v0)
         mesh.step(w.field, t_n, w.dt, w.scheme, v0, vo, start_mode=mode)
         torch.cuda.synchronize()
@@ -294,7 +296,7 @@ def measure_learned(alpha=50.0, n=1415, k=16, steps=10, samples_per_step=200_000
                                want_bary=False)
         hist = _walk_histogram(loc["steps"].cpu().numpy().astype(np.int64))
         res[name] = {"ms_per_step": ms, "feet_per_s": mesh.n_nodes / (ms * 1e-3), "walk_steps": hist}
-    identical = all(np.array_equal(outs["plain_steered"], outs[x]) for x in ("learned", "chart_exact"))
+    identical = all(np.array_equal(outs["plain_steered"], outs[x]) for x in ("learned", "learned_index", "chart_exact"))
     base = res["plain_steered"]["ms_per_step"]
     return {"workload": w.name, "n_nodes": int(mesh.n_nodes), "n_tris": int(mesh.n_tris),
             "alpha": w.extra.get("alpha", alpha),
@@ -302,6 +304,7 @@ def measure_learned(alpha=50.0, n=1415, k=16, steps=10, samples_per_step=200_000
             "gather_s": gather_s, "train_s": train_s, "train_plan": plan, "final_minibatch_loss": loss,
             "starts": res, "identical_bits": identical,
             "speedup_learned_vs_plain": base / res["learned"]["ms_per_step"],
+            "speedup_learned_index_vs_plain": base / res["learned_index"]["ms_per_step"],
             "speedup_chart_vs_plain": base / res["chart_exact"]["ms_per_step"]}
 
 

@@ -102,9 +102,12 @@ enum {
                               slw_mesh_attach_mlp (learned start; see below) */
     SLW_START_CHART = 5,   /* the start-table triangle of the foot's own chart cell
                               (exact chart lookup, no network; needs slw_chart_build) */
-    SLW_START_NEIGHBOR = 6 /* strategy (c): the element found for the preceding node of a
+    SLW_START_NEIGHBOR = 6, /* strategy (c): the element found for the preceding node of a
                               chain of consecutive internal-order nodes (slw_step only;
                               see slw_mesh_set_chain) */
+    SLW_START_LEARNED_INDEX = 7 /* a learned index: the network's chart cell as the guess of
+                              galloping searches in the chart's quantile tables, which end
+                              in the foot's own cell (the start of SLW_START_CHART) */
 };
 /* slw_mesh_upload flags */
 #define SLW_COORDS_F32 0x1u     /* store coordinates as float (FP32 walk, FP64/exact fallback) */

@@ -359,12 +359,12 @@ slw_status slw_locate_feet(slw_mesh *mesh, const slw_field *field, double t_np1,
         return set_error(SLW_E_ARG, "feet (SLW_FEET_IN) or a valid field is required");
     if (scheme != SLW_EULER && scheme != SLW_RK2)
         return set_error(SLW_E_ARG, "unknown scheme");
-    if (start_mode < SLW_START_STEERED || start_mode > SLW_START_CHART)
+    if (start_mode < SLW_START_STEERED || start_mode > SLW_START_LEARNED_INDEX || start_mode == SLW_START_NEIGHBOR)
         return set_error(SLW_E_ARG, "unknown start mode (SLW_START_NEIGHBOR is for slw_step)");
     if ((start_mode == SLW_START_GIVEN || start_mode == SLW_START_FIXED) && !start)
         return set_error(SLW_E_ARG, "start array required for this start mode");
-    if (start_mode == SLW_START_LEARNED && !mesh->m.mlp)
-        return set_error(SLW_E_ARG, "SLW_START_LEARNED needs a network attached (slw_mesh_attach_mlp)");
+    if ((start_mode == SLW_START_LEARNED || start_mode == SLW_START_LEARNED_INDEX) && !mesh->m.mlp)
+        return set_error(SLW_E_ARG, "learned starts need a network attached (slw_mesh_attach_mlp)");
     if (start_mode == SLW_START_CHART && !mesh->m.chart_table)
         return set_error(SLW_E_ARG, "SLW_START_CHART needs a chart (slw_chart_build)");
     slw_ctx *ctx = mesh->ctx;
@@ -373,9 +373,10 @@ slw_status slw_locate_feet(slw_mesh *mesh, const slw_field *field, double t_np1,
     if (st != SLW_OK)
         return st;
     FieldDev fd = to_dev(field);
-    if (start_mode == SLW_START_LEARNED || start_mode == SLW_START_CHART) {
+    if (start_mode == SLW_START_LEARNED || start_mode == SLW_START_CHART || start_mode == SLW_START_LEARNED_INDEX) {
+        const int kind = start_mode == SLW_START_CHART ? 0 : (start_mode == SLW_START_LEARNED ? 1 : 2);
         st = hip_check(launch_chart_start(mesh->m, ctx->stream, fd, t_np1, dt, scheme, feet_in ? feet : nullptr,
-                                          mesh->m.n_dofs, start_mode == SLW_START_LEARNED, mesh->m.learned_start),
+                                          mesh->m.n_dofs, kind, mesh->m.learned_start),
                        "chart start");
         if (st != SLW_OK)
             return st;
@@ -421,12 +422,12 @@ slw_status slw_step(slw_mesh *mesh, const slw_field *field, double t_n, double d
         return set_error(SLW_E_ARG, "unknown scheme");
     if (vdtype != SLW_F64 && vdtype != SLW_F32)
         return set_error(SLW_E_ARG, "unknown vdtype");
-    if (start_mode < SLW_START_STEERED || start_mode > SLW_START_NEIGHBOR)
+    if (start_mode < SLW_START_STEERED || start_mode > SLW_START_LEARNED_INDEX)
         return set_error(SLW_E_ARG, "unknown start mode");
     if ((start_mode == SLW_START_GIVEN || start_mode == SLW_START_FIXED) && !start)
         return set_error(SLW_E_ARG, "start array required for this start mode");
-    if (start_mode == SLW_START_LEARNED && !mesh->m.mlp)
-        return set_error(SLW_E_ARG, "SLW_START_LEARNED needs a network attached (slw_mesh_attach_mlp)");
+    if ((start_mode == SLW_START_LEARNED || start_mode == SLW_START_LEARNED_INDEX) && !mesh->m.mlp)
+        return set_error(SLW_E_ARG, "learned starts need a network attached (slw_mesh_attach_mlp)");
     if (start_mode == SLW_START_CHART && !mesh->m.chart_table)
         return set_error(SLW_E_ARG, "SLW_START_CHART needs a chart (slw_chart_build)");
     const DevMesh &m = mesh->m;

@@ -219,10 +219,11 @@ hipError_t launch_step(const DevMesh &m, hipStream_t st, const FieldDev &f, doub
                        int order, int start_mode, const int32_t *start, const void *v_in, int vdtype, int k,
                        void *v_out, double outside, bool write_prev, const int32_t *out_map, DevStats *stats);
 hipError_t launch_zero_stats(hipStream_t st, DevStats *p);
-// chart starts (the mesh needs a chart; use_net: the attached network, else
-// the exact chart cell of the foot)
+// chart starts (the mesh needs a chart; kind 0: the exact chart cell of the
+// foot; 1: the attached network's cell; 2: the network's cell corrected by
+// galloping searches to the foot's own cell)
 hipError_t launch_chart_start(const DevMesh &m, hipStream_t st, const FieldDev &f, double t_np1, double dt,
-                              int scheme, const void *feet_in, int64_t n_iter, bool use_net, int32_t *start);
+                              int scheme, const void *feet_in, int64_t n_iter, int kind, int32_t *start);
 hipError_t launch_learned_gather(const DevMesh &m, hipStream_t st, const FieldDev &f, double t_np1, double dt,
                                  int scheme, const int32_t *dofs, int64_t cnt, float *X, float *Y);
 

@@ -186,7 +186,8 @@ __device__ inline int32_t start_for(const MeshView &mv, int64_t d, int64_t api, 
         if (pe >= 0)
             return pe;
     }
-    if (mode == SLW_START_LEARNED || mode == SLW_START_CHART) {  // internal ids from the chart
+    if (mode == SLW_START_LEARNED || mode == SLW_START_CHART || mode == SLW_START_LEARNED_INDEX) {
+        // internal ids from the chart
         const int32_t j = start[d];
         if (j >= 0 && j < mv.n_tris)
             return j;
@@ -1241,18 +1242,59 @@ __device__ inline int upper_index(const float *__restrict__ tab, int n, float x)
     return lo;
 }
 
+// upper_index searched outwards from a guess i0 (exponential steps, then
+// bisection): the same answer, in about 2 log2 |answer - i0| probes
+__device__ inline int gallop_index(const float *__restrict__ tab, int n, float x, int i0)
+{
+    i0 = i0 < 0 ? 0 : (i0 >= n ? n - 1 : i0);
+    int lo, hi;  // tab[lo] <= x or lo = 0; hi = n or tab[hi] > x
+    if (tab[i0] <= x || i0 == 0) {
+        lo = i0;
+        int step = 1;
+        hi = lo + 1;
+        while (hi < n && tab[hi] <= x) {
+            lo = hi;
+            step <<= 1;
+            hi = lo + step;
+        }
+        hi = hi < n ? hi : n;
+    } else {
+        hi = i0;
+        int step = 1;
+        lo = hi - 1;
+        while (lo > 0 && tab[lo] > x) {
+            hi = lo;
+            step <<= 1;
+            lo = hi - step;
+        }
+        lo = lo > 0 ? lo : 0;
+    }
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (tab[mid] <= x)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
 // Chart start of DOF d (internal order; valid: d is a DOF whose foot q lies
-// in the bounding box): NET, the table cell of chart(node) + network output;
-// else the cell that holds the foot (quantile tables); then whichever of that
-// proposal and the node's steered start lies nearer the foot.  With NET every
-// lane of the wavefront must call it (the network runs on the whole
+// in the bounding box).  KIND 0: the cell that holds the foot (binary
+// searches in the quantile tables); 1: the table cell of chart(node) +
+// network output; 2 (a learned index): the network's cell as the guess of
+// galloping searches that end in the foot's own cell.  Then whichever of that
+// proposal and the node's steered start lies nearer the foot.  With KIND > 0
+// every lane of the wavefront must call it (the network runs on the whole
 // wavefront); the result is meaningful on valid lanes only.
-template <bool F32, bool NET>
+template <bool F32, int KIND>
 __device__ inline int32_t chart_start(const MeshView &mv, bool valid, int64_t d, typename CT<F32>::R2 x,
                                       typename CT<F32>::R qx, typename CT<F32>::R qy, double t_np1)
 {
     using R = typename CT<F32>::R;
+    constexpr bool NET = KIND > 0;
     int32_t j = 0;
+    float2 guess = make_float2(0.f, 0.f);
     if (NET) {
         float feat[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
         float2 c = make_float2(0.f, 0.f);
@@ -1262,18 +1304,26 @@ __device__ inline int32_t chart_start(const MeshView &mv, bool valid, int64_t d,
             mlp_normalise(mv.mlp_norm, feat);
         }
         const float2 duv = mlp_forward_wave(mv.mlp_wpack, mv.mlp_bias, feat);  // every lane
-        if (valid)
-            j = chart_lookup(mv.chart_table, mv.chart_g, make_float2(c.x + duv.x, c.y + duv.y));
+        guess = make_float2(c.x + duv.x, c.y + duv.y);
+        if (valid && KIND == 1)
+            j = chart_lookup(mv.chart_table, mv.chart_g, guess);
     }
     if (!valid)
         return -1;
     // the foot in the records' float frame, as the chart was built
     const float fx = F32 ? (float)qx : (float)((double)qx - mv.fc.cx);
     const float fy = F32 ? (float)qy : (float)((double)qy - mv.fc.cy);
-    if (!NET) {
+    if (KIND != 1) {
         const int g = mv.chart_g;
-        const int bu = upper_index(mv.chart_qx, g, fx);
-        const int bv = upper_index(mv.chart_qy + (int64_t)bu * g, g, fy);
+        int bu, bv;
+        if (KIND == 0) {
+            bu = upper_index(mv.chart_qx, g, fx);
+            bv = upper_index(mv.chart_qy + (int64_t)bu * g, g, fy);
+        } else {
+            const float u = fminf(fmaxf(guess.x, 0.f), 0.99999994f), v = fminf(fmaxf(guess.y, 0.f), 0.99999994f);
+            bu = gallop_index(mv.chart_qx, g, fx, (int)(u * (float)g));
+            bv = gallop_index(mv.chart_qy + (int64_t)bu * g, g, fy, (int)(v * (float)g));
+        }
         j = mv.chart_table[(int64_t)bu * g + bv];
     }
     const int32_t js = quadrant_start(mv.qstart[d], (float)(qx - x.x), (float)(qy - x.y));
@@ -1283,7 +1333,7 @@ __device__ inline int32_t chart_start(const MeshView &mv, bool valid, int64_t d,
 // start[d] for the DOFs [0, n_iter) (internal order) by chart_start; feet
 // computed from the field or read from feet_in (indexed like
 // slw_locate_feet's feet)
-template <bool F32, bool NET>
+template <bool F32, int KIND>
 __global__ void __launch_bounds__(kBlock)
     k_chart_start(MeshView mv, FieldDev f, double dt, double t_np1, int scheme,
                   const typename CT<F32>::R2 *__restrict__ feet_in, int64_t n_iter, int32_t *__restrict__ start)
@@ -1307,7 +1357,7 @@ __global__ void __launch_bounds__(kBlock)
     }
     // outside the box the walk does not run; the steered start is written
     const bool valid = d < n_iter && in_box<R>(qx, qy, mv.bb);
-    const int32_t j = chart_start<F32, NET>(mv, valid, d, x, qx, qy, t_np1);
+    const int32_t j = chart_start<F32, KIND>(mv, valid, d, x, qx, qy, t_np1);
     if (d < n_iter)
         start[d] = valid ? j : mv.qstart[d].x;
 }
@@ -1354,10 +1404,10 @@ __device__ inline void step_chunk(const MeshView &mv, const FieldDev &f, double 
         }
         const bool valid = d < n_iter && in_box<R>(q.x, q.y, mv.bb);
         if constexpr (NET) {  // the learned start (kernels instantiated for it alone)
-            const int32_t jc = chart_start<F32, true>(mv, valid, d, x, q.x, q.y, t_np1);
+            const int32_t jc = chart_start<F32, 1>(mv, valid, d, x, q.x, q.y, t_np1);
             j0 = valid ? jc : j0;
         } else if (mode == SLW_START_CHART) {
-            const int32_t jc = chart_start<F32, false>(mv, valid, d, x, q.x, q.y, t_np1);
+            const int32_t jc = chart_start<F32, 0>(mv, valid, d, x, q.x, q.y, t_np1);
             j0 = valid ? jc : j0;
         } else if (valid) {
             const int64_t api = (mode == SLW_START_GIVEN && !mv.internal_order) ? mv.dof_user[d] : d;
@@ -1650,10 +1700,12 @@ hipError_t launch_step(const DevMesh &m, hipStream_t st, const FieldDev &f0, dou
     const int rp = m.bc_kind ? 0 : m.repack;
     if (m.bc_kind && mode == SLW_START_NEIGHBOR)
         return hipErrorNotSupported;
-    if ((mode == SLW_START_LEARNED || mode == SLW_START_CHART) && rp == 0) {
-        // one foot per lane: the proposals come from their own kernel
+    if (((mode == SLW_START_LEARNED || mode == SLW_START_CHART) && rp == 0) || mode == SLW_START_LEARNED_INDEX) {
+        // the proposals come from their own kernel (the repacking kernel
+        // computes chart and learned starts itself)
         hipError_t e = launch_chart_start(m, st, f0, t_n + dt, dt, scheme, nullptr, n_iter,
-                                          mode == SLW_START_LEARNED, m.learned_start);
+                                          mode == SLW_START_CHART ? 0 : (mode == SLW_START_LEARNED ? 1 : 2),
+                                          m.learned_start);
         if (e != hipSuccess)
             return e;
         start = m.learned_start;
@@ -1801,11 +1853,11 @@ hipError_t launch_permute_rows(hipStream_t st, const void *src, void *dst, int64
 }
 
 hipError_t launch_chart_start(const DevMesh &m, hipStream_t st, const FieldDev &f0, double t_np1, double dt,
-                              int scheme, const void *feet_in, int64_t n_iter, bool use_net, int32_t *start)
+                              int scheme, const void *feet_in, int64_t n_iter, int kind, int32_t *start)
 {
     if (n_iter <= 0)
         return hipSuccess;
-    if (!m.chart_table || (use_net && !m.mlp))
+    if (!m.chart_table || (kind > 0 && !m.mlp) || kind < 0 || kind > 2)
         return hipErrorInvalidValue;
     unsigned g;
     if (!tiles_for(n_iter, g))
@@ -1813,13 +1865,13 @@ hipError_t launch_chart_start(const DevMesh &m, hipStream_t st, const FieldDev &
     MeshView mv = view_of(m);
     FieldDev f = f0;
     field_time_factors(f, t_np1, dt);
-#define SLW_CSTART(F32, NET, R2)                                                                                  \
-    hipLaunchKernelGGL((k_chart_start<F32, NET>), dim3(g), dim3(kBlock), 0, st, mv, f, dt, t_np1, scheme,        \
+#define SLW_CSTART(F32, KIND, R2)                                                                                 \
+    hipLaunchKernelGGL((k_chart_start<F32, KIND>), dim3(g), dim3(kBlock), 0, st, mv, f, dt, t_np1, scheme,       \
                        (const R2 *)feet_in, n_iter, start)
     if (m.coords_f32) {
-        if (use_net) SLW_CSTART(true, true, float2); else SLW_CSTART(true, false, float2);
+        if (kind == 2) SLW_CSTART(true, 2, float2); else if (kind == 1) SLW_CSTART(true, 1, float2); else SLW_CSTART(true, 0, float2);
     } else {
-        if (use_net) SLW_CSTART(false, true, double2); else SLW_CSTART(false, false, double2);
+        if (kind == 2) SLW_CSTART(false, 2, double2); else if (kind == 1) SLW_CSTART(false, 1, double2); else SLW_CSTART(false, 0, double2);
     }
 #undef SLW_CSTART
     return hipGetLastError();

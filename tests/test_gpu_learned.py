@@ -202,9 +202,14 @@ def test_learned_start_finds_the_oracles_elements(S, C, orc, flags):
     out_s = mesh.locate_feet(feet=dev(feet[perm]), feet_in=True, want_steps=True, stats=True)
     out_c = mesh.locate_feet(feet=dev(feet[perm]), feet_in=True, start_mode=S.START_CHART, want_steps=True,
                              stats=True)
+    out_i = mesh.locate_feet(t_np1=t_np1, dt=dt, feet=dev(feet[perm]), feet_in=True,
+                             start_mode=S.START_LEARNED_INDEX, want_steps=True, stats=True)
     assert np.array_equal(host(out_l["elem"]), e_ref[perm])
     assert np.array_equal(host(out_s["elem"]), e_ref[perm])
     assert np.array_equal(host(out_c["elem"]), e_ref[perm])
+    assert np.array_equal(host(out_i["elem"]), e_ref[perm])
+    # the learned index's searches end in the exact chart cell: the same starts, the same walks
+    assert np.array_equal(host(out_i["steps"]), host(out_c["steps"]))
     # the exact chart cell starts within a few steps of the foot
     assert out_c["stats"]["walk_steps"] < 0.2 * out_s["stats"]["walk_steps"], (out_c["stats"], out_s["stats"])
     if not flags & 0x1:
@@ -217,8 +222,10 @@ def test_learned_start_finds_the_oracles_elements(S, C, orc, flags):
     a = host(mesh.step(fld, 1.5 * dt, dt, S.SLW_RK2, dev(v0), start_mode=S.START_LEARNED))
     b = host(mesh.step(fld, 1.5 * dt, dt, S.SLW_RK2, dev(v0)))
     c = host(mesh.step(fld, 1.5 * dt, dt, S.SLW_RK2, dev(v0), start_mode=S.START_CHART))
+    i = host(mesh.step(fld, 1.5 * dt, dt, S.SLW_RK2, dev(v0), start_mode=S.START_LEARNED_INDEX))
     assert np.array_equal(a, b)
     assert np.array_equal(c, b)
+    assert np.array_equal(i, b)
 
 
 def test_untrained_network_is_still_exact(S, C, orc):
@@ -233,6 +240,9 @@ def test_untrained_network_is_still_exact(S, C, orc):
     ref, _, _, _ = orc.sl_step(xy, tri, v0, fld, 0.0, dt, I.SCHEME_EULER, order=2, p2=p2)
     assert np.abs(v - ref).max() <= 1e-12 * np.abs(v0).max()
     v = host(mesh.step(fld, 0.0, dt, S.SLW_EULER, dev(v0), order=2, start_mode=S.START_CHART))
+    assert np.abs(v - ref).max() <= 1e-12 * np.abs(v0).max()
+    # an untrained network as the guess of the learned index: still the exact cell
+    v = host(mesh.step(fld, 0.0, dt, S.SLW_EULER, dev(v0), order=2, start_mode=S.START_LEARNED_INDEX))
     assert np.abs(v - ref).max() <= 1e-12 * np.abs(v0).max()
     mesh.attach_mlp(None)
     with pytest.raises(S.SlwError):

@@ -114,6 +114,6 @@ def test_chart_starts_fused_in_every_schedule(S, C):
     mesh.set_repack(1)
     ref, st_ref = mesh.step(fld, 0.2, dt, S.SLW_RK2, dev(v0), stats=True)
     ref = host(ref).copy()
-    for mode in (S.START_CHART, S.START_LEARNED):
+    for mode in (S.START_CHART, S.START_LEARNED, S.START_LEARNED_INDEX):
         v, _ = _same(_run(S, mesh, fld, 0.2, dt, S.SLW_RK2, v0, start_mode=mode))
         assert np.array_equal(v, ref), mode
