@@ -884,6 +884,123 @@ __global__ void __launch_bounds__(kBlock)
     wave_interp<V, NA>(row, wgt, nf, vin, k, vout, nullptr, base, (V)outside);
 }
 
+// ---------------------------------------------------------------------------
+// learned start proposal: the network maps a foot to chart coordinates and
+// the chart table to a start triangle; the walk above finishes the search
+
+// raw network inputs of a foot: the node's position (in chart coordinates),
+// its displacement to the foot, time
+template <typename R>
+__device__ inline void raw_features(float2 node_uv, R x, R y, R qx, R qy, double t, float f[5])
+{
+    f[0] = node_uv.x;
+    f[1] = node_uv.y;
+    f[2] = (float)(qx - x);
+    f[3] = (float)(qy - y);
+    f[4] = (float)t;
+}
+
+// largest i in [0, n) with tab[i] <= x (0 when there is none; tab sorted);
+// the trip count depends on n only
+__device__ inline int upper_index(const float *__restrict__ tab, int n, float x)
+{
+    int lo = 0;
+    while (n > 1) {
+        const int half = n >> 1;
+        lo = tab[lo + half] <= x ? lo + half : lo;
+        n -= half;
+    }
+    return lo;
+}
+
+// upper_index searched outwards from a guess i0 (exponential steps, then
+// bisection): the same answer, in about 2 log2 |answer - i0| probes
+__device__ inline int gallop_index(const float *__restrict__ tab, int n, float x, int i0)
+{
+    i0 = i0 < 0 ? 0 : (i0 >= n ? n - 1 : i0);
+    int lo, hi;  // tab[lo] <= x or lo = 0; hi = n or tab[hi] > x
+    if (tab[i0] <= x || i0 == 0) {
+        lo = i0;
+        int step = 1;
+        hi = lo + 1;
+        while (hi < n && tab[hi] <= x) {
+            lo = hi;
+            step <<= 1;
+            hi = lo + step;
+        }
+        hi = hi < n ? hi : n;
+    } else {
+        hi = i0;
+        int step = 1;
+        lo = hi - 1;
+        while (lo > 0 && tab[lo] > x) {
+            hi = lo;
+            step <<= 1;
+            lo = hi - step;
+        }
+        lo = lo > 0 ? lo : 0;
+    }
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (tab[mid] <= x)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Chart start of DOF d (internal order; valid: d is a DOF whose foot q lies
+// in the bounding box).  KIND 0: the cell that holds the foot (binary
+// searches in the quantile tables); 1: the table cell of chart(node) +
+// network output; 2 (a learned index): the network's cell as the guess of
+// galloping searches that end in the foot's own cell.  Then whichever of that
+// proposal and the node's steered start lies nearer the foot.  With KIND > 0
+// every lane of the wavefront must call it (the network runs on the whole
+// wavefront); the result is meaningful on valid lanes only.
+template <bool F32, int KIND>
+__device__ inline int32_t chart_start(const MeshView &mv, bool valid, int64_t d, typename CT<F32>::R2 x,
+                                      typename CT<F32>::R qx, typename CT<F32>::R qy, double t_np1)
+{
+    using R = typename CT<F32>::R;
+    constexpr bool NET = KIND > 0;
+    int32_t j = 0;
+    float2 guess = make_float2(0.f, 0.f);
+    if (NET) {
+        float feat[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+        float2 c = make_float2(0.f, 0.f);
+        if (valid) {
+            c = mv.chart_node[d];
+            raw_features<R>(c, x.x, x.y, qx, qy, t_np1, feat);
+            mlp_normalise(mv.mlp_norm, feat);
+        }
+        const float2 duv = mlp_forward_wave(mv.mlp_wpack, mv.mlp_bias, feat);  // every lane
+        guess = make_float2(c.x + duv.x, c.y + duv.y);
+        if (valid && KIND == 1)
+            j = chart_lookup(mv.chart_table, mv.chart_g, guess);
+    }
+    if (!valid)
+        return -1;
+    // the foot in the records' float frame, as the chart was built
+    const float fx = F32 ? (float)qx : (float)((double)qx - mv.fc.cx);
+    const float fy = F32 ? (float)qy : (float)((double)qy - mv.fc.cy);
+    if (KIND != 1) {
+        const int g = mv.chart_g;
+        int bu, bv;
+        if (KIND == 0) {
+            bu = upper_index(mv.chart_qx, g, fx);
+            bv = upper_index(mv.chart_qy + (int64_t)bu * g, g, fy);
+        } else {
+            const float u = fminf(fmaxf(guess.x, 0.f), 0.99999994f), v = fminf(fmaxf(guess.y, 0.f), 0.99999994f);
+            bu = gallop_index(mv.chart_qx, g, fx, (int)(u * (float)g));
+            bv = gallop_index(mv.chart_qy + (int64_t)bu * g, g, fy, (int)(v * (float)g));
+        }
+        j = mv.chart_table[(int64_t)bu * g + bv];
+    }
+    const int32_t js = quadrant_start(mv.qstart[d], (float)(qx - x.x), (float)(qy - x.y));
+    return nearer_start<F32>(mv, j, js, qx, qy);
+}
+
 // Variable step at the boundary: a characteristic that leaves the domain is
 // stopped where it crosses the boundary (the treatment of Dirichlet
 // conditions mentioned after eq. (eulero)).  The segment x -> q from the DOF
@@ -942,7 +1059,7 @@ __device__ inline bool boundary_value(const MeshView &mv, bool f32, double xx, d
 // [base, base + 64) of one wavefront: one lane per foot for foot -> start ->
 // walk -> tie rule -> weights; then the wavefront computes its feet's values
 // cooperatively.  Every lane of the wavefront calls it.
-template <bool F32, typename V, int NA>
+template <bool F32, typename V, int NA, int KIND = -1>
 __device__ inline void step_wave(const MeshView &mv, const FieldDev &f, double dt, double t_np1, int scheme, int mode,
                                  const int32_t *__restrict__ start, const V *__restrict__ vin, int k,
                                  V *__restrict__ vout, double outside, int write_prev,
@@ -961,16 +1078,27 @@ __device__ inline void step_wave(const MeshView &mv, const FieldDev &f, double d
 #pragma unroll
     for (int a = 0; a < NA; ++a)
         wgt[a] = (V)0;
+    R2 x;
+    x.x = x.y = (R)0;
+    R qx = (R)0, qy = (R)0;
     if (d < n_iter) {
-        const R2 x = ((const R2 *)mv.dof_xy)[d];
-        R qx, qy;
+        x = ((const R2 *)mv.dof_xy)[d];
         foot_of<R>(f, scheme, x.x, x.y, (R)dt, qx, qy);
+    }
+    // with boundary data every finite foot is walked (to learn where it leaves)
+    const bool run = d < n_iter && (mv.bc_kind ? (isfinite((double)qx) && isfinite((double)qy))
+                                              : in_box<R>(qx, qy, mv.bb));
+    int32_t jc = 0;
+    if constexpr (KIND >= 0)  // chart starts computed here, for the whole wavefront
+        jc = chart_start<F32, KIND>(mv, run, d, x, qx, qy, t_np1);
+    if (d < n_iter) {
         WalkResult<R> w = outside_result<R>(0, 0);
-        // with boundary data every finite foot is walked (to learn where it leaves)
-        const bool run = mv.bc_kind ? (isfinite((double)qx) && isfinite((double)qy)) : in_box<R>(qx, qy, mv.bb);
         if (run) {
-            const int64_t api = (mode == SLW_START_GIVEN && !mv.internal_order) ? mv.dof_user[d] : d;
-            const int32_t j0 = start_for<F32>(mv, d, api, mode, start, (float)(qx - x.x), (float)(qy - x.y));
+            int32_t j0 = jc;
+            if constexpr (KIND < 0) {
+                const int64_t api = (mode == SLW_START_GIVEN && !mv.internal_order) ? mv.dof_user[d] : d;
+                j0 = start_for<F32>(mv, d, api, mode, start, (float)(qx - x.x), (float)(qy - x.y));
+            }
             w = walk<F32>(mv, j0, qx, qy, (uint32_t)d * 2654435761u, ls.c);
         }
         if (write_prev)
@@ -996,15 +1124,15 @@ __device__ inline void step_wave(const MeshView &mv, const FieldDev &f, double d
     wave_interp<V, NA>(row, wgt, nf, vin, k, vout, out_map, base, (V)outside);
 }
 
-template <bool F32, typename V, int NA>
+template <bool F32, typename V, int NA, int KIND = -1>
 __global__ void __launch_bounds__(kBlock)
     k_step(MeshView mv, FieldDev f, double dt, double t_np1, int scheme, int mode, const int32_t *__restrict__ start,
            const V *__restrict__ vin, int k, V *__restrict__ vout, double outside, int write_prev,
            const int32_t *__restrict__ out_map, int64_t n_iter, DevStats *st)
 {
     const int64_t base = xcd_tile(blockIdx.x, gridDim.x) * kBlock + (threadIdx.x & ~(kWave - 1));
-    step_wave<F32, V, NA>(mv, f, dt, t_np1, scheme, mode, start, vin, k, vout, outside, write_prev, out_map, n_iter,
-                          base, st);
+    step_wave<F32, V, NA, KIND>(mv, f, dt, t_np1, scheme, mode, start, vin, k, vout, outside, write_prev, out_map,
+                                n_iter, base, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -1211,123 +1339,6 @@ __global__ void k_permute_rows(const uint32_t *__restrict__ src, uint32_t *__res
         else
             dst[i] = src[(int64_t)map[r] * words + w];
     }
-}
-
-// ---------------------------------------------------------------------------
-// learned start proposal: the network maps a foot to chart coordinates and
-// the chart table to a start triangle; the walk above finishes the search
-
-// raw network inputs of a foot: the node's position (in chart coordinates),
-// its displacement to the foot, time
-template <typename R>
-__device__ inline void raw_features(float2 node_uv, R x, R y, R qx, R qy, double t, float f[5])
-{
-    f[0] = node_uv.x;
-    f[1] = node_uv.y;
-    f[2] = (float)(qx - x);
-    f[3] = (float)(qy - y);
-    f[4] = (float)t;
-}
-
-// largest i in [0, n) with tab[i] <= x (0 when there is none; tab sorted);
-// the trip count depends on n only
-__device__ inline int upper_index(const float *__restrict__ tab, int n, float x)
-{
-    int lo = 0;
-    while (n > 1) {
-        const int half = n >> 1;
-        lo = tab[lo + half] <= x ? lo + half : lo;
-        n -= half;
-    }
-    return lo;
-}
-
-// upper_index searched outwards from a guess i0 (exponential steps, then
-// bisection): the same answer, in about 2 log2 |answer - i0| probes
-__device__ inline int gallop_index(const float *__restrict__ tab, int n, float x, int i0)
-{
-    i0 = i0 < 0 ? 0 : (i0 >= n ? n - 1 : i0);
-    int lo, hi;  // tab[lo] <= x or lo = 0; hi = n or tab[hi] > x
-    if (tab[i0] <= x || i0 == 0) {
-        lo = i0;
-        int step = 1;
-        hi = lo + 1;
-        while (hi < n && tab[hi] <= x) {
-            lo = hi;
-            step <<= 1;
-            hi = lo + step;
-        }
-        hi = hi < n ? hi : n;
-    } else {
-        hi = i0;
-        int step = 1;
-        lo = hi - 1;
-        while (lo > 0 && tab[lo] > x) {
-            hi = lo;
-            step <<= 1;
-            lo = hi - step;
-        }
-        lo = lo > 0 ? lo : 0;
-    }
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (tab[mid] <= x)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
-// Chart start of DOF d (internal order; valid: d is a DOF whose foot q lies
-// in the bounding box).  KIND 0: the cell that holds the foot (binary
-// searches in the quantile tables); 1: the table cell of chart(node) +
-// network output; 2 (a learned index): the network's cell as the guess of
-// galloping searches that end in the foot's own cell.  Then whichever of that
-// proposal and the node's steered start lies nearer the foot.  With KIND > 0
-// every lane of the wavefront must call it (the network runs on the whole
-// wavefront); the result is meaningful on valid lanes only.
-template <bool F32, int KIND>
-__device__ inline int32_t chart_start(const MeshView &mv, bool valid, int64_t d, typename CT<F32>::R2 x,
-                                      typename CT<F32>::R qx, typename CT<F32>::R qy, double t_np1)
-{
-    using R = typename CT<F32>::R;
-    constexpr bool NET = KIND > 0;
-    int32_t j = 0;
-    float2 guess = make_float2(0.f, 0.f);
-    if (NET) {
-        float feat[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-        float2 c = make_float2(0.f, 0.f);
-        if (valid) {
-            c = mv.chart_node[d];
-            raw_features<R>(c, x.x, x.y, qx, qy, t_np1, feat);
-            mlp_normalise(mv.mlp_norm, feat);
-        }
-        const float2 duv = mlp_forward_wave(mv.mlp_wpack, mv.mlp_bias, feat);  // every lane
-        guess = make_float2(c.x + duv.x, c.y + duv.y);
-        if (valid && KIND == 1)
-            j = chart_lookup(mv.chart_table, mv.chart_g, guess);
-    }
-    if (!valid)
-        return -1;
-    // the foot in the records' float frame, as the chart was built
-    const float fx = F32 ? (float)qx : (float)((double)qx - mv.fc.cx);
-    const float fy = F32 ? (float)qy : (float)((double)qy - mv.fc.cy);
-    if (KIND != 1) {
-        const int g = mv.chart_g;
-        int bu, bv;
-        if (KIND == 0) {
-            bu = upper_index(mv.chart_qx, g, fx);
-            bv = upper_index(mv.chart_qy + (int64_t)bu * g, g, fy);
-        } else {
-            const float u = fminf(fmaxf(guess.x, 0.f), 0.99999994f), v = fminf(fmaxf(guess.y, 0.f), 0.99999994f);
-            bu = gallop_index(mv.chart_qx, g, fx, (int)(u * (float)g));
-            bv = gallop_index(mv.chart_qy + (int64_t)bu * g, g, fy, (int)(v * (float)g));
-        }
-        j = mv.chart_table[(int64_t)bu * g + bv];
-    }
-    const int32_t js = quadrant_start(mv.qstart[d], (float)(qx - x.x), (float)(qy - x.y));
-    return nearer_start<F32>(mv, j, js, qx, qy);
 }
 
 // start[d] for the DOFs [0, n_iter) (internal order) by chart_start; feet
@@ -1700,12 +1711,32 @@ hipError_t launch_step(const DevMesh &m, hipStream_t st, const FieldDev &f0, dou
     const int rp = m.bc_kind ? 0 : m.repack;
     if (m.bc_kind && mode == SLW_START_NEIGHBOR)
         return hipErrorNotSupported;
-    if (((mode == SLW_START_LEARNED || mode == SLW_START_CHART) && rp == 0) || mode == SLW_START_LEARNED_INDEX) {
+    const bool chart_mode = mode == SLW_START_LEARNED || mode == SLW_START_CHART || mode == SLW_START_LEARNED_INDEX;
+    const int kind = mode == SLW_START_CHART ? 0 : (mode == SLW_START_LEARNED ? 1 : 2);
+    if (chart_mode && rp == 0 && order == 1 && kind != 1) {
+        // one foot per lane, P1: the chart start is computed inside the step
+        // kernel (not the plain learned start: the network's registers would
+        // lower the occupancy of its long walks; its own kernel runs first)
+#define SLW_STEP_CHART(F32, V, KD)                                                                                \
+    hipLaunchKernelGGL((k_step<F32, V, 3, KD>), dim3(g), dim3(kBlock), 0, st, mv, f, dt, t_n + dt, scheme, mode,    \
+                       start, (const V *)v_in, k, (V *)v_out, outside, (int)write_prev, out_map, n_iter, stats)
+#define SLW_STEP_CHART_K(F32, V)                                                                                  \
+    do {                                                                                                          \
+        if (kind == 0) SLW_STEP_CHART(F32, V, 0); else SLW_STEP_CHART(F32, V, 2);                                 \
+    } while (0)
+        if (m.coords_f32) {
+            if (vdtype == SLW_F32) SLW_STEP_CHART_K(true, float); else SLW_STEP_CHART_K(true, double);
+        } else {
+            if (vdtype == SLW_F32) SLW_STEP_CHART_K(false, float); else SLW_STEP_CHART_K(false, double);
+        }
+#undef SLW_STEP_CHART_K
+#undef SLW_STEP_CHART
+        return hipGetLastError();
+    }
+    if ((chart_mode && rp == 0) || mode == SLW_START_LEARNED_INDEX) {
         // the proposals come from their own kernel (the repacking kernel
         // computes chart and learned starts itself)
-        hipError_t e = launch_chart_start(m, st, f0, t_n + dt, dt, scheme, nullptr, n_iter,
-                                          mode == SLW_START_CHART ? 0 : (mode == SLW_START_LEARNED ? 1 : 2),
-                                          m.learned_start);
+        hipError_t e = launch_chart_start(m, st, f0, t_n + dt, dt, scheme, nullptr, n_iter, kind, m.learned_start);
         if (e != hipSuccess)
             return e;
         start = m.learned_start;
