@@ -1248,7 +1248,7 @@ __device__ inline void field_time_factors_dev(FieldDev &f, double t_np1, double 
 // Items of the concatenated tile space [0, total) of a batch: mesh m owns
 // tiles [items[m].tile0, items[m + 1].tile0).
 template <bool F32, typename V, int BS>
-__device__ inline void batch_tile(const BatchItem *__restrict__ items, int n_items, int64_t tile, int64_t step,
+__device__ __forceinline__ void batch_tile(const BatchItem *__restrict__ items, int n_items, int64_t tile, int64_t step,
                                   int scheme, int k, double outside, DevStats *st)
 {
     int lo = 0, hi = n_items - 1;  // last item with tile0 <= tile (uniform binary search)
@@ -1275,15 +1275,29 @@ __device__ inline void batch_tile(const BatchItem *__restrict__ items, int n_ite
 // from 8 per-XCD queues (each queue covers one XCD's contiguous range) and
 // stealing from the other queues when their own is empty.
 template <bool F32, typename V, int BS>
+__device__ inline void batch_persistent(const BatchItem *__restrict__ items, int n_items, int64_t total,
+                                        int64_t step, int scheme, int k, double outside, unsigned *queues,
+                                        DevStats *st);
+
+// (The schedule is a template parameter: the persistent loop's state would
+// otherwise raise the register count, and lower the occupancy, of both.)
+template <bool F32, typename V, int BS, int SCHEDULE>
 __global__ void __launch_bounds__(BS)
     k_batch_step(const BatchItem *__restrict__ items, int n_items, int64_t total, const int64_t *__restrict__ counter,
-                 int scheme, int k, double outside, int schedule, unsigned *queues, DevStats *st)
+                 int scheme, int k, double outside, unsigned *queues, DevStats *st)
 {
     const int64_t step = *counter;
-    if (schedule == 0) {
+    if constexpr (SCHEDULE == 0)
         batch_tile<F32, V, BS>(items, n_items, xcd_tile(blockIdx.x, gridDim.x), step, scheme, k, outside, st);
-        return;
-    }
+    else
+        batch_persistent<F32, V, BS>(items, n_items, total, step, scheme, k, outside, queues, st);
+}
+
+template <bool F32, typename V, int BS>
+__device__ inline void batch_persistent(const BatchItem *__restrict__ items, int n_items, int64_t total,
+                                        int64_t step, int scheme, int k, double outside, unsigned *queues,
+                                        DevStats *st)
+{
     __shared__ int64_t s_tile;
     constexpr int64_t kXcd = 8;
     const int64_t q = total / kXcd, r = total % kXcd;
@@ -1840,8 +1854,14 @@ hipError_t launch_batch_step(hipStream_t st, int coords_f32, int vdtype, int blo
     }
     const unsigned g = schedule == 1 ? (unsigned)persistent_blocks : (unsigned)total_tiles;
 #define SLW_BSTEP(F32, V, BS)                                                                                      \
-    hipLaunchKernelGGL((k_batch_step<F32, V, BS>), dim3(g), dim3(BS), 0, st, items, n_items, total_tiles, counter, \
-                       scheme, k, outside, schedule, queues, stats)
+    do {                                                                                                           \
+        if (schedule == 1)                                                                                         \
+            hipLaunchKernelGGL((k_batch_step<F32, V, BS, 1>), dim3(g), dim3(BS), 0, st, items, n_items, total_tiles, \
+                               counter, scheme, k, outside, queues, stats);                                        \
+        else                                                                                                       \
+            hipLaunchKernelGGL((k_batch_step<F32, V, BS, 0>), dim3(g), dim3(BS), 0, st, items, n_items, total_tiles, \
+                               counter, scheme, k, outside, queues, stats);                                        \
+    } while (0)
 #define SLW_BSTEP_BS(F32, V)            \
     switch (block) {                    \
     case 64: SLW_BSTEP(F32, V, 64); break;   \
