@@ -90,23 +90,30 @@ __global__ void __launch_bounds__(64)
         for (int c = 0; c < 5; ++c)
             sX[t][c] = x[c];
         // forward (padding lanes carry w = 0: their deltas vanish)
-        float h1[64];
 #pragma unroll
         for (int j = 0; j < 64; ++j) {
             float z = P[kOB1 + j];
 #pragma unroll
             for (int c = 0; c < 5; ++c)
                 z = fmaf(x[c], P[kOW1 + c * 64 + j], z);
-            h1[j] = fmaxf(z, 0.f);
-            sA[t][j] = h1[j];
+            sA[t][j] = fmaxf(z, 0.f);
+        }
+        // layer 2 with the weights read row by row (contiguous, uniform:
+        // wide scalar loads), inputs from LDS, 64 accumulators in registers
+        float z2[64];
+#pragma unroll
+        for (int j = 0; j < 64; ++j)
+            z2[j] = P[kOB2 + j];
+        for (int c = 0; c < 64; ++c) {
+            const float hc = sA[t][c];
+#pragma unroll
+            for (int j = 0; j < 64; ++j)
+                z2[j] = fmaf(hc, P[kOW2 + c * 64 + j], z2[j]);
         }
         float o0 = P[kOB3], o1 = P[kOB3 + 1];
-        for (int j = 0; j < 64; ++j) {
-            float z = P[kOB2 + j];
 #pragma unroll
-            for (int c = 0; c < 64; ++c)
-                z = fmaf(h1[c], P[kOW2 + c * 64 + j], z);
-            const float h2 = fmaxf(z, 0.f);
+        for (int j = 0; j < 64; ++j) {
+            const float h2 = fmaxf(z2[j], 0.f);
             sB[t][j] = h2;
             o0 = fmaf(h2, P[kOW3 + 2 * j], o0);
             o1 = fmaf(h2, P[kOW3 + 2 * j + 1], o1);
@@ -153,11 +160,17 @@ __global__ void __launch_bounds__(64)
             sG[70][t] += sb2;
         }
         __syncthreads();
-        // delta1 = (delta2 W2^T) masked by h1 > 0, over h1 in LDS (own row)
+        // delta1 = (delta2 W2^T) masked by h1 > 0, over h1 in LDS (own row);
+        // delta2 in registers, weight rows contiguous
+        float d2[64];
+#pragma unroll
+        for (int j = 0; j < 64; ++j)
+            d2[j] = sB[t][j];
         for (int c = 0; c < 64; ++c) {
             float z = 0.f;
+#pragma unroll
             for (int j = 0; j < 64; ++j)
-                z = fmaf(sB[t][j], P[kOW2 + c * 64 + j], z);
+                z = fmaf(d2[j], P[kOW2 + c * 64 + j], z);
             const float h = sA[t][c];
             sA[t][c] = h > 0.f ? z : 0.f;
         }
