@@ -359,6 +359,8 @@ def main():
     ap.add_argument("--k", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--only-a", action="store_true", help="measure strategy (a) only")
+    ap.add_argument("--only-b", action="store_true",
+                    help="measure strategy (b) only (a short line, for hardware-counter runs)")
     ap.add_argument("--no-batch", action="store_true", help="skip the multi-mesh batch measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-start measurement")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
@@ -394,6 +396,12 @@ def main():
     v0 = torch.from_numpy(np.ascontiguousarray(w.v0[perm])).to("cuda:0")
     n_feet = mesh.n_nodes
 
+    if args.only_b:
+        rb = measure(mesh, w, v0, args.steps, args.warmup, S.START_PREV)
+        print(json.dumps({"strategy_b": {"ms_per_step": rb["ms_per_step"], "kernel_ms": rb["kernel_ms"],
+                                         "mean_walk_steps": rb["stats"]["walk_steps"] / max(rb["stats"]["feet"], 1)},
+                          "workload": w.name}), flush=True)
+        return
     ra = measure(mesh, w, v0, args.steps, args.warmup, S.START_STEERED)
     value = n_feet / (ra["ms_per_step"] * 1e-3)
     abytes = algorithmic_bytes(n_feet, mesh.n_tris, 16, 4, args.k)
