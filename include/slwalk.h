@@ -194,6 +194,15 @@ slw_status slw_mesh_set_walk_limits(slw_mesh *mesh, int32_t step_cap, int32_t ha
  * maximum.  Results are identical for every setting.  0 selects the
  * library's default. */
 slw_status slw_mesh_set_repack(slw_mesh *mesh, int feet_per_lane);
+/* Width of the neighbour offsets in the walk's 32-byte triangle records.
+ * A walk move reads the float vertex coordinates and the three neighbours
+ * of one triangle; the neighbours are stored as offsets from the triangle's
+ * own (Morton-ordered) id, in `bits`-bit two's complement (2 <= bits <= 21;
+ * 0 selects the default 21), and a neighbour whose offset does not fit is
+ * read from the full record instead.  Narrower codes only add such escapes:
+ * results are identical for every setting.  Rebuilds the records (a device
+ * to host to device copy of the mesh's triangle records; synchronous). */
+slw_status slw_mesh_set_neighbour_codes(slw_mesh *mesh, int bits);
 /* Boundary data for feet that leave the domain (slw_step).  The paper
  * treats Dirichlet conditions by a variable step that stops characteristics
  * on the boundary (remark after eq. eulero).  With kind != SLW_BC_NONE a
@@ -408,6 +417,13 @@ slw_status slw_orient_sign_host(const double *pts_h, int64_t m, int8_t *out_h, i
  * the exact stages. */
 slw_status slw_float_filter_host(const double *pts_h, int64_t m, double cx, double cy, double cmax, int f32,
                                  int8_t *out_h);
+/* Host copy of the neighbour coding of the walk records (for tests): for
+ * triangles t = 0 .. n_tris-1 with neighbours nb_h[3t .. 3t+2] (-1 on the
+ * boundary, ids in the same numbering as t), writes the two 32-bit words
+ * (lo, hi) of each record's codes to words_h[2t], words_h[2t+1]: code k in
+ * bits [21k, 21k + 21) of hi:lo, 0 for a boundary edge, -2^20 when the
+ * offset nb - t does not fit in `bits` bits, else the offset. */
+slw_status slw_walk_codes_host(const int32_t *nb_h, int64_t n_tris, int bits, uint32_t *words_h);
 
 #ifdef __cplusplus
 }

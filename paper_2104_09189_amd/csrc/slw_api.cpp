@@ -291,6 +291,49 @@ slw_status slw_mesh_set_repack(slw_mesh *mesh, int feet_per_lane)
     return SLW_OK;
 }
 
+slw_status slw_mesh_set_neighbour_codes(slw_mesh *mesh, int bits)
+{
+    if (!mesh)
+        return set_error(SLW_E_ARG, "mesh is NULL");
+    if (bits == 0)
+        bits = kCodeBits;
+    if (bits < 2 || bits > kCodeBits)
+        return set_error(SLW_E_ARG, "slw_mesh_set_neighbour_codes: bits must be in [2, 21] (0: default)");
+    DevMesh &m = mesh->m;
+    DeviceGuard g(mesh->ctx->device);
+    std::vector<GeoRec> geo(m.n_tris);
+    slw_status st = hip_check(hipStreamSynchronize(mesh->ctx->stream), "synchronize before recoding");
+    if (st == SLW_OK)
+        st = hip_check(hipMemcpy(geo.data(), m.geo, m.n_tris * sizeof(GeoRec), hipMemcpyDeviceToHost), "copy records");
+    if (st != SLW_OK)
+        return st;
+    const std::vector<WalkRec> w = walk_records(geo, bits);
+    st = hip_check(hipMemcpy(m.wrec, w.data(), m.n_tris * sizeof(WalkRec), hipMemcpyHostToDevice), "copy walk records");
+    if (st == SLW_OK)
+        m.code_bits = bits;
+    return st;
+}
+
+slw_status slw_walk_codes_host(const int32_t *nb_h, int64_t n_tris, int bits, uint32_t *words_h)
+{
+    if (!nb_h || !words_h || n_tris < 0)
+        return set_error(SLW_E_ARG, "slw_walk_codes_host: null array or negative size");
+    if (bits < 2 || bits > kCodeBits)
+        return set_error(SLW_E_ARG, "slw_walk_codes_host: bits must be in [2, 21]");
+    std::vector<GeoRec> geo(n_tris);
+    for (int64_t t = 0; t < n_tris; ++t) {
+        std::memset(&geo[t], 0, sizeof(GeoRec));
+        for (int k = 0; k < 3; ++k)
+            geo[t].nb[k] = nb_h[3 * t + k];
+    }
+    const std::vector<WalkRec> w = walk_records(geo, bits);
+    for (int64_t t = 0; t < n_tris; ++t) {
+        words_h[2 * t] = w[t].lo;
+        words_h[2 * t + 1] = w[t].hi;
+    }
+    return SLW_OK;
+}
+
 slw_status slw_mesh_set_boundary(slw_mesh *mesh, int kind, const double *p_h)
 {
     if (!mesh)

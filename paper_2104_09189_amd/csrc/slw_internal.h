@@ -25,6 +25,22 @@ struct alignas(16) GeoRec {
 };
 static_assert(sizeof(GeoRec) == 48, "GeoRec layout");
 
+// Walk record (32 bytes: two 16-byte loads that never straddle a cache
+// line), the part of GeoRec a walk move needs: the same float coordinates and
+// the three neighbours as 21-bit two's-complement offsets from the
+// triangle's own internal id, code k in bits [21k, 21k + 21) of the 64-bit
+// word (hi:lo).  Code 0 marks a boundary edge (a triangle is never its own
+// neighbour); kCodeEscape marks an offset that does not fit, the neighbour is
+// then read from GeoRec::nb.  Along a Morton order nearly every neighbour
+// lies within 2^20 ids (all of them for meshes of up to 2^20 triangles).
+struct alignas(32) WalkRec {
+    float2 p[3];
+    uint32_t lo, hi;
+};
+static_assert(sizeof(WalkRec) == 32, "WalkRec layout");
+constexpr int kCodeBits = 21;
+constexpr int32_t kCodeEscape = -(1 << (kCodeBits - 1));
+
 // Coefficients of the float filter's error bound (see the walk kernel):
 // |det_float - det| <= c1 (|l| + |r|) + c2 (|ax|+|ay|+|bx|+|by|) + c3.
 struct FilterConst {
@@ -39,6 +55,8 @@ struct DevMesh {
     FilterConst fc = {0, 0, 0, 0, 0};
     // device arrays (internal order)
     GeoRec *geo = nullptr;        // [n_tris]
+    WalkRec *wrec = nullptr;      // [n_tris] the walk's copy of geo (packed neighbours)
+    int code_bits = kCodeBits;    // widest neighbour offset coded in wrec (narrower: more escapes)
     int32_t *tri_uf = nullptr;    // [n_tris] user id | (1 << 31 if vertices 1, 2 were swapped to make it CCW)
     int4 *tedge = nullptr;        // [n_tris] P2: internal DOF ids of the edge opposite vertex k
     void *dof_xy = nullptr;       // double2/float2 [n_dofs], exact coordinates
@@ -156,6 +174,9 @@ void free_mesh(DevMesh &m);
 // coefficients of the walk's float filter for a mesh whose float coordinates
 // are fl32(x - (cx, cy)) with |x - c| <= cmax (f32: coordinates already float)
 FilterConst filter_constants(bool f32, double cx, double cy, double cmax);
+// walk records of the records geo, neighbour offsets coded when they fit in
+// `bits` bits (2 <= bits <= kCodeBits), escaped otherwise
+std::vector<WalkRec> walk_records(const std::vector<GeoRec> &geo, int bits);
 
 // launchers (slw_kernels.hip)
 
@@ -163,6 +184,7 @@ FilterConst filter_constants(bool f32, double cx, double cy, double cmax);
 // filter constants), passed by value.
 struct MeshView {
     const GeoRec *geo;
+    const WalkRec *wrec;
     const int32_t *tri_uf;
     const int4 *tedge;
     const void *dof_xy;

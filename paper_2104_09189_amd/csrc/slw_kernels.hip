@@ -108,6 +108,7 @@ MeshView view_of(const DevMesh &m)
 {
     MeshView v;
     v.geo = m.geo;
+    v.wrec = m.wrec;
     v.tri_uf = m.tri_uf;
     v.tedge = m.tedge;
     v.dof_xy = m.dof_xy;
@@ -163,7 +164,7 @@ __device__ inline int32_t nearer_start(const MeshView &mv, int32_t ja, int32_t j
 {
     const float fx = F32 ? (float)qx : (float)((double)qx - mv.fc.cx);
     const float fy = F32 ? (float)qy : (float)((double)qy - mv.fc.cy);
-    const GeoRec ra = mv.geo[ja], rb = mv.geo[jb];
+    const WalkRec ra = mv.wrec[ja], rb = mv.wrec[jb];
     const float ax = (ra.p[0].x + ra.p[1].x + ra.p[2].x) * (1.f / 3.f) - fx;
     const float ay = (ra.p[0].y + ra.p[1].y + ra.p[2].y) * (1.f / 3.f) - fy;
     const float bx = (rb.p[0].x + rb.p[1].x + rb.p[2].x) * (1.f / 3.f) - fx;
@@ -231,19 +232,20 @@ __device__ __noinline__ int slow_sign(const void *dof_xy, float2 pa, float2 pb, 
 }
 
 // Signs of the three edge orientations o_k = orient(x_{k+1}, x_{k+2}, q) of
-// record r: the float filter on the rounded inputs (filter_sign_f32) decides
-// when its bound allows, the exact coordinates otherwise.  o[] keeps the
-// float values, used to pick among negative edges (any negative edge is a
-// valid move).
+// triangle j with float vertex coordinates p: the float filter on the
+// rounded inputs (filter_sign_f32) decides when its bound allows, the exact
+// coordinates otherwise (read through the vertex ids of geo[j]).  o[] keeps
+// the float values, used to pick among negative edges (any negative edge is
+// a valid move).
 template <bool F32>
-__device__ inline void edge_signs(const MeshView &mv, const GeoRec &r, float qfx, float qfy,
+__device__ inline void edge_signs(const MeshView &mv, int32_t j, const float2 p[3], float qfx, float qfy,
                                   typename CT<F32>::R qx, typename CT<F32>::R qy, float o[3], int s[3], Counters &c)
 {
     float dx[3], dy[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        dx[k] = r.p[k].x - qfx;
-        dy[k] = r.p[k].y - qfy;
+        dx[k] = p[k].x - qfx;
+        dy[k] = p[k].y - qfy;
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -255,7 +257,8 @@ __device__ inline void edge_signs(const MeshView &mv, const GeoRec &r, float qfx
         for (int k = 0; k < 3; ++k) {
             if (s[k] == 0) {
                 const int a = (k + 1) % 3, b = (k + 2) % 3;
-                const int sg = slow_sign<F32>(mv.dof_xy, r.p[a], r.p[b], r.v[a], r.v[b], qx, qy);
+                const int32_t *v = mv.geo[j].v;
+                const int sg = slow_sign<F32>(mv.dof_xy, p[a], p[b], v[a], v[b], qx, qy);
                 ++c.fp64;
                 c.exact += (sg == 2 || sg == -2 || sg == 0);
                 s[k] = sg > 0 ? 1 : (sg < 0 ? -1 : 0);
@@ -263,6 +266,27 @@ __device__ inline void edge_signs(const MeshView &mv, const GeoRec &r, float qfx
         }
     }
 }
+
+// the three neighbour codes of a walk record (offsets, 0 boundary,
+// kCodeEscape: read GeoRec::nb)
+__device__ inline void nb_codes(const WalkRec &r, int32_t cd[3])
+{
+    static_assert(kCodeBits == 21, "decoding assumes 21-bit codes");
+    cd[0] = (int32_t)(r.lo << 11) >> 11;
+    cd[1] = (int32_t)(__builtin_amdgcn_alignbit(r.hi, r.lo, 21) << 11) >> 11;
+    cd[2] = (int32_t)(r.hi << 1) >> 11;
+}
+
+// neighbour k of triangle j from its code (-1 on the boundary)
+__device__ inline int32_t nb_of(const MeshView &mv, int32_t j, int k, int32_t code)
+{
+    if (code == kCodeEscape)
+        return mv.geo[j].nb[k];
+    return code == 0 ? -1 : j + code;
+}
+
+// {nb[2], v[0], v[1], v[2]} of triangle j: the vertex ids with one load
+__device__ inline int4 tri_verts(const MeshView &mv, int32_t j) { return ((const int4 *)(mv.geo + j))[2]; }
 
 __device__ inline int32_t sel3(int k, int32_t a, int32_t b, int32_t c) { return k == 0 ? a : (k == 1 ? b : c); }
 
@@ -304,22 +328,24 @@ __device__ inline WalkResult<R> outside_result(int32_t steps, int32_t flags)
 // 2 = outside (a negative coordinate across boundary edge zmask of r; or
 // the hard step limit: then zmask = -1 and flags gets bits 0 and 1).
 template <bool F32>
-__device__ inline int walk_move(const MeshView &mv, int32_t &j, GeoRec &r, int &zmask, float qfx, float qfy,
+__device__ inline int walk_move(const MeshView &mv, int32_t &j, WalkRec &r, int &zmask, float qfx, float qfy,
                                 typename CT<F32>::R qx, typename CT<F32>::R qy, uint32_t seed, int32_t &steps,
                                 int32_t &flags, Counters &c)
 {
     float o[3];
     int s[3];
-    r = mv.geo[j];
-    edge_signs<F32>(mv, r, qfx, qfy, qx, qy, o, s, c);
+    r = mv.wrec[j];
+    edge_signs<F32>(mv, j, r.p, qfx, qfy, qx, qy, o, s, c);
     const bool n0 = s[0] < 0, n1 = s[1] < 0, n2 = s[2] < 0;
     if (!(n0 | n1 | n2)) {
         zmask = (int)(s[0] == 0) | ((int)(s[1] == 0) << 1) | ((int)(s[2] == 0) << 2);
         return 1;
     }
+    int32_t cd[3];
+    nb_codes(r, cd);
     // a negative side on the boundary: the foot is outside the (convex) domain;
     // zmask tells through which edge
-    const bool x0 = n0 && r.nb[0] < 0, x1 = n1 && r.nb[1] < 0, x2 = n2 && r.nb[2] < 0;
+    const bool x0 = n0 && cd[0] == 0, x1 = n1 && cd[1] == 0, x2 = n2 && cd[2] == 0;
     if (x0 || x1 || x2) {
         zmask = x0 ? 0 : (x1 ? 1 : 2);
         return 2;
@@ -346,33 +372,34 @@ __device__ inline int walk_move(const MeshView &mv, int32_t &j, GeoRec &r, int &
         const int second = (n0 && n1) ? 1 : 2;
         k = pick == 0 ? first : (pick == 1 ? second : 2);
     }
-    j = sel3(k, r.nb[0], r.nb[1], r.nb[2]);
+    const int32_t ck = sel3(k, cd[0], cd[1], cd[2]);  // never 0 here: edge k is interior
+    j = ck == kCodeEscape ? mv.geo[j].nb[k] : j + ck;
     ++steps;
     return 0;
 }
 
-// Barycentric coordinates of q in the triangle of record r (internal
-// counter-clockwise vertex order) on the exact coordinates:
+// Barycentric coordinates of q in a triangle (internal counter-clockwise
+// vertex order; float coordinates p, vertex ids v) on the exact coordinates:
 // theta_k = o_k / (o_0 + o_1 + o_2), o_k = orient(x_{k+1}, x_{k+2}, q)
 template <bool F32>
-__device__ inline void exact_weights(const MeshView &mv, const GeoRec &r, typename CT<F32>::R qx,
-                                     typename CT<F32>::R qy, typename CT<F32>::R th[3])
+__device__ inline void exact_weights(const MeshView &mv, const float2 p[3], const int32_t v[3],
+                                     typename CT<F32>::R qx, typename CT<F32>::R qy, typename CT<F32>::R th[3])
 {
     using R = typename CT<F32>::R;
     R ex[3], ey[3];
     if constexpr (F32) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            ex[k] = r.p[k].x - qx;
-            ey[k] = r.p[k].y - qy;
+            ex[k] = p[k].x - qx;
+            ey[k] = p[k].y - qy;
         }
     } else {
         const double2 *X = (const double2 *)mv.dof_xy;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const double2 p = X[r.v[k]];
-            ex[k] = p.x - qx;
-            ey[k] = p.y - qy;
+            const double2 xv = X[v[k]];
+            ex[k] = xv.x - qx;
+            ey[k] = xv.y - qy;
         }
     }
     R oo[3];
@@ -387,38 +414,52 @@ __device__ inline void exact_weights(const MeshView &mv, const GeoRec &r, typena
         th[k] = oo[k] / sum;
 }
 
-// End of a walk that stopped in triangle j (record r, zero-sign mask zmask):
-// the tie rule (smallest user id among the closed containers), then the
-// weights on the exact coordinates.
+// End of a walk that stopped in triangle j (walk record r, zero-sign mask
+// zmask): the tie rule (smallest user id among the closed containers), then
+// the weights on the exact coordinates.
 template <bool F32>
-__device__ inline WalkResult<typename CT<F32>::R> finish_walk(const MeshView &mv, int32_t j, GeoRec r, int zmask,
-                                                              int32_t steps, int32_t flags,
+__device__ inline WalkResult<typename CT<F32>::R> finish_walk(const MeshView &mv, int32_t j, const WalkRec &r,
+                                                              int zmask, int32_t steps, int32_t flags,
                                                               typename CT<F32>::R qx, typename CT<F32>::R qy)
 {
     using R = typename CT<F32>::R;
     const int z = (zmask & 1) + ((zmask >> 1) & 1) + ((zmask >> 2) & 1);
+    int4 tv = tri_verts(mv, j);
     int32_t e = j;
     if (z == 1) {
         const int k = (zmask & 1) ? 0 : ((zmask & 2) ? 1 : 2);
-        const int32_t nbk = sel3(k, r.nb[0], r.nb[1], r.nb[2]);
+        int32_t cd[3];
+        nb_codes(r, cd);
+        const int32_t nbk = nb_of(mv, j, k, sel3(k, cd[0], cd[1], cd[2]));
         flags |= 4;
         if (nbk >= 0 && (mv.tri_uf[nbk] & kUidMask) < (mv.tri_uf[j] & kUidMask))
             e = nbk;
     } else if (z == 2) {
         const int cidx = !(zmask & 1) ? 0 : (!(zmask & 2) ? 1 : 2);
         flags |= 8;
-        e = mv.vmin[sel3(cidx, r.v[0], r.v[1], r.v[2])];
+        e = mv.vmin[sel3(cidx, tv.y, tv.z, tv.w)];
     }
-    if (e != j)
-        r = mv.geo[e];
+    float2 p[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        p[k] = r.p[k];
+    if (e != j) {
+        tv = tri_verts(mv, e);
+        if constexpr (F32) {
+            const WalkRec re = mv.wrec[e];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                p[k] = re.p[k];
+        }
+    }
     WalkResult<R> w;
     w.elem = e;
     w.steps = steps;
     w.flags = flags;
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-        w.v[k] = r.v[k];
-    exact_weights<F32>(mv, r, qx, qy, w.th);
+    w.v[0] = tv.y;
+    w.v[1] = tv.z;
+    w.v[2] = tv.w;
+    exact_weights<F32>(mv, p, w.v, qx, qy, w.th);
     return w;
 }
 
@@ -431,7 +472,7 @@ __device__ WalkResult<typename CT<F32>::R> walk(const MeshView &mv, int32_t j, t
     using R = typename CT<F32>::R;
     const float qfx = F32 ? (float)qx : (float)((double)qx - mv.fc.cx);
     const float qfy = F32 ? (float)qy : (float)((double)qy - mv.fc.cy);
-    GeoRec r;
+    WalkRec r;
     int zmask = 0;
     int32_t steps = 0, flags = 0;
     for (;;) {
@@ -441,8 +482,9 @@ __device__ WalkResult<typename CT<F32>::R> walk(const MeshView &mv, int32_t j, t
         if (st == 2) {
             WalkResult<R> w = outside_result<R>(steps, flags);
             if (zmask >= 0) {  // the boundary edge opposite vertex zmask, counter-clockwise
-                w.v[0] = sel3(zmask, r.v[1], r.v[2], r.v[0]);
-                w.v[1] = sel3(zmask, r.v[2], r.v[0], r.v[1]);
+                const int4 tv = tri_verts(mv, j);
+                w.v[0] = sel3(zmask, tv.z, tv.w, tv.y);
+                w.v[1] = sel3(zmask, tv.w, tv.y, tv.z);
                 w.flags |= 16;
             }
             return w;
@@ -625,7 +667,7 @@ __global__ void __launch_bounds__(kBlock)
     if (i < m) {
         const R qx = q[i].x, qy = q[i].y;
         int32_t best = -1, best_uid = 0x7fffffff;
-        GeoRec rb;
+        WalkRec rb;
         if (in_box<R>(qx, qy, mv.bb)) {
             const float qfx = F32 ? (float)qx : (float)((double)qx - mv.fc.cx);
             const float qfy = F32 ? (float)qy : (float)((double)qy - mv.fc.cy);
@@ -640,10 +682,10 @@ __global__ void __launch_bounds__(kBlock)
             }
             for (int32_t c = 0; c < nd.z; ++c) {
                 const int32_t t = lists[nd.y + c];
-                const GeoRec r = mv.geo[t];
+                const WalkRec r = mv.wrec[t];
                 float o[3];
                 int sg[3];
-                edge_signs<F32>(mv, r, qfx, qfy, qx, qy, o, sg, ls.c);
+                edge_signs<F32>(mv, t, r.p, qfx, qfy, qx, qy, o, sg, ls.c);
                 if (sg[0] >= 0 && sg[1] >= 0 && sg[2] >= 0) {
                     const int32_t uid = mv.tri_uf[t] & kUidMask;
                     if (uid < best_uid) {
@@ -662,7 +704,9 @@ __global__ void __launch_bounds__(kBlock)
         if (bary) {
             if (best >= 0) {
                 R th[3], ub[3];
-                exact_weights<F32>(mv, rb, qx, qy, th);
+                const int4 tv = tri_verts(mv, best);
+                const int32_t v[3] = {tv.y, tv.z, tv.w};
+                exact_weights<F32>(mv, rb.p, v, qx, qy, th);
                 user_bary<R>(mv.tri_uf[best], th, ub);
                 bary[3 * i] = ub[0];
                 bary[3 * i + 1] = ub[1];
@@ -863,14 +907,15 @@ __global__ void __launch_bounds__(kBlock)
         // ids outside [0, n_tris) are treated as outside
         const int32_t e = (u >= 0 && u < mv.n_tris) ? mv.tri_int[u] : -1;
         if (e >= 0) {
-            const GeoRec r = mv.geo[e];
+            const int4 tv = tri_verts(mv, e);
+            const int32_t v[3] = {tv.y, tv.z, tv.w};
             const bool flip = mv.tri_uf[e] < 0;
             // user vertex order -> internal order
             R th[3];
             th[0] = bary[3 * i];
             th[1] = flip ? bary[3 * i + 2] : bary[3 * i + 1];
             th[2] = flip ? bary[3 * i + 1] : bary[3 * i + 2];
-            lagrange<R, V, NA>(mv, e, r.v, th, row, wgt);
+            lagrange<R, V, NA>(mv, e, v, th, row, wgt);
             if (user_rows) {
 #pragma unroll
                 for (int a = 0; a < NA; ++a)
@@ -1482,7 +1527,7 @@ __device__ inline void step_chunk(const MeshView &mv, const FieldDev &f, double 
             continue;
         }
         if (slot >= 0) {
-            GeoRec r;
+            WalkRec r;
             int zmask = 0;
             const int res = walk_move<F32>(mv, j, r, zmask, qfx, qfy, qx, qy, seed, steps, flags, ls.c);
             if (res != 0) {
@@ -1516,7 +1561,7 @@ __device__ inline void step_chunk(const MeshView &mv, const FieldDev &f, double 
             int32_t elem = -1;
             if (e0 >= 0) {
                 const R2 q = sq[sl];
-                const WalkResult<R> w = finish_walk<F32>(mv, e0, mv.geo[e0], (int)sz[sl], 0, 0, q.x, q.y);
+                const WalkResult<R> w = finish_walk<F32>(mv, e0, mv.wrec[e0], (int)sz[sl], 0, 0, q.x, q.y);
                 ls.add_ties(w.flags);
                 elem = w.elem;
                 lagrange<R, V, NA>(mv, w.elem, w.v, w.th, row, wgt);

@@ -130,9 +130,35 @@ FilterConst filter_constants(bool f32, double cx, double cy, double cmax)
     return fc;
 }
 
+std::vector<WalkRec> walk_records(const std::vector<GeoRec> &geo, int bits)
+{
+    bits = std::min(std::max(bits, 2), kCodeBits);
+    const int64_t lim = (int64_t)1 << (bits - 1);  // offsets in (-lim, lim) are coded
+    std::vector<WalkRec> w(geo.size());
+    for (size_t t = 0; t < geo.size(); ++t) {
+        uint64_t word = 0;
+        for (int k = 0; k < 3; ++k) {
+            const int64_t nb = geo[t].nb[k];
+            int32_t code;
+            if (nb < 0)
+                code = 0;
+            else if (nb - (int64_t)t > -lim && nb - (int64_t)t < lim)
+                code = (int32_t)(nb - (int64_t)t);
+            else
+                code = kCodeEscape;
+            word |= (uint64_t)((uint32_t)code & ((1u << kCodeBits) - 1u)) << (kCodeBits * k);
+        }
+        for (int k = 0; k < 3; ++k)
+            w[t].p[k] = geo[t].p[k];
+        w[t].lo = (uint32_t)word;
+        w[t].hi = (uint32_t)(word >> 32);
+    }
+    return w;
+}
+
 void free_mesh(DevMesh &m)
 {
-    void *ptrs[] = {m.geo, m.tri_uf, m.tedge, m.dof_xy, m.qstart, m.vmin, m.dof_user,
+    void *ptrs[] = {m.geo, m.wrec, m.tri_uf, m.tedge, m.dof_xy, m.qstart, m.vmin, m.dof_user,
                     m.dof_int, m.tri_int, m.prev_elem, m.jump, m.chart_uv, m.chart_node, m.chart_table,
                     m.chart_qx, m.chart_qy, m.learned_start, m.bnext, m.bprev, m.qt_nodes, m.qt_lists};
     for (void *p : ptrs)
@@ -537,6 +563,10 @@ slw_status build_mesh(slw_ctx *ctx, const double *xy, int64_t n, const int32_t *
         }                                              \
     } while (0)
     UP(geo, m.geo);
+    {
+        std::vector<WalkRec> wr = walk_records(geo, kCodeBits);
+        UP(wr, m.wrec);
+    }
     UP(tri_uf, m.tri_uf);
     if (f32) {
         std::vector<float2> dxy(ndof);

@@ -98,6 +98,8 @@ _sig("slw_mesh_dof_coords", ctypes.c_int, [_vp, _vp])
 _sig("slw_mesh_dof_order", ctypes.c_int, [_vp, _vp])
 _sig("slw_mesh_set_walk_limits", ctypes.c_int, [_vp, _i32, _i32])
 _sig("slw_mesh_set_repack", ctypes.c_int, [_vp, ctypes.c_int])
+_sig("slw_mesh_set_neighbour_codes", ctypes.c_int, [_vp, ctypes.c_int])
+_sig("slw_walk_codes_host", ctypes.c_int, [_vp, _i64, ctypes.c_int, _vp])
 _sig("slw_mesh_set_chain", ctypes.c_int, [_vp, ctypes.c_int])
 _sig("slw_mesh_set_boundary", ctypes.c_int, [_vp, ctypes.c_int, _vp])
 _sig("slw_locate", ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, _vp, _vp])
@@ -148,7 +150,7 @@ MLP_PARAMS = 5 * 64 + 64 + 64 * 64 + 64 + 64 * 2 + 2
 
 EXPORTED = ["slw_status_string", "slw_last_error", "slw_ctx_create", "slw_ctx_set_stream", "slw_ctx_destroy",
             "slw_mesh_upload", "slw_mesh_check", "slw_mesh_free", "slw_mesh_get_info", "slw_mesh_dof_coords", "slw_mesh_dof_order",
-            "slw_mesh_set_walk_limits", "slw_mesh_set_repack", "slw_mesh_set_chain", "slw_mesh_set_boundary", "slw_locate", "slw_locate_feet", "slw_interpolate", "slw_step",
+            "slw_mesh_set_walk_limits", "slw_mesh_set_repack", "slw_mesh_set_neighbour_codes", "slw_walk_codes_host", "slw_mesh_set_chain", "slw_mesh_set_boundary", "slw_locate", "slw_locate_feet", "slw_interpolate", "slw_step",
             "slw_permute_rows", "slw_orient_sign_host",
             "slw_float_filter_host", "slw_batch_create", "slw_batch_free", "slw_batch_set_fields",
             "slw_batch_set_values", "slw_batch_set_step", "slw_batch_get_step", "slw_batch_set_schedule",
@@ -300,6 +302,9 @@ class Mesh:
 
     def set_repack(self, feet_per_lane: int):
         _check(_lib.slw_mesh_set_repack(self.h, int(feet_per_lane)), "slw_mesh_set_repack")
+
+    def set_neighbour_codes(self, bits: int):
+        _check(_lib.slw_mesh_set_neighbour_codes(self.h, int(bits)), "slw_mesh_set_neighbour_codes")
 
     def set_chain(self, length: int):
         _check(_lib.slw_mesh_set_chain(self.h, int(length)), "slw_mesh_set_chain")
@@ -691,6 +696,16 @@ def slw_float_filter_host(pts, cx: float, cy: float, cmax: float, f32: bool = Fa
     out = np.empty(pts.shape[0], dtype=np.int8)
     _check(_lib.slw_float_filter_host(pts.ctypes.data_as(_vp), pts.shape[0], float(cx), float(cy), float(cmax),
                                       int(f32), out.ctypes.data_as(_vp)), "slw_float_filter_host")
+    return out
+
+
+def slw_walk_codes_host(nb, bits: int = 21) -> np.ndarray:
+    """The neighbour codes of the walk records on the host: (n, 2) uint32
+    words (lo, hi) for neighbour triples nb (n, 3), -1 on the boundary."""
+    nb = np.ascontiguousarray(nb, dtype=np.int32).reshape(-1, 3)
+    out = np.empty((nb.shape[0], 2), dtype=np.uint32)
+    _check(_lib.slw_walk_codes_host(nb.ctypes.data_as(_vp), nb.shape[0], int(bits), out.ctypes.data_as(_vp)),
+           "slw_walk_codes_host")
     return out
 
 

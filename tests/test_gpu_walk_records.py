@@ -1,0 +1,103 @@
+"""Neighbour codes of the walk records: any code width gives the same
+elements, weights, values and walk statistics (narrow codes force the escape
+path on most moves), and the oracle's elements."""
+import numpy as np
+import pytest
+
+from paper_2104_09189_amd import inputs as I
+from gpu_util import ctx as _ctx, dev, host, rel_err
+
+pytestmark = pytest.mark.gpu
+
+WIDTHS = (21, 8, 2)
+STAT_KEYS = ("feet", "outside", "walk_steps", "max_steps", "edge_ties", "vertex_ties", "fallback_walks")
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2104_09189_amd import slwalk
+    return slwalk
+
+
+@pytest.fixture(scope="module")
+def C(S):
+    return _ctx()
+
+
+def test_locate_same_elements_every_width(S, C, orc):
+    # user order random: internal Morton ids still give small offsets, the
+    # narrow widths escape
+    xy, tri = I.permute_mesh(*I.jittered_grid(65, 901), 902)
+    q = np.concatenate([I.random_points(20000, 903), xy, 0.5 * (xy[tri[:, 0]] + xy[tri[:, 1]])])
+    mesh = S.Mesh(C, xy, tri)
+    ref, ref_b = orc.locate(xy, tri, q)
+    res = {}
+    for b in WIDTHS:
+        mesh.set_neighbour_codes(b)
+        elem, bary, steps = mesh.locate(dev(q), want_steps=True)
+        res[b] = {"elem": host(elem).copy(), "bary": host(bary).copy(), "steps": host(steps).copy()}
+        assert np.array_equal(res[b]["elem"], ref), b
+        inside = ref >= 0
+        assert np.abs(res[b]["bary"][inside] - ref_b[inside]).max() < 1e-12
+    for b in WIDTHS[1:]:
+        for k in res[21]:
+            assert np.array_equal(res[b][k], res[21][k], equal_nan=True), (b, k)
+    mesh.set_neighbour_codes(0)
+
+
+@pytest.mark.parametrize("flags", [0, "P2", "COORDS_F32"])
+def test_step_same_bits_every_width(S, C, orc, flags):
+    xy, tri = I.jittered_grid(49, 904)
+    fl = getattr(S, flags) if flags else 0
+    mesh = S.Mesh(C, xy, tri, fl)
+    h = 1.0 / 48
+    fld, dt = I.swirl(1.0), 6 * h
+    n = mesh.n_dofs
+    dof = mesh.dof_coords() if flags == "P2" else xy
+    v0 = np.stack([I.gaussian_hill(dof), dof[:, 0] - 0.3 * dof[:, 1]], axis=1).astype(np.float32)
+    order = 2 if flags == "P2" else 1
+    res = {}
+    for b in WIDTHS:
+        mesh.set_neighbour_codes(b)
+        for rp in (1, 4):
+            mesh.set_repack(rp)
+            v, st = mesh.step(fld, 0.2, dt, S.SLW_RK2, dev(v0), order=order, stats=True)
+            res[(b, rp)] = (host(v).copy(), {k: st[k] for k in STAT_KEYS})
+    mesh.set_repack(0)
+    mesh.set_neighbour_codes(0)
+    v1, s1 = res[(21, 1)]
+    assert s1["feet"] == n and s1["walk_steps"] > n
+    for key, (v, s) in res.items():
+        assert np.array_equal(v, v1), key
+        assert s == s1, (key, s, s1)
+
+
+def test_strategy_b_and_outside_feet_every_width(S, C, orc):
+    # a constant field that pushes a band of feet out of the domain
+    xy, tri = I.jittered_grid(41, 905)
+    mesh = S.Mesh(C, xy, tri)
+    fld, dt = I.constant(0.9, -0.4), 0.05
+    v0 = I.gaussian_hill(xy)
+    outs = {}
+    for b in WIDTHS:
+        mesh.set_neighbour_codes(b)
+        e1 = host(mesh.locate_feet(fld, dt, dt, S.SLW_EULER, start_mode=S.START_PREV)["elem"]).copy()
+        e2 = host(mesh.locate_feet(fld, 2 * dt, dt, S.SLW_EULER, start_mode=S.START_PREV)["elem"]).copy()
+        v, st = mesh.step(fld, 0.0, dt, S.SLW_EULER, dev(v0), stats=True)
+        outs[b] = (e1, e2, host(v).copy(), st["outside"])
+    assert outs[21][3] > 0
+    for b in WIDTHS[1:]:
+        for a, c in zip(outs[b], outs[21]):
+            assert np.array_equal(a, c), b
+    ref, _, e_ref, _ = orc.sl_step(xy, tri, v0, fld, 0.0, dt, I.SCHEME_EULER)
+    assert np.array_equal(outs[2][0], e_ref)
+    assert rel_err(outs[2][2].ravel(), np.asarray(ref).ravel(), np.abs(v0).max()) < 1e-12
+    mesh.set_neighbour_codes(0)
+
+
+def test_neighbour_code_width_is_checked(S, C):
+    xy, tri = I.jittered_grid(9, 906)
+    mesh = S.Mesh(C, xy, tri)
+    for b in (1, 22, -3):
+        with pytest.raises(S.SlwError):
+            mesh.set_neighbour_codes(b)

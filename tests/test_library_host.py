@@ -203,3 +203,41 @@ def test_walk_float_filter_certifies_typical_walk_tests(S, orc):
     cert = got != 2
     assert (got[cert] == exact[cert]).all()
     assert cert.mean() > 0.99, cert.mean()
+
+
+def _decode_codes(words):
+    """Neighbour codes of the walk records: code k in bits [21k, 21k + 21) of
+    the 64-bit word hi:lo, two's complement."""
+    w = words[:, 0].astype(np.uint64) | (words[:, 1].astype(np.uint64) << np.uint64(32))
+    out = np.empty((words.shape[0], 3), dtype=np.int64)
+    for k in range(3):
+        c = ((w >> np.uint64(21 * k)) & np.uint64((1 << 21) - 1)).astype(np.int64)
+        out[:, k] = np.where(c >= 1 << 20, c - (1 << 21), c)
+    return out
+
+
+@pytest.mark.parametrize("bits", [2, 5, 12, 21])
+def test_walk_record_neighbour_codes(S, bits):
+    # neighbour triples with every kind of offset: boundary, +-1, near the
+    # code limits, far (escapes), the largest ids
+    rng = np.random.default_rng(bits)
+    n = 1 << 22
+    t = np.concatenate([rng.integers(0, n, 20000), [0, 1, n - 1, n - 2, 1 << 20, (1 << 20) + 7]])
+    t = np.unique(t)
+    off = rng.choice([-1, 1, -(1 << 19), (1 << 19), -(1 << 20) + 1, (1 << 20) - 1, -(1 << 20), 1 << 20,
+                      -(1 << bits - 1) + 1, (1 << bits - 1) - 1, -(1 << bits - 1), 1 << bits - 1, 3, -3],
+                     size=(t.size, 3))
+    nb = t[:, None] + off
+    nb = np.where((nb < 0) | (nb >= n) | (rng.random(nb.shape) < 0.1), -1, nb)
+    # triangles listed densely: ids 0..len-1 map to t via a full table
+    full = -np.ones((n, 3), dtype=np.int64)
+    full[t] = nb
+    words = S.slw_walk_codes_host(full.astype(np.int32), bits)
+    codes = _decode_codes(words)[t]
+    lim = 1 << (bits - 1)
+    d = nb - t[:, None]
+    fits = (nb >= 0) & (d > -lim) & (d < lim)
+    assert np.array_equal(codes == 0, nb < 0)
+    assert np.array_equal(codes == -(1 << 20), (nb >= 0) & ~fits)
+    assert np.array_equal(np.where(fits, t[:, None] + codes, -7), np.where(fits, nb, -7))
+    assert np.all(words[:, 1] >> 31 == 0)
