@@ -38,6 +38,27 @@ struct CT<true> {
     using R2 = float2;
 };
 
+// Accesses marked non-temporal: data a step touches once (the new values,
+// the previous element of strategy (b)) need not take cache lines from the
+// value rows and triangle records that neighbouring feet reuse.  (A DOF's own
+// coordinates are reused: the weights of nearby feet read them.)
+__device__ inline void store_stream(float4 *p, float4 v)
+{
+    typedef float nv4 __attribute__((ext_vector_type(4)));
+    nv4 t = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(t, (nv4 *)p);
+}
+__device__ inline void store_stream(double2 *p, double2 v)
+{
+    typedef double nv2 __attribute__((ext_vector_type(2)));
+    nv2 t = {v.x, v.y};
+    __builtin_nontemporal_store(t, (nv2 *)p);
+}
+__device__ inline void store_stream(float *p, float v) { __builtin_nontemporal_store(v, p); }
+__device__ inline void store_stream(double *p, double v) { __builtin_nontemporal_store(v, p); }
+__device__ inline void store_stream(int32_t *p, int32_t v) { __builtin_nontemporal_store(v, p); }
+__device__ inline int32_t load_stream(const int32_t *p) { return __builtin_nontemporal_load(p); }
+
 // ---------------------------------------------------------------------------
 // advecting fields (kinds as in slw_field) and feet
 
@@ -172,28 +193,44 @@ __device__ inline int32_t nearer_start(const MeshView &mv, int32_t ja, int32_t j
     return ax * ax + ay * ay < bx * bx + by * by ? ja : jb;
 }
 
+// The start id a DOF carries (given, previous or proposed), read before the
+// foot is computed: the load does not depend on the foot, so its latency
+// overlaps the field evaluation.  The quadrant table row of strategy (a) is
+// read once the foot is known (holding it across the field evaluation would
+// cost registers).
+__device__ inline int32_t start_id(const MeshView &mv, int64_t d, int64_t api, int mode,
+                                   const int32_t *__restrict__ start)
+{
+    if (mode == SLW_START_GIVEN || mode == SLW_START_FIXED)
+        return start[mode == SLW_START_GIVEN ? api : 0];  // user id
+    if (mode == SLW_START_PREV)
+        return load_stream(mv.prev + d);
+    if (mode == SLW_START_LEARNED || mode == SLW_START_CHART || mode == SLW_START_LEARNED_INDEX)
+        return start[d];  // internal id from the chart
+    return -1;
+}
+
+__device__ inline int32_t start_pick(const MeshView &mv, int64_t d, int32_t id, int mode, float dx, float dy)
+{
+    // caller-given ids outside [0, n_tris) fall back to the steered start
+    if (mode == SLW_START_GIVEN || mode == SLW_START_FIXED) {
+        if (id >= 0 && id < mv.n_tris)
+            return mv.tri_int[id];
+    } else if (mode == SLW_START_PREV) {
+        if (id >= 0)
+            return id;
+    } else if (mode == SLW_START_LEARNED || mode == SLW_START_CHART || mode == SLW_START_LEARNED_INDEX) {
+        if (id >= 0 && id < mv.n_tris)
+            return id;
+    }
+    return quadrant_start(mv.qstart[d], dx, dy);
+}
+
 template <bool F32>
 __device__ inline int32_t start_for(const MeshView &mv, int64_t d, int64_t api, int mode,
                                     const int32_t *__restrict__ start, float dx, float dy)
 {
-    // caller-given ids outside [0, n_tris) fall back to the steered start
-    if (mode == SLW_START_GIVEN || mode == SLW_START_FIXED) {
-        const int32_t u = start[mode == SLW_START_GIVEN ? api : 0];
-        if (u >= 0 && u < mv.n_tris)
-            return mv.tri_int[u];
-    }
-    if (mode == SLW_START_PREV) {
-        const int32_t pe = mv.prev[d];
-        if (pe >= 0)
-            return pe;
-    }
-    if (mode == SLW_START_LEARNED || mode == SLW_START_CHART || mode == SLW_START_LEARNED_INDEX) {
-        // internal ids from the chart
-        const int32_t j = start[d];
-        if (j >= 0 && j < mv.n_tris)
-            return j;
-    }
-    return quadrant_start(mv.qstart[d], dx, dy);
+    return start_pick(mv, d, start_id(mv, d, api, mode, start), mode, dx, dy);
 }
 
 // ---------------------------------------------------------------------------
@@ -414,26 +451,25 @@ __device__ inline void exact_weights(const MeshView &mv, const float2 p[3], cons
         th[k] = oo[k] / sum;
 }
 
-// End of a walk that stopped in triangle j (walk record r, zero-sign mask
-// zmask): the tie rule (smallest user id among the closed containers), then
-// the weights on the exact coordinates.
+// End of a walk that stopped in triangle j (float vertex coordinates p,
+// zero-sign mask zmask; nbz = the neighbour across the zero edge when exactly
+// one sign is zero): the tie rule (smallest user id among the closed
+// containers), then the weights on the exact coordinates.  tv_j holds j's
+// vertex ids when have_tv.
 template <bool F32>
-__device__ inline WalkResult<typename CT<F32>::R> finish_walk(const MeshView &mv, int32_t j, const WalkRec &r,
-                                                              int zmask, int32_t steps, int32_t flags,
-                                                              typename CT<F32>::R qx, typename CT<F32>::R qy)
+__device__ inline WalkResult<typename CT<F32>::R> finish_walk(const MeshView &mv, int32_t j, const float2 pj[3],
+                                                              int32_t nbz, int zmask, int32_t steps, int32_t flags,
+                                                              typename CT<F32>::R qx, typename CT<F32>::R qy,
+                                                              bool have_tv = false, int4 tv_j = int4())
 {
     using R = typename CT<F32>::R;
     const int z = (zmask & 1) + ((zmask >> 1) & 1) + ((zmask >> 2) & 1);
-    int4 tv = tri_verts(mv, j);
+    int4 tv = have_tv ? tv_j : tri_verts(mv, j);
     int32_t e = j;
     if (z == 1) {
-        const int k = (zmask & 1) ? 0 : ((zmask & 2) ? 1 : 2);
-        int32_t cd[3];
-        nb_codes(r, cd);
-        const int32_t nbk = nb_of(mv, j, k, sel3(k, cd[0], cd[1], cd[2]));
         flags |= 4;
-        if (nbk >= 0 && (mv.tri_uf[nbk] & kUidMask) < (mv.tri_uf[j] & kUidMask))
-            e = nbk;
+        if (nbz >= 0 && (mv.tri_uf[nbz] & kUidMask) < (mv.tri_uf[j] & kUidMask))
+            e = nbz;
     } else if (z == 2) {
         const int cidx = !(zmask & 1) ? 0 : (!(zmask & 2) ? 1 : 2);
         flags |= 8;
@@ -442,7 +478,7 @@ __device__ inline WalkResult<typename CT<F32>::R> finish_walk(const MeshView &mv
     float2 p[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k)
-        p[k] = r.p[k];
+        p[k] = pj[k];
     if (e != j) {
         tv = tri_verts(mv, e);
         if constexpr (F32) {
@@ -463,15 +499,55 @@ __device__ inline WalkResult<typename CT<F32>::R> finish_walk(const MeshView &mv
     return w;
 }
 
+// the neighbour across the zero edge of a stop with one zero sign (-1 otherwise)
+__device__ inline int32_t zero_edge_nb(const MeshView &mv, int32_t j, const WalkRec &r, int zmask)
+{
+    if (zmask != 1 && zmask != 2 && zmask != 4)
+        return -1;
+    const int k = zmask == 1 ? 0 : (zmask == 2 ? 1 : 2);
+    int32_t cd[3];
+    nb_codes(r, cd);
+    return nb_of(mv, j, k, sel3(k, cd[0], cd[1], cd[2]));
+}
+
+template <bool F32>
+__device__ inline WalkResult<typename CT<F32>::R> finish_walk_rec(const MeshView &mv, int32_t j, const WalkRec &r,
+                                                                  int zmask, int32_t steps, int32_t flags,
+                                                                  typename CT<F32>::R qx, typename CT<F32>::R qy)
+{
+    return finish_walk<F32>(mv, j, r.p, zero_edge_nb(mv, j, r, zmask), zmask, steps, flags, qx, qy);
+}
+
 // Barycentric walk of Section 2.2 from triangle j to the foot q, then the tie
 // rule, then the weights.
 template <bool F32>
 __device__ WalkResult<typename CT<F32>::R> walk(const MeshView &mv, int32_t j, typename CT<F32>::R qx,
-                                                 typename CT<F32>::R qy, uint32_t seed, Counters &c)
+                                                 typename CT<F32>::R qy, uint32_t seed, Counters &c,
+                                                 bool likely_stop = false)
 {
     using R = typename CT<F32>::R;
     const float qfx = F32 ? (float)qx : (float)((double)qx - mv.fc.cx);
     const float qfy = F32 ? (float)qy : (float)((double)qy - mv.fc.cy);
+    // when the start is likely to contain the foot (strategy (b)), the first
+    // test reads its full record (coordinates, neighbours and vertex ids in
+    // one place); if the foot lies elsewhere the walk starts there as usual
+    if (likely_stop) {
+        const float4 p01 = ((const float4 *)(mv.geo + j))[0];
+        const float2 p2 = ((const float2 *)(mv.geo + j))[2];
+        const int4 tv = tri_verts(mv, j);  // {nb[2], v[0], v[1], v[2]}
+        const float2 pj[3] = {make_float2(p01.x, p01.y), make_float2(p01.z, p01.w), p2};
+        float o[3];
+        int s[3];
+        Counters c0;  // counted only if the walk ends here (else the loop repeats the test)
+        edge_signs<F32>(mv, j, pj, qfx, qfy, qx, qy, o, s, c0);
+        if (s[0] >= 0 && s[1] >= 0 && s[2] >= 0) {
+            c.exact += c0.exact;
+            c.fp64 += c0.fp64;
+            const int zm = (int)(s[0] == 0) | ((int)(s[1] == 0) << 1) | ((int)(s[2] == 0) << 2);
+            const int32_t nbz = zm == 4 ? tv.x : ((zm == 1 || zm == 2) ? mv.geo[j].nb[zm >> 1] : -1);
+            return finish_walk<F32>(mv, j, pj, nbz, zm, 0, 0, qx, qy, true, tv);
+        }
+    }
     WalkRec r;
     int zmask = 0;
     int32_t steps = 0, flags = 0;
@@ -490,7 +566,7 @@ __device__ WalkResult<typename CT<F32>::R> walk(const MeshView &mv, int32_t j, t
             return w;
         }
     }
-    return finish_walk<F32>(mv, j, r, zmask, steps, flags, qx, qy);
+    return finish_walk_rec<F32>(mv, j, r, zmask, steps, flags, qx, qy);
 }
 
 __device__ inline unsigned long long wave_sum(unsigned long long v)
@@ -752,7 +828,7 @@ __global__ void __launch_bounds__(kBlock)
             w = walk<F32>(mv, j0, qx, qy, (uint32_t)d * 2654435761u, ls.c);
         }
         if (mode == SLW_START_PREV)
-            mv.prev[d] = w.elem;
+            store_stream(mv.prev + d, w.elem);
         if (st)
             ls.add(w);
         const int32_t uf = w.elem >= 0 ? mv.tri_uf[w.elem] : -1;
@@ -870,7 +946,7 @@ __device__ inline void wave_interp(const int32_t row[NA], const V wgt[NA], int n
                     for (int a = 0; a < NA; ++a)
                         vv_fma(ww[a], *((const VV *)(vin + (int64_t)rr[a] * k) + c), acc);
                 }
-                *((VV *)(vout + o * (int64_t)k) + c) = acc;
+                store_stream((VV *)(vout + o * (int64_t)k) + c, acc);
             } else {
                 V acc = rr[0] == -2 ? ww[0] : outside;
                 if (rr[0] >= 0) {
@@ -879,7 +955,7 @@ __device__ inline void wave_interp(const int32_t row[NA], const V wgt[NA], int n
                     for (int a = 0; a < NA; ++a)
                         acc = fma(ww[a], vin[(int64_t)rr[a] * k + c], acc);
                 }
-                vout[o * (int64_t)k + c] = acc;
+                store_stream(vout + o * (int64_t)k + c, acc);
             }
         }
     }
@@ -1103,7 +1179,10 @@ __device__ inline bool boundary_value(const MeshView &mv, bool f32, double xx, d
 // The fused step (Algorithm 2, one pass of its loop) for the 64 DOFs
 // [base, base + 64) of one wavefront: one lane per foot for foot -> start ->
 // walk -> tie rule -> weights; then the wavefront computes its feet's values
-// cooperatively.  Every lane of the wavefront calls it.
+// cooperatively.  Every lane of the wavefront calls it.  KIND: -1 the start
+// given by `mode`; -2 strategy (b) (its own instantiation: the first test
+// reads the full record of the previous element, which holds registers the
+// other starts do not need); 0 / 2 chart starts computed here.
 template <bool F32, typename V, int NA, int KIND = -1>
 __device__ inline void step_wave(const MeshView &mv, const FieldDev &f, double dt, double t_np1, int scheme, int mode,
                                  const int32_t *__restrict__ start, const V *__restrict__ vin, int k,
@@ -1126,8 +1205,13 @@ __device__ inline void step_wave(const MeshView &mv, const FieldDev &f, double d
     R2 x;
     x.x = x.y = (R)0;
     R qx = (R)0, qy = (R)0;
+    int32_t sid = -1;
     if (d < n_iter) {
         x = ((const R2 *)mv.dof_xy)[d];
+        if constexpr (KIND < 0) {
+            const int64_t api = (mode == SLW_START_GIVEN && !mv.internal_order) ? mv.dof_user[d] : d;
+            sid = start_id(mv, d, api, mode, start);
+        }
         foot_of<R>(f, scheme, x.x, x.y, (R)dt, qx, qy);
     }
     // with boundary data every finite foot is walked (to learn where it leaves)
@@ -1140,14 +1224,12 @@ __device__ inline void step_wave(const MeshView &mv, const FieldDev &f, double d
         WalkResult<R> w = outside_result<R>(0, 0);
         if (run) {
             int32_t j0 = jc;
-            if constexpr (KIND < 0) {
-                const int64_t api = (mode == SLW_START_GIVEN && !mv.internal_order) ? mv.dof_user[d] : d;
-                j0 = start_for<F32>(mv, d, api, mode, start, (float)(qx - x.x), (float)(qy - x.y));
-            }
-            w = walk<F32>(mv, j0, qx, qy, (uint32_t)d * 2654435761u, ls.c);
+            if constexpr (KIND < 0)
+                j0 = start_pick(mv, d, sid, mode, (float)(qx - x.x), (float)(qy - x.y));
+            w = walk<F32>(mv, j0, qx, qy, (uint32_t)d * 2654435761u, ls.c, KIND == -2);
         }
         if (write_prev)
-            mv.prev[d] = w.elem;
+            store_stream(mv.prev + d, w.elem);
         if (st)
             ls.add(w);
         if (w.elem >= 0) {
@@ -1169,8 +1251,15 @@ __device__ inline void step_wave(const MeshView &mv, const FieldDev &f, double d
     wave_interp<V, NA>(row, wgt, nf, vin, k, vout, out_map, base, (V)outside);
 }
 
+// Occupancy floor per instantiation: seven wavefronts per SIMD for strategy
+// (b) (its first test holds a full record; without the floor it takes 74
+// registers and six wavefronts).  The others keep the compiler's choice
+// (the plain step takes 66 registers, seven wavefronts; forcing eight spills
+// one value and measured slower).
+constexpr int step_waves_per_eu(int kind) { return kind == -2 ? 7 : 1; }
+
 template <bool F32, typename V, int NA, int KIND = -1>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(step_waves_per_eu(KIND))))
     k_step(MeshView mv, FieldDev f, double dt, double t_np1, int scheme, int mode, const int32_t *__restrict__ start,
            const V *__restrict__ vin, int k, V *__restrict__ vout, double outside, int write_prev,
            const int32_t *__restrict__ out_map, int64_t n_iter, DevStats *st)
@@ -1561,13 +1650,13 @@ __device__ inline void step_chunk(const MeshView &mv, const FieldDev &f, double 
             int32_t elem = -1;
             if (e0 >= 0) {
                 const R2 q = sq[sl];
-                const WalkResult<R> w = finish_walk<F32>(mv, e0, mv.wrec[e0], (int)sz[sl], 0, 0, q.x, q.y);
+                const WalkResult<R> w = finish_walk_rec<F32>(mv, e0, mv.wrec[e0], (int)sz[sl], 0, 0, q.x, q.y);
                 ls.add_ties(w.flags);
                 elem = w.elem;
                 lagrange<R, V, NA>(mv, w.elem, w.v, w.th, row, wgt);
             }
             if (write_prev)
-                mv.prev[d] = elem;
+                store_stream(mv.prev + d, elem);
         }
         const int nf = (int)min<int64_t>(kWave, n_iter - gbase);
         wave_interp<V, NA>(row, wgt, nf, vin, k, vout, out_map, gbase, (V)outside);
@@ -1861,8 +1950,13 @@ hipError_t launch_step(const DevMesh &m, hipStream_t st, const FieldDev &f0, dou
     case 4: SLW_STEP_RP(F32, V, NA, 4); break;                                                                 \
     case 8: SLW_STEP_RP(F32, V, NA, 8); break;                                                                 \
     default:                                                                                                   \
-        hipLaunchKernelGGL((k_step<F32, V, NA>), dim3(g), dim3(kBlock), 0, st, mv, f, dt, t_n + dt, scheme, mode, \
-                           start, (const V *)v_in, k, (V *)v_out, outside, (int)write_prev, out_map, n_iter, stats); \
+        if (mode == SLW_START_PREV)                                                                            \
+            hipLaunchKernelGGL((k_step<F32, V, NA, -2>), dim3(g), dim3(kBlock), 0, st, mv, f, dt, t_n + dt, scheme, \
+                               mode, start, (const V *)v_in, k, (V *)v_out, outside, (int)write_prev, out_map,   \
+                               n_iter, stats);                                                                 \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_step<F32, V, NA>), dim3(g), dim3(kBlock), 0, st, mv, f, dt, t_n + dt, scheme, mode, \
+                               start, (const V *)v_in, k, (V *)v_out, outside, (int)write_prev, out_map, n_iter, stats); \
     }                                                                                                          \
     } while (0)
     if (m.coords_f32) {
