@@ -551,20 +551,48 @@ __device__ WalkResult<typename CT<F32>::R> walk(const MeshView &mv, int32_t j, t
     WalkRec r;
     int zmask = 0;
     int32_t steps = 0, flags = 0;
-    for (;;) {
-        const int st = walk_move<F32>(mv, j, r, zmask, qfx, qfy, qx, qy, seed, steps, flags, c);
-        if (st == 1)
+    int st = 0;
+    // the deterministic walk (most negative coordinate) up to the step cap,
+    // in a loop of its own: the cap, the hard limit and the randomised choice
+    // stay out of the hot loop
+    const int32_t fast_lim = mv.step_cap < mv.hard_limit ? mv.step_cap : mv.hard_limit;
+    while (steps < fast_lim) {
+        r = mv.wrec[j];
+        float o[3];
+        int s[3];
+        edge_signs<F32>(mv, j, r.p, qfx, qfy, qx, qy, o, s, c);
+        const bool n0 = s[0] < 0, n1 = s[1] < 0, n2 = s[2] < 0;
+        if (!(n0 | n1 | n2)) {
+            zmask = (int)(s[0] == 0) | ((int)(s[1] == 0) << 1) | ((int)(s[2] == 0) << 2);
+            st = 1;
             break;
-        if (st == 2) {
-            WalkResult<R> w = outside_result<R>(steps, flags);
-            if (zmask >= 0) {  // the boundary edge opposite vertex zmask, counter-clockwise
-                const int4 tv = tri_verts(mv, j);
-                w.v[0] = sel3(zmask, tv.z, tv.w, tv.y);
-                w.v[1] = sel3(zmask, tv.w, tv.y, tv.z);
-                w.flags |= 16;
-            }
-            return w;
         }
+        int32_t cd[3];
+        nb_codes(r, cd);
+        const bool x0 = n0 && cd[0] == 0, x1 = n1 && cd[1] == 0, x2 = n2 && cd[2] == 0;
+        if (x0 || x1 || x2) {
+            zmask = x0 ? 0 : (x1 ? 1 : 2);
+            st = 2;
+            break;
+        }
+        const float m0 = n0 ? o[0] : INFINITY, m1 = n1 ? o[1] : INFINITY, m2 = n2 ? o[2] : INFINITY;
+        const int k = (m1 < m0) ? ((m2 < m1) ? 2 : 1) : ((m2 < m0) ? 2 : 0);
+        const int32_t ck = sel3(k, cd[0], cd[1], cd[2]);  // never 0: edge k is interior
+        j = ck == kCodeEscape ? mv.geo[j].nb[k] : j + ck;
+        ++steps;
+    }
+    // past the cap: the same moves with the randomised choice and the hard limit
+    while (st == 0)
+        st = walk_move<F32>(mv, j, r, zmask, qfx, qfy, qx, qy, seed, steps, flags, c);
+    if (st == 2) {
+        WalkResult<R> w = outside_result<R>(steps, flags);
+        if (zmask >= 0) {  // the boundary edge opposite vertex zmask, counter-clockwise
+            const int4 tv = tri_verts(mv, j);
+            w.v[0] = sel3(zmask, tv.z, tv.w, tv.y);
+            w.v[1] = sel3(zmask, tv.w, tv.y, tv.z);
+            w.flags |= 16;
+        }
+        return w;
     }
     return finish_walk_rec<F32>(mv, j, r, zmask, steps, flags, qx, qy);
 }
