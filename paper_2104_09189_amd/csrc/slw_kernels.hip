@@ -931,6 +931,61 @@ __device__ inline void lagrange(const MeshView &mv, int32_t e, const int32_t v[3
     }
 }
 
+// wave_interp for rows of K = VW * CH fields (CH 16-byte chunks per row, a
+// compile-time count): the same items as below, lane L of pass p handles
+// point p * (64 / CH) + L / CH, chunk L % CH.  The passes are unrolled with
+// constant index arithmetic, and the gathers of B passes at a time are
+// issued before any of them is used (outside points and the lanes past the
+// last point read row 0 and discard it), so their latencies overlap.
+template <typename V, int NA, int CH>
+__device__ inline void wave_interp_ch(const int32_t row[NA], const V wgt[NA], int nf, const V *__restrict__ vin,
+                                      V *__restrict__ vout, const int32_t *__restrict__ out_map, int64_t base,
+                                      V outside)
+{
+    constexpr int VW = sizeof(V) == 4 ? 4 : 2;
+    constexpr int K = VW * CH;
+    constexpr int PER = kWave / CH;  // points per pass
+    constexpr int B = (NA == 3 && CH >= 2) ? 2 : 1;  // passes whose gathers are in flight together (four would cost registers)
+    using VV = typename std::conditional<sizeof(V) == 4, float4, double2>::type;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int c = lane % CH;
+#pragma unroll
+    for (int p0 = 0; p0 < CH; p0 += B) {
+        int32_t rr[B][NA];
+        V ww[B][NA];
+        VV g[B][NA];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int f = (p0 + b) * PER + lane / CH;
+#pragma unroll
+            for (int a = 0; a < NA; ++a) {
+                rr[b][a] = __shfl(row[a], f, kWave);
+                ww[b][a] = __shfl(wgt[a], f, kWave);
+            }
+            const bool live = f < nf && rr[b][0] >= 0;
+#pragma unroll
+            for (int a = 0; a < NA; ++a)
+                g[b][a] = *((const VV *)(vin + (int64_t)(live ? rr[b][a] : 0) * K) + c);
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int f = (p0 + b) * PER + lane / CH;
+            VV acc = vv_zero<VV>();
+            if (rr[b][0] < 0) {
+                acc = vv_fill(rr[b][0] == -2 ? ww[b][0] : outside);  // -2: boundary value in the first weight
+            } else {
+#pragma unroll
+                for (int a = 0; a < NA; ++a)
+                    vv_fma(ww[b][a], g[b][a], acc);
+            }
+            if (f < nf) {
+                const int64_t o = out_map ? (int64_t)out_map[base + f] : base + f;
+                store_stream((VV *)(vout + o * K) + c, acc);
+            }
+        }
+    }
+}
+
 // Values of the 64 points of a wavefront, computed cooperatively: lane L of
 // pass p handles item p * 64 + L = (point f, chunk c of VW fields), reading
 // point f's rows and weights from lane f with cross-lane shuffles.  The
@@ -946,6 +1001,15 @@ __device__ inline void wave_interp(const int32_t row[NA], const V wgt[NA], int n
     using VV = typename std::conditional<sizeof(V) == 4, float4, double2>::type;
     const bool vec = (k % VW == 0) &&
                      (((reinterpret_cast<uintptr_t>(vin) | reinterpret_cast<uintptr_t>(vout)) & 15) == 0);
+    // the common field counts with a constant chunk count (uniform branches)
+    if (vec && k == VW) {
+        wave_interp_ch<V, NA, 1>(row, wgt, nf, vin, vout, out_map, base, outside);
+        return;
+    }
+    if (vec && k == 4 * VW) {
+        wave_interp_ch<V, NA, 4>(row, wgt, nf, vin, vout, out_map, base, outside);
+        return;
+    }
     const int chunks = vec ? k / VW : k;
     const int total = nf * chunks;
     // chunks is uniform; a power of two (the common k = 1, 4, 16 ...) divides by shifting
