@@ -294,8 +294,14 @@ __device__ inline void edge_signs(const MeshView &mv, int32_t j, const float2 p[
         for (int k = 0; k < 3; ++k) {
             if (s[k] == 0) {
                 const int a = (k + 1) % 3, b = (k + 2) % 3;
-                const int32_t *v = mv.geo[j].v;
-                const int sg = slow_sign<F32>(mv.dof_xy, p[a], p[b], v[a], v[b], qx, qy);
+                // double meshes read the exact coordinates through the vertex
+                // ids; float meshes' record coordinates are exact
+                int32_t va = -1, vb = -1;
+                if constexpr (!F32) {
+                    va = mv.geo[j].v[a];
+                    vb = mv.geo[j].v[b];
+                }
+                const int sg = slow_sign<F32>(mv.dof_xy, p[a], p[b], va, vb, qx, qy);
                 ++c.fp64;
                 c.exact += (sg == 2 || sg == -2 || sg == 0);
                 s[k] = sg > 0 ? 1 : (sg < 0 ? -1 : 0);
@@ -518,6 +524,62 @@ __device__ inline WalkResult<typename CT<F32>::R> finish_walk_rec(const MeshView
     return finish_walk<F32>(mv, j, r.p, zero_edge_nb(mv, j, r, zmask), zmask, steps, flags, qx, qy);
 }
 
+// One move of the deterministic walk from triangle j (walk record r already
+// read) towards q: 0 = moved (j is the next triangle, steps counted), 1 =
+// stopped (zmask: zero signs), 2 = outside (zmask: the boundary edge).  No
+// step limit here (the callers bound the moves).
+template <bool F32>
+__device__ inline int det_move(const MeshView &mv, int32_t &j, const WalkRec &r, int &zmask, float qfx, float qfy,
+                               typename CT<F32>::R qx, typename CT<F32>::R qy, int32_t &steps, Counters &c)
+{
+    float o[3];
+    int s[3];
+    edge_signs<F32>(mv, j, r.p, qfx, qfy, qx, qy, o, s, c);
+    const bool n0 = s[0] < 0, n1 = s[1] < 0, n2 = s[2] < 0;
+    if (!(n0 | n1 | n2)) {
+        zmask = (int)(s[0] == 0) | ((int)(s[1] == 0) << 1) | ((int)(s[2] == 0) << 2);
+        return 1;
+    }
+    int32_t cd[3];
+    nb_codes(r, cd);
+    const bool x0 = n0 && cd[0] == 0, x1 = n1 && cd[1] == 0, x2 = n2 && cd[2] == 0;
+    if (x0 || x1 || x2) {
+        zmask = x0 ? 0 : (x1 ? 1 : 2);
+        return 2;
+    }
+    const float m0 = n0 ? o[0] : INFINITY, m1 = n1 ? o[1] : INFINITY, m2 = n2 ? o[2] : INFINITY;
+    const int k = (m1 < m0) ? ((m2 < m1) ? 2 : 1) : ((m2 < m0) ? 2 : 0);
+    const int32_t ck = sel3(k, cd[0], cd[1], cd[2]);  // never 0: edge k is interior
+    j = ck == kCodeEscape ? mv.geo[j].nb[k] : j + ck;
+    ++steps;
+    return 0;
+}
+
+// End of a walk whose deterministic moves stopped with status st (0: the step
+// cap was reached; the walk goes on with the randomised choice and the hard
+// limit), then the outside result or the tie rule and the weights.
+template <bool F32>
+__device__ inline WalkResult<typename CT<F32>::R> walk_end(const MeshView &mv, int32_t j, WalkRec r, int zmask,
+                                                           float qfx, float qfy, typename CT<F32>::R qx,
+                                                           typename CT<F32>::R qy, uint32_t seed, int32_t steps,
+                                                           int32_t flags, int st, Counters &c)
+{
+    using R = typename CT<F32>::R;
+    while (st == 0)
+        st = walk_move<F32>(mv, j, r, zmask, qfx, qfy, qx, qy, seed, steps, flags, c);
+    if (st == 2) {
+        WalkResult<R> w = outside_result<R>(steps, flags);
+        if (zmask >= 0) {  // the boundary edge opposite vertex zmask, counter-clockwise
+            const int4 tv = tri_verts(mv, j);
+            w.v[0] = sel3(zmask, tv.z, tv.w, tv.y);
+            w.v[1] = sel3(zmask, tv.w, tv.y, tv.z);
+            w.flags |= 16;
+        }
+        return w;
+    }
+    return finish_walk_rec<F32>(mv, j, r, zmask, steps, flags, qx, qy);
+}
+
 // Barycentric walk of Section 2.2 from triangle j to the foot q, then the tie
 // rule, then the weights.
 template <bool F32>
@@ -525,7 +587,6 @@ __device__ WalkResult<typename CT<F32>::R> walk(const MeshView &mv, int32_t j, t
                                                  typename CT<F32>::R qy, uint32_t seed, Counters &c,
                                                  bool likely_stop = false)
 {
-    using R = typename CT<F32>::R;
     const float qfx = F32 ? (float)qx : (float)((double)qx - mv.fc.cx);
     const float qfy = F32 ? (float)qy : (float)((double)qy - mv.fc.cy);
     // when the start is likely to contain the foot (strategy (b)), the first
@@ -548,7 +609,7 @@ __device__ WalkResult<typename CT<F32>::R> walk(const MeshView &mv, int32_t j, t
             return finish_walk<F32>(mv, j, pj, nbz, zm, 0, 0, qx, qy, true, tv);
         }
     }
-    WalkRec r;
+    WalkRec r{};
     int zmask = 0;
     int32_t steps = 0, flags = 0;
     int st = 0;
@@ -558,43 +619,11 @@ __device__ WalkResult<typename CT<F32>::R> walk(const MeshView &mv, int32_t j, t
     const int32_t fast_lim = mv.step_cap < mv.hard_limit ? mv.step_cap : mv.hard_limit;
     while (steps < fast_lim) {
         r = mv.wrec[j];
-        float o[3];
-        int s[3];
-        edge_signs<F32>(mv, j, r.p, qfx, qfy, qx, qy, o, s, c);
-        const bool n0 = s[0] < 0, n1 = s[1] < 0, n2 = s[2] < 0;
-        if (!(n0 | n1 | n2)) {
-            zmask = (int)(s[0] == 0) | ((int)(s[1] == 0) << 1) | ((int)(s[2] == 0) << 2);
-            st = 1;
+        st = det_move<F32>(mv, j, r, zmask, qfx, qfy, qx, qy, steps, c);
+        if (st != 0)
             break;
-        }
-        int32_t cd[3];
-        nb_codes(r, cd);
-        const bool x0 = n0 && cd[0] == 0, x1 = n1 && cd[1] == 0, x2 = n2 && cd[2] == 0;
-        if (x0 || x1 || x2) {
-            zmask = x0 ? 0 : (x1 ? 1 : 2);
-            st = 2;
-            break;
-        }
-        const float m0 = n0 ? o[0] : INFINITY, m1 = n1 ? o[1] : INFINITY, m2 = n2 ? o[2] : INFINITY;
-        const int k = (m1 < m0) ? ((m2 < m1) ? 2 : 1) : ((m2 < m0) ? 2 : 0);
-        const int32_t ck = sel3(k, cd[0], cd[1], cd[2]);  // never 0: edge k is interior
-        j = ck == kCodeEscape ? mv.geo[j].nb[k] : j + ck;
-        ++steps;
     }
-    // past the cap: the same moves with the randomised choice and the hard limit
-    while (st == 0)
-        st = walk_move<F32>(mv, j, r, zmask, qfx, qfy, qx, qy, seed, steps, flags, c);
-    if (st == 2) {
-        WalkResult<R> w = outside_result<R>(steps, flags);
-        if (zmask >= 0) {  // the boundary edge opposite vertex zmask, counter-clockwise
-            const int4 tv = tri_verts(mv, j);
-            w.v[0] = sel3(zmask, tv.z, tv.w, tv.y);
-            w.v[1] = sel3(zmask, tv.w, tv.y, tv.z);
-            w.flags |= 16;
-        }
-        return w;
-    }
-    return finish_walk_rec<F32>(mv, j, r, zmask, steps, flags, qx, qy);
+    return walk_end<F32>(mv, j, r, zmask, qfx, qfy, qx, qy, seed, steps, flags, st, c);
 }
 
 __device__ inline unsigned long long wave_sum(unsigned long long v)
