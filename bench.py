@@ -429,7 +429,7 @@ def main():
         "walk": {k: st[k] for k in ("max_steps", "outside", "exact_tests", "fp64_tests", "fallback_walks",
                                     "edge_ties", "vertex_ties")},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_step<false, float, 3>",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_step<false, float, 3, -1>",
                      "kernel_ms": ra["kernel_ms"], "algorithmic_bytes_per_launch": abytes},
         "upload_s": upload_s,
         "wall_s": ra["wall_s"],
