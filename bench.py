@@ -172,7 +172,8 @@ def measure_batch(steps=100):
     from paper_2104_09189_amd import slwalk as S
     wl = I.batch_meshes()
     ctx = S.Context(0)
-    meshes = [S.Mesh(ctx, w.xy, w.tri, S.INTERNAL_ORDER | S.COORDS_F32) for w in wl]
+    # Hilbert order: measured faster than the Morton order for these short walks
+    meshes = [S.Mesh(ctx, w.xy, w.tri, S.INTERNAL_ORDER | S.COORDS_F32 | S.HILBERT) for w in wl]
     va = [torch.from_numpy(np.ascontiguousarray(w.v0[m.dof_order()])).cuda() for w, m in zip(wl, meshes)]
     vb = [torch.empty_like(a) for a in va]
     b = S.Batch(ctx, meshes)
@@ -210,7 +211,7 @@ def measure_batch(steps=100):
     abytes = n_nodes * (8 + 4 + 4 + 2 * 4) + 12 * n_tris
     g.free()
     b.free()
-    return {"workload": f"{len(meshes)} jittered meshes, swirl, Courant 5, float coordinates, 1 field",
+    return {"workload": f"{len(meshes)} jittered meshes, swirl, Courant 5, float coordinates, 1 field, Hilbert order",
             "n_nodes": n_nodes, "n_tris": n_tris, "steps_in_graph": steps, "schedule": schedule, "block": block,
             "ms_per_step": graph_ms, "feet_per_s": n_nodes / (graph_ms * 1e-3),
             "roofline_frac": abytes / (graph_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,

@@ -114,6 +114,9 @@ enum {
 #define SLW_P2 0x2u             /* build P2 edge DOFs */
 #define SLW_NO_REORDER 0x4u     /* keep the user's node/triangle order internally */
 #define SLW_INTERNAL_ORDER 0x8u /* DOF-indexed arrays at this interface use the internal order */
+#define SLW_HILBERT 0x10u       /* order along the Hilbert curve instead of the Morton curve (measured:
+                                   faster for short walks and one launch per mesh, slower for the long
+                                   walks of a graded mesh) */
 /* slw_locate_feet flags */
 #define SLW_FEET_IN 0x1u        /* feet are an input (not computed from the field) */
 
@@ -166,7 +169,8 @@ void slw_ctx_destroy(slw_ctx *ctx);
  * builds the neighbour lists of Section 3 (neighbour k across the edge
  * opposite vertex k, -1 on the boundary), the incident-triangle lists of
  * every DOF with their edge directions (start selection), the P2 edge DOFs,
- * and a Morton order of nodes and triangles (unless SLW_NO_REORDER), and
+ * and a Morton (or, with SLW_HILBERT, Hilbert) order of nodes and triangles
+ * (unless SLW_NO_REORDER), and
  * copies the result to the device.  Synchronous. */
 slw_status slw_mesh_upload(slw_ctx *ctx, const double *xy_h, int64_t n_nodes, const int32_t *tri_h,
                            int64_t n_tris, uint32_t flags, slw_mesh **out);

@@ -177,7 +177,7 @@ slw_status slw_mesh_upload(slw_ctx *ctx, const double *xy_h, int64_t n_nodes, co
     if (!ctx || !out)
         return set_error(SLW_E_ARG, "ctx or out is NULL");
     *out = nullptr;
-    if (flags & ~(uint32_t)(SLW_COORDS_F32 | SLW_P2 | SLW_NO_REORDER | SLW_INTERNAL_ORDER))
+    if (flags & ~(uint32_t)(SLW_COORDS_F32 | SLW_P2 | SLW_NO_REORDER | SLW_INTERNAL_ORDER | SLW_HILBERT))
         return set_error(SLW_E_ARG, "unknown mesh flag");
     DeviceGuard g(ctx->device);
     slw_mesh *m = new (std::nothrow) slw_mesh();
@@ -196,7 +196,7 @@ slw_status slw_mesh_upload(slw_ctx *ctx, const double *xy_h, int64_t n_nodes, co
 slw_status slw_mesh_check(const double *xy_h, int64_t n_nodes, const int32_t *tri_h, int64_t n_tris,
                           uint32_t flags, slw_mesh_info *info_h)
 {
-    if (flags & ~(uint32_t)(SLW_COORDS_F32 | SLW_P2 | SLW_NO_REORDER | SLW_INTERNAL_ORDER))
+    if (flags & ~(uint32_t)(SLW_COORDS_F32 | SLW_P2 | SLW_NO_REORDER | SLW_INTERNAL_ORDER | SLW_HILBERT))
         return set_error(SLW_E_ARG, "unknown mesh flag");
     DevMesh m;
     slw_status st = build_mesh(nullptr, xy_h, n_nodes, tri_h, n_tris, flags, m, false);

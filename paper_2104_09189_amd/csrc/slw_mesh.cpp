@@ -57,13 +57,40 @@ uint64_t spread21(uint64_t v)
     return v;
 }
 
+// Position of cell (x, y) of the 2^21 x 2^21 grid along the Hilbert curve
+// (the usual quadrant recursion: at each level, from the coarsest, add the
+// quadrant's rank along the curve times the quadrant's cell count, then
+// rotate / reflect the coordinates into that quadrant's frame).
+uint64_t hilbert21(uint64_t x, uint64_t y)
+{
+    constexpr uint64_t n = (uint64_t)1 << 21;
+    uint64_t d = 0;
+    for (uint64_t s = n >> 1; s > 0; s >>= 1) {
+        const uint64_t rx = (x & s) ? 1 : 0, ry = (y & s) ? 1 : 0;
+        d += s * s * ((3 * rx) ^ ry);
+        if (ry == 0) {
+            if (rx == 1) {
+                x = n - 1 - x;
+                y = n - 1 - y;
+            }
+            std::swap(x, y);
+        }
+    }
+    return d;
+}
+
+// Space-filling-curve key of a point: its cell in a 2^21 x 2^21 grid over
+// the bounding box, ranked along the Hilbert curve (or the Morton curve)
 struct MortonFrame {
     double x0, y0, scale;
+    bool hilbert;
     uint64_t key(double x, double y) const
     {
         double fx = (x - x0) * scale, fy = (y - y0) * scale;
         uint64_t qx = (uint64_t)std::min(std::max(fx, 0.0), 2097151.0);
         uint64_t qy = (uint64_t)std::min(std::max(fy, 0.0), 2097151.0);
+        if (hilbert)
+            return hilbert21(qx, qy);
         return spread21(qx) | (spread21(qy) << 1);
     }
 };
@@ -321,7 +348,7 @@ slw_status build_mesh(slw_ctx *ctx, const double *xy, int64_t n, const int32_t *
 
     // ---------------- orders ----------------
     double span = std::max(bb[2] - bb[0], bb[3] - bb[1]);
-    MortonFrame mf{bb[0], bb[1], span > 0 ? 2097151.0 / span : 1.0};
+    MortonFrame mf{bb[0], bb[1], span > 0 ? 2097151.0 / span : 1.0, (flags & SLW_HILBERT) != 0};
     std::vector<int32_t> node_u(n), tri_u(nt);  // internal -> user
     std::iota(node_u.begin(), node_u.end(), 0);
     std::iota(tri_u.begin(), tri_u.end(), 0);

@@ -35,7 +35,7 @@ SLW_EULER, SLW_RK2 = 0, 1
 START_STEERED, START_GIVEN, START_PREV, START_FIXED, START_LEARNED, START_CHART, START_NEIGHBOR = 0, 1, 2, 3, 4, 5, 6
 START_LEARNED_INDEX = 7
 BC_NONE, BC_CONSTANT, BC_AFFINE = 0, 1, 2
-COORDS_F32, P2, NO_REORDER, INTERNAL_ORDER = 0x1, 0x2, 0x4, 0x8
+COORDS_F32, P2, NO_REORDER, INTERNAL_ORDER, HILBERT = 0x1, 0x2, 0x4, 0x8, 0x10
 FEET_IN = 0x1
 
 STATUS = {0: "SLW_OK", 1: "SLW_E_ARG", 2: "SLW_E_MESH_INDEX", 3: "SLW_E_MESH_DEGENERATE",

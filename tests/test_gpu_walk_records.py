@@ -101,3 +101,31 @@ def test_neighbour_code_width_is_checked(S, C):
     for b in (1, 22, -3):
         with pytest.raises(S.SlwError):
             mesh.set_neighbour_codes(b)
+
+
+def test_hilbert_order_same_results_and_curve_adjacency(S, C, orc):
+    # the Hilbert order is an internal numbering: results in user order are
+    # bit-identical to the Morton order's
+    xy, tri = I.permute_mesh(*I.jittered_grid(45, 907), 908)
+    fld, dt = I.swirl(1.0), 5.0 / 44
+    v0 = np.stack([I.gaussian_hill(xy), xy[:, 1]], axis=1).astype(np.float32)
+    out = {}
+    for fl in (0, S.HILBERT):
+        mesh = S.Mesh(C, xy, tri, fl)
+        v, st = mesh.step(fld, 0.1, dt, S.SLW_RK2, dev(v0), stats=True)
+        e = mesh.locate_feet(fld, 0.1 + dt, dt, S.SLW_RK2)["elem"]
+        out[fl] = (host(v).copy(), host(e).copy(), st["walk_steps"])
+    assert np.array_equal(out[0][0], out[S.HILBERT][0])
+    assert np.array_equal(out[0][1], out[S.HILBERT][1])
+    ref, _, e_ref, _ = orc.sl_step(xy, tri, v0.astype(np.float64), fld, 0.1, dt, I.SCHEME_RK2)
+    assert np.array_equal(out[S.HILBERT][1], e_ref)
+    # on an unjittered 2^k x 2^k grid consecutive nodes of the Hilbert order
+    # are grid neighbours (unit steps), unlike the Morton order's jumps
+    n = 16
+    g = np.array([(i, j) for j in range(n) for i in range(n)], dtype=np.float64)
+    xy2 = g / (n - 1)
+    tri2 = I.grid_triangles(n)
+    for fl, unit in ((S.HILBERT, True), (0, False)):
+        order = S.Mesh(C, xy2, tri2, fl).dof_order()
+        step = np.abs(np.diff(g[order], axis=0)).sum(axis=1)
+        assert (step == 1).all() == unit, fl
