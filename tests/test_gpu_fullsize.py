@@ -99,3 +99,29 @@ def test_swirl_500_fp32_mesh_indices_on_rounded_inputs(S, C, orc):
     ref, _, _, _ = orc.sl_step(w.xy, w.tri, v0.astype(np.float64), w.field, 0.4 - w.dt, w.dt, w.scheme)
     err = rel_err(v, ref, np.abs(v0).max())
     assert err < 1e-4, err
+
+
+def test_graded_1415_escaped_neighbour_codes(S, C, orc, graded):
+    # On 3,998,792 triangles some neighbour offsets in the Morton order do not
+    # fit the walk records' 21-bit codes (escapes, read from the full
+    # records); 2-bit codes escape nearly every move.  All 2,002,225 feet of
+    # a Courant-5 step (the oracle's feet): identical elements and walk
+    # statistics at both widths, and the oracle's elements on a sample.
+    w = graded
+    mesh = S.Mesh(C, w.xy, w.tri, S.INTERNAL_ORDER)
+    perm = mesh.dof_order()
+    feet = orc.feet(w.xy, w.field, 2 * w.dt, w.dt, w.scheme)
+    res = {}
+    for bits in (21, 2):
+        mesh.set_neighbour_codes(bits)
+        out = mesh.locate_feet(feet=dev(feet[perm]), feet_in=True, stats=True)
+        st = out["stats"]
+        res[bits] = (host(out["elem"]).copy(),
+                     (st["walk_steps"], st["max_steps"], st["outside"], st["vertex_ties"], st["edge_ties"]))
+    mesh.set_neighbour_codes(0)
+    assert np.array_equal(res[21][0], res[2][0])
+    assert res[21][1] == res[2][1]
+    rng = np.random.default_rng(3031)
+    sample = rng.choice(w.xy.shape[0], 5000, replace=False)  # internal positions
+    e_ref, _ = orc.locate(w.xy, w.tri, feet[perm[sample]])
+    assert (res[21][0][sample] == e_ref).all()
