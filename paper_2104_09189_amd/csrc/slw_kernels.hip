@@ -1374,10 +1374,13 @@ __device__ inline void step_wave(const MeshView &mv, const FieldDev &f, double d
 
 // Occupancy floor per instantiation: seven wavefronts per SIMD for strategy
 // (b) (its first test holds a full record; without the floor it takes 74
-// registers and six wavefronts).  The others keep the compiler's choice
-// (the plain step takes 66 registers, seven wavefronts; forcing eight spills
-// one value and measured slower).
-constexpr int step_waves_per_eu(int kind) { return kind == -2 ? 7 : 1; }
+// registers and six wavefronts); four for the learned index (the network's
+// accumulators would take 140 registers and three wavefronts; at four the
+// compiler spills 32 bytes, measured 5% faster; five spills more and is
+// slower).  The others keep the compiler's choice (the plain step takes 66
+// registers, seven wavefronts; forcing eight spills one value and measured
+// slower).
+constexpr int step_waves_per_eu(int kind) { return kind == -2 ? 7 : (kind == 2 ? 4 : 1); }
 
 template <bool F32, typename V, int NA, int KIND = -1>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(step_waves_per_eu(KIND))))
