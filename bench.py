@@ -135,6 +135,69 @@ def measure(mesh, w, v0, steps, warmup, start_mode):
     return {"ms_per_step": gpu_ms / steps, "kernel_ms": kernel_ms, "wall_s": wall, "stats": st}
 
 
+def measure_precision(alpha=5.0, steps=20, warmup=3):
+    """FP32 coordinates, feet, weights and values (FP64 and exact fallback
+    for the orientation signs) against the FP64 path on the 500 x 500
+    jittered mesh in Morton input order, swirl, Euler, Courant alpha, P1, one
+    field: time per step of each; the FP32 values' error per step from the
+    same V^n (mid-run, relative to max |V^n|) and after the whole run to
+    t = T (the FP64 path itself matches the oracle to 1e-12 per step in the
+    tests); the share of feet located in the same element (the two paths
+    round the coordinates differently, so feet near edges may legitimately
+    land in a neighbour)."""
+    import torch
+    from paper_2104_09189_amd import inputs as I
+    from paper_2104_09189_amd import slwalk as S
+    w = I.swirl_500(alpha=alpha, order="morton")
+    ctx = S.Context(0)
+    res = {"workload": w.name, "n_nodes": int(w.xy.shape[0]), "n_tris": int(w.tri.shape[0]), "steps_to_T": w.steps}
+    meshes, vals = {}, {}
+    for name, flags, dtype in (("f64", 0, torch.float64), ("f32", S.COORDS_F32, torch.float32)):
+        mesh = S.Mesh(ctx, w.xy, w.tri, S.INTERNAL_ORDER | flags)
+        perm = mesh.dof_order()
+        v0 = torch.from_numpy(np.ascontiguousarray(w.v0[perm])).to("cuda:0", dtype)
+        r = measure(mesh, w, v0, steps, warmup, S.START_STEERED)
+        res[name] = {"ms_per_step": r["ms_per_step"], "kernel_ms": r["kernel_ms"],
+                     "feet_per_s": mesh.n_nodes / (r["ms_per_step"] * 1e-3)}
+        meshes[name], vals[name] = (mesh, perm), v0
+    # one step from the same V^n at mid-run (V^n from the FP64 run)
+    m64, p64 = meshes["f64"]
+    m32, p32 = meshes["f32"]
+    mid = w.steps // 2
+    va = vals["f64"].clone()
+    vb = torch.empty_like(va)
+    va, vb, _ = run_steps(m64, w, va, vb, 0, mid, S.START_STEERED)
+    vn_user = np.empty_like(va.cpu().numpy())
+    vn_user[p64] = va.cpu().numpy()
+    t = mid * w.dt
+    a64 = m64.step(w.field, t, w.dt, w.scheme, va)
+    vn32 = torch.from_numpy(np.ascontiguousarray(vn_user[p32])).to("cuda:0", torch.float32)
+    a32 = m32.step(w.field, t, w.dt, w.scheme, vn32)
+    e64 = m64.locate_feet(w.field, t + w.dt, w.dt, w.scheme)["elem"]
+    e32 = m32.locate_feet(w.field, t + w.dt, w.dt, w.scheme)["elem"]
+    torch.cuda.synchronize()
+    u64 = np.empty(a64.shape[0]); u64[p64] = a64.cpu().numpy()[:, 0]
+    u32 = np.empty(a32.shape[0]); u32[p32] = a32.cpu().numpy()[:, 0].astype(np.float64)
+    scale = float(np.abs(vn_user).max())
+    g64 = np.empty(e64.shape[0], dtype=np.int64); g64[p64] = e64.cpu().numpy()
+    g32 = np.empty(e32.shape[0], dtype=np.int64); g32[p32] = e32.cpu().numpy()
+    res["step_error_f32_vs_f64"] = float(np.abs(u32 - u64).max() / scale)
+    res["same_element_share"] = float((g64 == g32).mean())
+    # the whole run to t = T in each precision
+    ends = {}
+    for name in ("f64", "f32"):
+        mesh, perm = meshes[name]
+        va = vals[name].clone()
+        vb = torch.empty_like(va)
+        va, vb, _ = run_steps(mesh, w, va, vb, 0, w.steps, S.START_STEERED)
+        torch.cuda.synchronize()
+        u = np.empty(va.shape[0]); u[perm] = va.cpu().numpy()[:, 0].astype(np.float64)
+        ends[name] = u
+    res["run_error_f32_vs_f64"] = float(np.abs(ends["f32"] - ends["f64"]).max() / np.abs(w.v0).max())
+    res["speedup_f32"] = res["f64"]["ms_per_step"] / res["f32"]["ms_per_step"]
+    return res
+
+
 def measure_k_reuse(mesh, w, v0, reps=20):
     """One location reused by K fields (one K = 16 step) against K separate
     single-field steps (K locations) on the same mesh and feet."""
@@ -453,6 +516,7 @@ def main():
             "roofline_frac": abytes / (rc["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
         out["k_field_reuse"] = measure_k_reuse(mesh, w, v0)
         out["locators"] = measure_locators(mesh, w)
+        out["precision"] = measure_precision()
     if not args.no_batch and not args.only_a:
         out["batch"] = measure_batch()
     if not args.no_learned and not args.only_a:
