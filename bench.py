@@ -67,6 +67,26 @@ def measured_traffic():
     return float(b.group(1))
 
 
+def cpu_model() -> str:
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def hist_dict(step_hist) -> dict:
+    """slw_stats.step_hist as {"[a,b)": count} (bin 0: no element change)."""
+    out = {"[0,1)": int(step_hist[0])}
+    for b in range(1, 16):
+        lo, hi = 1 << (b - 1), (1 << b) if b < 15 else None
+        out[f"[{lo},{hi if hi else 'inf'})"] = int(step_hist[b])
+    return out
+
+
 def cpu_baseline(w, budget_s: float = 10.0):
     """The oracle (feet, brute-force bucket location with exact predicates,
     interpolation) on whole steps of the same workload until budget_s."""
@@ -85,6 +105,7 @@ def cpu_baseline(w, budget_s: float = 10.0):
     feet = steps * w.xy.shape[0]
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": feet / el, "unit": "feet/s", "cores": min(threads, os.cpu_count() or 1), "kind": "oracle",
+            "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count(),
             "sample": f"{steps} whole oracle steps of the same workload ({feet} feet, {el:.1f} s)"}
 
 
@@ -372,6 +393,50 @@ def measure_learned(alpha=50.0, n=1415, k=16, steps=10, samples_per_step=200_000
             "speedup_chart_vs_plain": base / res["chart_exact"]["ms_per_step"]}
 
 
+def wave_walks(mesh, w, t_n, mode) -> dict:
+    """Walk lengths of one step's feet (element changes per foot) as the step
+    kernel's wavefronts see them: 64 consecutive internal-order DOFs per
+    wavefront, each waiting for its longest walk."""
+    from paper_2104_09189_amd import slwalk as S
+    if mode == S.START_PREV:
+        # the previous element of every DOF from the step before
+        mesh.locate_feet(w.field, t_n, w.dt, w.scheme, start_mode=mode, want_bary=False, want_elem=False)
+    loc = mesh.locate_feet(w.field, t_n + w.dt, w.dt, w.scheme, start_mode=mode, want_steps=True,
+                           want_bary=False, want_elem=False)
+    st = loc["steps"].cpu().numpy().astype(np.int64)
+    return _walk_histogram(st)
+
+
+def measure_courant_range(mesh, w, v0, steps=20, warmup=3, alphas=(1.0, 5.0, 20.0, 50.0), chart_g=2048):
+    """The graded mesh across its Courant range: strategy (a) (steered
+    incident start), strategy (b) (previous element) and the exact chart
+    start, each with ms per step, kernel time, HBM-roofline fraction and the
+    walk lengths (mean, and the mean over wavefronts of each wavefront's
+    longest walk, which sets its time)."""
+    import dataclasses
+    from paper_2104_09189_amd import inputs as I
+    from paper_2104_09189_amd import slwalk as S
+    if mesh.chart_g != chart_g:
+        mesh.chart_build(chart_g)
+    abytes = algorithmic_bytes(mesh.n_nodes, mesh.n_tris, 16, 4, v0.shape[1])
+    out = {}
+    for alpha in alphas:
+        dt, _ = I.courant_dt(alpha, w.h)
+        wa = dataclasses.replace(w, dt=dt)
+        line = {"dt": dt}
+        for name, mode in (("a_steered", S.START_STEERED), ("b_previous", S.START_PREV),
+                           ("chart_exact", S.START_CHART)):
+            r = measure(mesh, wa, v0, steps, warmup, mode)
+            ww = wave_walks(mesh, wa, 7 * dt, mode)
+            line[name] = {"ms_per_step": r["ms_per_step"], "kernel_ms": r["kernel_ms"],
+                          "feet_per_s": mesh.n_nodes / (r["ms_per_step"] * 1e-3),
+                          "roofline_frac": abytes / (r["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                          "mean_walk_steps": ww["mean"], "mean_wavefront_max": ww["mean_wavefront_max"],
+                          "p99": ww["p99"], "max": ww["max"]}
+        out[f"alpha_{alpha:g}"] = line
+    return out
+
+
 def measure_locators(mesh, w, reps=10):
     """Point location alone on the feet of one step of the headline workload:
     the steered walk (strategy (a)), the walk from a bucket-grid start
@@ -483,15 +548,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64/f32",
         "data": "synthetic",
         "config": {"workload": w.name, "n_nodes": int(n_feet), "n_tris": int(mesh.n_tris), "alpha": args.alpha,
                    "k_fields": args.k, "coords": "f64", "values": "f32", "order": 1, "scheme": "rk2",
                    "start": "strategy (a): incident triangle facing the foot", "parallelism": "none (1 GPU)"},
         "field_values_per_s": value * args.k,
         "mean_walk_steps": st["walk_steps"] / max(st["feet"], 1),
-        "walk": {k: st[k] for k in ("max_steps", "outside", "exact_tests", "fp64_tests", "fallback_walks",
-                                    "edge_ties", "vertex_ties")},
+        "walk": {**{k: st[k] for k in ("max_steps", "outside", "exact_tests", "fp64_tests", "fallback_walks",
+                                       "edge_ties", "vertex_ties")},
+                 "step_hist": hist_dict(st["step_hist"])},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_step<false, float, 3, -1>",
                      "kernel_ms": ra["kernel_ms"], "algorithmic_bytes_per_launch": abytes},
@@ -514,6 +580,7 @@ def main():
             "value": n_feet / (rc["ms_per_step"] * 1e-3), "ms_per_step": rc["ms_per_step"],
             "kernel_ms": rc["kernel_ms"], "mean_walk_steps": stc["walk_steps"] / max(stc["feet"], 1),
             "roofline_frac": abytes / (rc["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        out["courant_range"] = measure_courant_range(mesh, w, v0)
         out["k_field_reuse"] = measure_k_reuse(mesh, w, v0)
         out["locators"] = measure_locators(mesh, w)
         out["precision"] = measure_precision()

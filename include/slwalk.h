@@ -7,7 +7,8 @@
  *   - semi-Lagrangian step v_i^{n+1} = I[V^n](X^Delta(x_i, t_{n+1}; t_n)),
  *     eq. (schema_trasp);
  *   - foot by explicit Euler backward in time, eq. (eulero), or by the
- *     explicit midpoint rule (the "suitable ODE solver" of Section 3);
+ *     explicit midpoint rule (the higher-order ODE solver that Section 3
+ *     leaves open);
  *   - point location by the barycentric walk of Section 2.2 (stop when all
  *     barycentric coordinates are >= 0, else cross the edge opposite the
  *     most negative one), started from the node's own incident triangles as
@@ -54,6 +55,13 @@
  *     magnitude in [2^-100, 2^100] (checked at upload); query coordinates
  *     may be any double (non-finite ones, and points outside the mesh's
  *     bounding box, are outside).
+ *   - Teardown order: free every handle (graphs, batches, networks,
+ *     meshes, then contexts) while the HIP runtime is still loaded, i.e.
+ *     before the process's exit handlers unload it.  A handle released after
+ *     that (for instance by a garbage collector running during interpreter
+ *     shutdown) calls hipFree on a runtime that is gone, which can crash the
+ *     process at exit; the Python binding frees all live handles from an
+ *     exit hook registered after the runtime was loaded, which runs first.
  *   - The mesh must be conforming (every edge shared by at most two
  *     triangles, consistently oriented), free of zero-area triangles, and
  *     its domain convex (one boundary loop with no reflex corner), so that
@@ -144,6 +152,12 @@ typedef struct slw_stats {
     int64_t edge_ties;      /* feet on an edge shared by two triangles */
     int64_t vertex_ties;    /* feet on a mesh vertex */
     int64_t reserved[7];
+    /* Walks by length (Section 2.2 walk steps = element changes): bin 0 counts
+     * walks with no change (feet outside the bounding box included), bin b
+     * for 1 <= b <= 14 those with [2^(b-1), 2^b) changes, bin 15 those with
+     * 2^14 or more.  The bins add up to `feet` (slw_locate_quadtree, which
+     * does not walk, leaves them 0). */
+    int64_t step_hist[16];
 } slw_stats;
 
 typedef struct slw_mesh_info {
@@ -258,10 +272,14 @@ slw_status slw_interpolate(slw_mesh *mesh, int order, const int32_t *elem, const
  * in one kernel: foot at t_n + dt, start selection, walk, tie rule, weights,
  * and k values per DOF: v_out[i] = I[v_in](foot_i), outside_value for feet
  * outside the domain.  start_mode as in slw_locate_feet (GIVEN/FIXED read
- * start).  v_in and v_out must not overlap. */
+ * start).  v_in and v_out must not overlap.  elem (nullable, device, one int
+ * per stepped DOF: the nodes for order 1, every DOF for order 2, in the DOF
+ * order of this interface) receives the user id of the triangle the step
+ * located each foot in (-1 outside): the same element slw_locate_feet
+ * returns for that foot. */
 slw_status slw_step(slw_mesh *mesh, const slw_field *field, double t_n, double dt, int scheme, int order,
                     int start_mode, const int32_t *start, const void *v_in, int vdtype, int k,
-                    void *v_out, double outside_value, slw_stats *stats_h);
+                    void *v_out, double outside_value, int32_t *elem, slw_stats *stats_h);
 
 /* Permute a DOF-indexed array (n_dofs rows of row_bytes) between the user
  * order and the internal order (to_internal != 0: user -> internal). */
@@ -290,6 +308,11 @@ slw_status slw_batch_free(slw_batch *b);
 slw_status slw_batch_set_fields(slw_batch *b, const slw_field *fields_h, const double *dt_h, const double *t0_h);
 /* device value buffers va_h[i], vb_h[i] (n_nodes x k of vdtype, internal order) */
 slw_status slw_batch_set_values(slw_batch *b, void *const *va_h, void *const *vb_h, int vdtype, int k);
+/* Optional element output: elem_h[i] (device, n_nodes ints of mesh i,
+ * internal order) receives the user id of the triangle each node's foot was
+ * located in (-1 outside) at every later step; elem_h NULL (or an entry
+ * NULL) turns it off.  Graphs captured afterwards keep the pointers. */
+slw_status slw_batch_set_elem_out(slw_batch *b, int32_t *const *elem_h);
 /* set / read the device step index (both synchronise the context's stream) */
 slw_status slw_batch_set_step(slw_batch *b, int64_t n);
 slw_status slw_batch_get_step(slw_batch *b, int64_t *n_h);

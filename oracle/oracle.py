@@ -10,8 +10,8 @@ Paper: Cacace & Ferretti, arXiv 2104.09189.  What is computed, and where it
 is defined:
 
 * feet: explicit Euler backward in time, eq. (eulero); the explicit
-  midpoint rule stands in for the paper's unnamed "suitable solver for
-  ordinary differential equations" (Section 3, before Algorithm 1).
+  midpoint rule as the higher-order ODE solver that Section 3 (before
+  Algorithm 1) leaves open.
 * location: the walk of Section 2.2 stops in a triangle where every
   barycentric coordinate is non-negative, i.e. a closed triangle containing
   the point.  The oracle returns that result by definition, without a walk:

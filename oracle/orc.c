@@ -329,8 +329,8 @@ int orc_locate(const double *xy, int64_t n, const int32_t *tri, int64_t nt,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Advecting fields and feet (eq. eulero; midpoint variant for the "suitable
- * ODE solver" of Section 3). */
+/* Advecting fields and feet (eq. eulero; the explicit midpoint rule as the
+ * higher-order ODE solver that Section 3 leaves open). */
 
 void orc_field(int kind, const double *p, double x, double y, double t, double *out)
 {

@@ -1,19 +1,23 @@
-"""Build libslwalk.so (HIP, gfx950) in-tree with hipcc."""
+"""Build libslwalk.so (HIP, gfx950) in-tree with hipcc: one object per
+source, compiled in parallel, then linked."""
 from __future__ import annotations
 
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 from pathlib import Path
 
 PKG = Path(__file__).resolve().parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libslwalk.so"
-SOURCES = ["slw_api.cpp", "slw_mesh.cpp", "slw_kernels.hip", "slw_learned.hip", "slw_quadtree.cpp"]
+OBJ = PKG.parent / "_build"
+SOURCES = ["slw_api.cpp", "slw_mesh.cpp", "slw_kernels.hip", "slw_learned.hip", "slw_quadtree.cpp",
+           "slw_noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
-    "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
+    "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
     # every floating-point expression rounds as written: the static error
     # bounds of the orientation filters assume no fused multiply-add
     "-ffp-contract=off",
@@ -23,10 +27,23 @@ FLAGS = [
 ]
 
 
+def _compile(src: str, verbose: bool) -> Path:
+    obj = OBJ / (src + ".o")
+    cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", str(CSRC / src), "-o", str(obj)]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return obj
+
+
 def build(verbose: bool = False) -> Path:
-    objs = []
+    OBJ.mkdir(exist_ok=True)
+    sources = [s for s in SOURCES if (CSRC / s).exists()]
+    jobs = max(1, min(len(sources), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose), sources))
     tmp = LIB.with_suffix(".so.tmp")
-    cmd = [HIPCC, *FLAGS, "-x", "hip", *[str(CSRC / s) for s in SOURCES], "-o", str(tmp)]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *[str(o) for o in objs], "-o", str(tmp)]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -95,6 +95,8 @@ slw_status end_stats(slw_ctx *ctx, slw_stats *stats_h)
     stats_h->fallback_walks = (int64_t)h.fallback_walks;
     stats_h->edge_ties = (int64_t)h.edge_ties;
     stats_h->vertex_ties = (int64_t)h.vertex_ties;
+    for (int b = 0; b < kHistBins; ++b)
+        stats_h->step_hist[b] = (int64_t)h.step_hist[b];
     if (h.hard_fail)
         return set_error(SLW_E_WALK, std::to_string(h.hard_fail) + " walks exceeded the hard step limit");
     return SLW_OK;
@@ -453,7 +455,7 @@ slw_status slw_interpolate(slw_mesh *mesh, int order, const int32_t *elem, const
 
 slw_status slw_step(slw_mesh *mesh, const slw_field *field, double t_n, double dt, int scheme, int order,
                     int start_mode, const int32_t *start, const void *v_in, int vdtype, int k, void *v_out,
-                    double outside_value, slw_stats *stats_h)
+                    double outside_value, int32_t *elem, slw_stats *stats_h)
 {
     if (!mesh || !field_ok(field) || !v_in || !v_out || k < 1)
         return set_error(SLW_E_ARG, "slw_step: null pointer, bad field or k < 1");
@@ -504,7 +506,7 @@ slw_status slw_step(slw_mesh *mesh, const slw_field *field, double t_n, double d
     const bool write_prev = start_mode == SLW_START_PREV;
     FieldDev fd = to_dev(field);
     st = hip_check(launch_step(m, ctx->stream, fd, t_n, dt, scheme, order, start_mode, start, vin_int, vdtype, k,
-                               v_out, outside_value, write_prev, out_map, stats_h ? ctx->stats : nullptr),
+                               v_out, outside_value, write_prev, out_map, elem, stats_h ? ctx->stats : nullptr),
                    "slw_step");
     if (st != SLW_OK)
         return st;
@@ -723,6 +725,16 @@ slw_status slw_batch_set_values(slw_batch *b, void *const *va_h, void *const *vb
     b->vdtype = vdtype;
     b->k = k;
     b->have_values = 1;
+    DeviceGuard g(b->ctx->device);
+    return batch_upload_items(b);
+}
+
+slw_status slw_batch_set_elem_out(slw_batch *b, int32_t *const *elem_h)
+{
+    if (!b)
+        return set_error(SLW_E_ARG, "slw_batch_set_elem_out: batch is NULL");
+    for (size_t i = 0; i < b->items_h.size(); ++i)
+        b->items_h[i].elem = elem_h ? elem_h[i] : nullptr;
     DeviceGuard g(b->ctx->device);
     return batch_upload_items(b);
 }

@@ -103,9 +103,13 @@ struct DevMesh {
 };
 
 // Device counters accumulated by the kernels (all int64, see slw_stats).
+// step_hist: walks by element changes, bin 0 = no change, bin b in [1, 14]
+// = [2^(b-1), 2^b) changes, bin 15 = 2^14 or more.
+constexpr int kHistBins = 16;
 struct DevStats {
     unsigned long long feet, outside, walk_steps, max_steps, exact_tests, fp64_tests, fallback_walks,
         edge_ties, vertex_ties, hard_fail, pad[6];
+    unsigned long long step_hist[kHistBins];
 };
 
 }  // namespace slw
@@ -239,7 +243,8 @@ hipError_t launch_interp(const DevMesh &m, hipStream_t st, int order, const int3
                          bool user_order);
 hipError_t launch_step(const DevMesh &m, hipStream_t st, const FieldDev &f, double t_n, double dt, int scheme,
                        int order, int start_mode, const int32_t *start, const void *v_in, int vdtype, int k,
-                       void *v_out, double outside, bool write_prev, const int32_t *out_map, DevStats *stats);
+                       void *v_out, double outside, bool write_prev, const int32_t *out_map, int32_t *elem_out,
+                       DevStats *stats);
 hipError_t launch_zero_stats(hipStream_t st, DevStats *p);
 // chart starts (the mesh needs a chart; kind 0: the exact chart cell of the
 // foot; 1: the attached network's cell; 2: the network's cell corrected by
@@ -256,6 +261,7 @@ struct BatchItem {
     double dt, t0;   // step n advances from t0 + n dt to t0 + (n + 1) dt
     const void *va;  // even steps read va and write vb, odd steps the reverse
     void *vb;
+    int32_t *elem;   // nullable: user triangle id of each node's foot (-1 outside), internal node order
     int64_t n_iter;  // DOFs stepped (the nodes: P1)
     int64_t tile0;   // first tile of this mesh in the concatenated tile space
 };

@@ -696,6 +696,31 @@ __device__ inline void flush_stats(const LaneStats &ls, DevStats *st)
     }
 }
 
+// bin of a walk of `steps` element changes in DevStats::step_hist
+__device__ inline int hist_bin(int32_t steps)
+{
+    if (steps <= 0)
+        return 0;
+    const int b = 32 - __clz(steps);  // steps in [2^(b-1), 2^b)
+    return b < kHistBins - 1 ? b : kHistBins - 1;
+}
+
+// one walk per calling lane into the histogram: the calling lanes are
+// grouped by bin, one atomic per distinct bin
+__device__ inline void hist_add(DevStats *st, int32_t steps)
+{
+    const int bin = hist_bin(steps);
+    unsigned long long todo = __ballot(1);
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int lb = __shfl(bin, leader, kWave);
+        const unsigned long long same = __ballot(bin == lb) & todo;
+        if ((int)(threadIdx.x & (kWave - 1)) == leader)
+            atomicAdd(&st->step_hist[lb], (unsigned long long)__popcll(same));
+        todo &= ~same;
+    }
+}
+
 // queries outside the mesh's bounding box (or not finite) are outside
 // without a walk; written so that NaN compares false
 template <typename R>
@@ -760,8 +785,10 @@ __global__ void __launch_bounds__(kBlock) k_locate(MeshView mv, const typename C
             }
             w = walk<F32>(mv, j0, qx, qy, (uint32_t)i * 2654435761u, ls.c);
         }
-        if (st)
+        if (st) {
             ls.add(w);
+            hist_add(st, w.steps);
+        }
         const int32_t uf = w.elem >= 0 ? mv.tri_uf[w.elem] : -1;
         elem[i] = w.elem >= 0 ? (uf & kUidMask) : -1;
         if (bary) {
@@ -886,8 +913,10 @@ __global__ void __launch_bounds__(kBlock)
         }
         if (mode == SLW_START_PREV)
             store_stream(mv.prev + d, w.elem);
-        if (st)
+        if (st) {
             ls.add(w);
+            hist_add(st, w.steps);
+        }
         const int32_t uf = w.elem >= 0 ? mv.tri_uf[w.elem] : -1;
         if (elem)
             elem[api] = w.elem >= 0 ? (uf & kUidMask) : -1;
@@ -1308,7 +1337,8 @@ template <bool F32, typename V, int NA, int KIND = -1>
 __device__ inline void step_wave(const MeshView &mv, const FieldDev &f, double dt, double t_np1, int scheme, int mode,
                                  const int32_t *__restrict__ start, const V *__restrict__ vin, int k,
                                  V *__restrict__ vout, double outside, int write_prev,
-                                 const int32_t *__restrict__ out_map, int64_t n_iter, int64_t base, DevStats *st)
+                                 const int32_t *__restrict__ out_map, int32_t *__restrict__ elem_out,
+                                 int64_t n_iter, int64_t base, DevStats *st)
 {
     using R = typename CT<F32>::R;
     using R2 = typename CT<F32>::R2;
@@ -1351,8 +1381,12 @@ __device__ inline void step_wave(const MeshView &mv, const FieldDev &f, double d
         }
         if (write_prev)
             store_stream(mv.prev + d, w.elem);
-        if (st)
+        if (elem_out)
+            elem_out[out_map ? (int64_t)out_map[d] : d] = w.elem >= 0 ? (mv.tri_uf[w.elem] & kUidMask) : -1;
+        if (st) {
             ls.add(w);
+            hist_add(st, w.steps);
+        }
         if (w.elem >= 0) {
             lagrange<R, V, NA>(mv, w.elem, w.v, w.th, row, wgt);
         } else if (mv.bc_kind && (w.flags & 16)) {
@@ -1386,11 +1420,11 @@ template <bool F32, typename V, int NA, int KIND = -1>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(step_waves_per_eu(KIND))))
     k_step(MeshView mv, FieldDev f, double dt, double t_np1, int scheme, int mode, const int32_t *__restrict__ start,
            const V *__restrict__ vin, int k, V *__restrict__ vout, double outside, int write_prev,
-           const int32_t *__restrict__ out_map, int64_t n_iter, DevStats *st)
+           const int32_t *__restrict__ out_map, int32_t *__restrict__ elem_out, int64_t n_iter, DevStats *st)
 {
     const int64_t base = xcd_tile(blockIdx.x, gridDim.x) * kBlock + (threadIdx.x & ~(kWave - 1));
     step_wave<F32, V, NA, KIND>(mv, f, dt, t_np1, scheme, mode, start, vin, k, vout, outside, write_prev, out_map,
-                                n_iter, base, st);
+                                elem_out, n_iter, base, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -1421,8 +1455,8 @@ __device__ inline void wave_lds_sync()
 template <bool F32, typename V, int NA, int L>
 __global__ void __launch_bounds__(kWave)
     k_step_chain(MeshView mv, FieldDev f, double dt, int scheme, const V *__restrict__ vin, int k,
-                 V *__restrict__ vout, double outside, const int32_t *__restrict__ out_map, int64_t n_iter,
-                 DevStats *st)
+                 V *__restrict__ vout, double outside, const int32_t *__restrict__ out_map,
+                 int32_t *__restrict__ elem_out, int64_t n_iter, DevStats *st)
 {
     using R = typename CT<F32>::R;
     using R2 = typename CT<F32>::R2;
@@ -1457,8 +1491,12 @@ __global__ void __launch_bounds__(kWave)
                     j0 = nearer_start<F32>(mv, prev, j0, qx, qy);
                 w = walk<F32>(mv, j0, qx, qy, (uint32_t)d * 2654435761u, ls.c);
             }
-            if (st)
+            if (st) {
                 ls.add(w);
+                hist_add(st, w.steps);
+            }
+            if (elem_out)
+                elem_out[out_map ? (int64_t)out_map[d] : d] = w.elem >= 0 ? (mv.tri_uf[w.elem] & kUidMask) : -1;
             prev = w.elem;
             if (w.elem >= 0)
                 lagrange<R, V, NA>(mv, w.elem, w.v, w.th, row, wgt);
@@ -1525,7 +1563,7 @@ __device__ __forceinline__ void batch_tile(const BatchItem *__restrict__ items, 
     V *vout = (V *)(even ? it.vb : it.va);
     const int64_t base = (tile - it.tile0) * BS + (threadIdx.x & ~(kWave - 1));
     step_wave<F32, V, 3>(it.mv, f, it.dt, it.t0 + (double)(step + 1) * it.dt, scheme, SLW_START_STEERED, nullptr,
-                         vin, k, vout, outside, 0, nullptr, it.n_iter, base, st);
+                         vin, k, vout, outside, 0, nullptr, it.elem, it.n_iter, base, st);
 }
 
 // schedule 0: one workgroup per tile, XCD-contiguous ranges of the
@@ -1662,8 +1700,9 @@ template <bool F32, typename V, int NA, int RP, bool NET>
 __device__ inline void step_chunk(const MeshView &mv, const FieldDev &f, double dt, double t_np1, int scheme, int mode,
                                   const int32_t *__restrict__ start, const V *__restrict__ vin, int k,
                                   V *__restrict__ vout, double outside, int write_prev,
-                                  const int32_t *__restrict__ out_map, int64_t n_iter, int64_t base,
-                                  typename CT<F32>::R2 *sq, int32_t *sj, int8_t *sz, DevStats *st)
+                                  const int32_t *__restrict__ out_map, int32_t *__restrict__ elem_out,
+                                  int64_t n_iter, int64_t base, typename CT<F32>::R2 *sq, int32_t *sj, int8_t *sz,
+                                  DevStats *st)
 {
     using R = typename CT<F32>::R;
     using R2 = typename CT<F32>::R2;
@@ -1729,6 +1768,8 @@ __device__ inline void step_chunk(const MeshView &mv, const FieldDev &f, double 
                         seed = (uint32_t)(base + cand) * 2654435761u;
                     } else if (j0 == -1) {
                         ls.add_walk(false, 0, 0);
+                        if (st)
+                            hist_add(st, 0);
                     }
                 }
             }
@@ -1747,6 +1788,8 @@ __device__ inline void step_chunk(const MeshView &mv, const FieldDev &f, double 
                 sj[slot] = res == 1 ? j : -1;
                 sz[slot] = (int8_t)zmask;
                 ls.add_walk(res == 1, steps, flags);
+                if (st)
+                    hist_add(st, steps);
                 slot = -1;
             }
         }
@@ -1781,6 +1824,8 @@ __device__ inline void step_chunk(const MeshView &mv, const FieldDev &f, double 
             }
             if (write_prev)
                 store_stream(mv.prev + d, elem);
+            if (elem_out)
+                elem_out[out_map ? (int64_t)out_map[d] : d] = elem >= 0 ? (mv.tri_uf[elem] & kUidMask) : -1;
         }
         const int nf = (int)min<int64_t>(kWave, n_iter - gbase);
         wave_interp<V, NA>(row, wgt, nf, vin, k, vout, out_map, gbase, (V)outside);
@@ -1793,7 +1838,7 @@ template <bool F32, typename V, int NA, int RP, bool NET>
 __global__ void __launch_bounds__(kBlock)
     k_step_rp(MeshView mv, FieldDev f, double dt, double t_np1, int scheme, int mode, const int32_t *__restrict__ start,
               const V *__restrict__ vin, int k, V *__restrict__ vout, double outside, int write_prev,
-              const int32_t *__restrict__ out_map, int64_t n_iter, DevStats *st)
+              const int32_t *__restrict__ out_map, int32_t *__restrict__ elem_out, int64_t n_iter, DevStats *st)
 {
     constexpr int W = kBlock / kWave, C = kWave * RP;
     __shared__ typename CT<F32>::R2 sq[W][C];
@@ -1802,7 +1847,7 @@ __global__ void __launch_bounds__(kBlock)
     const int w = threadIdx.x / kWave;
     const int64_t base = xcd_tile(blockIdx.x, gridDim.x) * (int64_t)(kBlock * RP) + (int64_t)w * C;
     step_chunk<F32, V, NA, RP, NET>(mv, f, dt, t_np1, scheme, mode, start, vin, k, vout, outside, write_prev, out_map,
-                               n_iter, base, sq[w], sj[w], sz[w], st);
+                                    elem_out, n_iter, base, sq[w], sj[w], sz[w], st);
 }
 
 // Training pairs: for the DOFs dofs[i] (internal positions) the plain walk
@@ -1970,7 +2015,7 @@ hipError_t launch_interp(const DevMesh &m, hipStream_t st, int order, const int3
 
 hipError_t launch_step(const DevMesh &m, hipStream_t st, const FieldDev &f0, double t_n, double dt, int scheme,
                        int order, int mode, const int32_t *start, const void *v_in, int vdtype, int k, void *v_out,
-                       double outside, bool write_prev, const int32_t *out_map, DevStats *stats)
+                       double outside, bool write_prev, const int32_t *out_map, int32_t *elem_out, DevStats *stats)
 {
     MeshView mv = view_of(m);
     FieldDev f = f0;
@@ -1991,7 +2036,7 @@ hipError_t launch_step(const DevMesh &m, hipStream_t st, const FieldDev &f0, dou
         // lower the occupancy of its long walks; its own kernel runs first)
 #define SLW_STEP_CHART(F32, V, KD)                                                                                \
     hipLaunchKernelGGL((k_step<F32, V, 3, KD>), dim3(g), dim3(kBlock), 0, st, mv, f, dt, t_n + dt, scheme, mode,    \
-                       start, (const V *)v_in, k, (V *)v_out, outside, (int)write_prev, out_map, n_iter, stats)
+                       start, (const V *)v_in, k, (V *)v_out, outside, (int)write_prev, out_map, elem_out, n_iter, stats)
 #define SLW_STEP_CHART_K(F32, V)                                                                                  \
     do {                                                                                                          \
         if (kind == 0) SLW_STEP_CHART(F32, V, 0); else SLW_STEP_CHART(F32, V, 2);                                 \
@@ -2021,7 +2066,7 @@ hipError_t launch_step(const DevMesh &m, hipStream_t st, const FieldDev &f0, dou
         const unsigned gc = (unsigned)(t < 1 ? 1 : t);
 #define SLW_CHAIN_L(F32, V, NA, LL)                                                                               \
     hipLaunchKernelGGL((k_step_chain<F32, V, NA, LL>), dim3(gc), dim3(kWave), 0, st, mv, f, dt, scheme,           \
-                       (const V *)v_in, k, (V *)v_out, outside, out_map, n_iter, stats)
+                       (const V *)v_in, k, (V *)v_out, outside, out_map, elem_out, n_iter, stats)
 #define SLW_CHAIN(F32, V, NA)                                \
     do {                                                     \
         switch (L) {                                         \
@@ -2060,13 +2105,13 @@ hipError_t launch_step(const DevMesh &m, hipStream_t st, const FieldDev &f0, dou
 #define SLW_STEP_RP(F32, V, NA, RP)                                                                             \
     hipLaunchKernelGGL((k_step_rp<F32, V, NA, RP, false>), dim3(g), dim3(kBlock), 0, st, mv, f, dt, t_n + dt, scheme,   \
                        mode, start,                                                                             \
-                       (const V *)v_in, k, (V *)v_out, outside, (int)write_prev, out_map, n_iter, stats)
+                       (const V *)v_in, k, (V *)v_out, outside, (int)write_prev, out_map, elem_out, n_iter, stats)
 #define SLW_STEP(F32, V, NA)                                                                                   \
     do {                                                                                                       \
     if (rp > 0 && mode == SLW_START_LEARNED) {                                                                 \
         hipLaunchKernelGGL((k_step_rp<F32, V, NA, 4, true>), dim3(g4), dim3(kBlock), 0, st, mv, f, dt, t_n + dt, \
                            scheme, mode, start, (const V *)v_in, k, (V *)v_out, outside, (int)write_prev,      \
-                           out_map, n_iter, stats);                                                            \
+                           out_map, elem_out, n_iter, stats);                                                  \
         break;                                                                                                 \
     }                                                                                                          \
     switch (rp) {                                                                                              \
@@ -2077,10 +2122,11 @@ hipError_t launch_step(const DevMesh &m, hipStream_t st, const FieldDev &f0, dou
         if (mode == SLW_START_PREV)                                                                            \
             hipLaunchKernelGGL((k_step<F32, V, NA, -2>), dim3(g), dim3(kBlock), 0, st, mv, f, dt, t_n + dt, scheme, \
                                mode, start, (const V *)v_in, k, (V *)v_out, outside, (int)write_prev, out_map,   \
-                               n_iter, stats);                                                                 \
+                               elem_out, n_iter, stats);                                                       \
         else                                                                                                   \
             hipLaunchKernelGGL((k_step<F32, V, NA>), dim3(g), dim3(kBlock), 0, st, mv, f, dt, t_n + dt, scheme, mode, \
-                               start, (const V *)v_in, k, (V *)v_out, outside, (int)write_prev, out_map, n_iter, stats); \
+                               start, (const V *)v_in, k, (V *)v_out, outside, (int)write_prev, out_map, elem_out, \
+                               n_iter, stats);                                                                 \
     }                                                                                                          \
     } while (0)
     if (m.coords_f32) {

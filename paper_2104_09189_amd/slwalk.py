@@ -58,10 +58,12 @@ class slw_field(ctypes.Structure):
 class slw_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "feet", "outside", "walk_steps", "max_steps", "exact_tests", "fp64_tests", "fallback_walks",
-        "edge_ties", "vertex_ties")] + [("reserved", ctypes.c_int64 * 7)]
+        "edge_ties", "vertex_ties")] + [("reserved", ctypes.c_int64 * 7), ("step_hist", ctypes.c_int64 * 16)]
 
     def as_dict(self):
-        return {n: int(getattr(self, n)) for n, _ in self._fields_ if n != "reserved"}
+        d = {n: int(getattr(self, n)) for n, _ in self._fields_ if n not in ("reserved", "step_hist")}
+        d["step_hist"] = [int(x) for x in self.step_hist]
+        return d
 
 
 class slw_mesh_info(ctypes.Structure):
@@ -108,7 +110,7 @@ _sig("slw_locate_feet", ctypes.c_int, [_vp, ctypes.POINTER(slw_field), _dbl, _db
 _sig("slw_interpolate", ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _i64, _vp, ctypes.c_int, ctypes.c_int, _vp,
                                        _dbl])
 _sig("slw_step", ctypes.c_int, [_vp, ctypes.POINTER(slw_field), _dbl, _dbl, ctypes.c_int, ctypes.c_int,
-                                ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _dbl,
+                                ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _dbl, _vp,
                                 ctypes.POINTER(slw_stats)])
 _sig("slw_permute_rows", ctypes.c_int, [_vp, _vp, _vp, _i64, ctypes.c_int])
 _sig("slw_orient_sign_host", ctypes.c_int, [_vp, _i64, _vp, ctypes.c_int])
@@ -117,6 +119,7 @@ _sig("slw_batch_create", ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.POINTER(_
 _sig("slw_batch_free", ctypes.c_int, [_vp])
 _sig("slw_batch_set_fields", ctypes.c_int, [_vp, ctypes.POINTER(slw_field), _vp, _vp])
 _sig("slw_batch_set_values", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int])
+_sig("slw_batch_set_elem_out", ctypes.c_int, [_vp, _vp])
 _sig("slw_batch_set_step", ctypes.c_int, [_vp, _i64])
 _sig("slw_batch_get_step", ctypes.c_int, [_vp, ctypes.POINTER(_i64)])
 _sig("slw_batch_set_schedule", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int])
@@ -153,7 +156,7 @@ EXPORTED = ["slw_status_string", "slw_last_error", "slw_ctx_create", "slw_ctx_se
             "slw_mesh_set_walk_limits", "slw_mesh_set_repack", "slw_mesh_set_neighbour_codes", "slw_walk_codes_host", "slw_mesh_set_chain", "slw_mesh_set_boundary", "slw_locate", "slw_locate_feet", "slw_interpolate", "slw_step",
             "slw_permute_rows", "slw_orient_sign_host",
             "slw_float_filter_host", "slw_batch_create", "slw_batch_free", "slw_batch_set_fields",
-            "slw_batch_set_values", "slw_batch_set_step", "slw_batch_get_step", "slw_batch_set_schedule",
+            "slw_batch_set_values", "slw_batch_set_elem_out", "slw_batch_set_step", "slw_batch_get_step", "slw_batch_set_schedule",
             "slw_batch_step", "slw_batch_graph_capture", "slw_graph_launch", "slw_graph_free", "slw_batch_autotune",
             "slw_chart_build", "slw_chart_coords", "slw_mlp_create", "slw_mlp_free", "slw_mlp_set_params",
             "slw_mlp_get_params", "slw_mlp_set_normalization", "slw_mlp_get_normalization",
@@ -285,6 +288,7 @@ class Mesh:
         self.internal_order = bool(info.internal_order)
         self.bbox = tuple(info.bbox)
         self.cdtype = _torch().float32 if self.coords_f32 else _torch().float64
+        self.chart_g = 0
 
     # -- mesh queries
     def dof_coords(self) -> np.ndarray:
@@ -447,7 +451,10 @@ class Mesh:
         return v_out
 
     def step(self, field, t_n, dt, scheme, v_in, v_out=None, order=1, start_mode=START_STEERED, start=None,
-             outside_value=0.0, stats=False):
+             outside_value=0.0, stats=False, elem=None):
+        """slw_step.  elem (optional int32 tensor, one entry per stepped DOF)
+        receives the element of each foot.  Returns v_out, or (v_out, stats)
+        with stats=True."""
         torch = _torch()
         dev = self.ctx.device
         vdtype = _vdtype(v_in)
@@ -459,11 +466,14 @@ class Mesh:
             v_out = torch.empty_like(v_in)
         if v_out.shape != v_in.shape:
             raise ValueError("v_out must have the shape of v_in")
+        if elem is not None and tuple(elem.shape) != (rows,):
+            raise ValueError(f"elem must hold {rows} ints")
         st = slw_stats() if stats else None
         _check(_lib.slw_step(self.h, ctypes.byref(make_field(field)), float(t_n), float(dt), int(scheme), int(order),
                              int(start_mode), _ptr(start, torch.int32, dev, "start", True),
                              _ptr(v_in, v_in.dtype, dev, "v_in"), vdtype, k, _ptr(v_out, v_in.dtype, dev, "v_out"),
-                             float(outside_value), ctypes.byref(st) if st is not None else None), "slw_step")
+                             float(outside_value), _ptr(elem, torch.int32, dev, "elem", True),
+                             ctypes.byref(st) if st is not None else None), "slw_step")
         return (v_out, st.as_dict()) if stats else v_out
 
     def permute_rows(self, src, dst=None, to_internal=True):
@@ -515,6 +525,25 @@ class Batch:
         pb = (ctypes.c_void_p * n)(*[t.data_ptr() for t in vb])
         _check(_lib.slw_batch_set_values(self.h, pa, pb, _vdtype(va[0]), k), "slw_batch_set_values")
         self._values = (list(va), list(vb))
+
+    def set_elem_out(self, elems):
+        """elems[i]: int32 device tensor of n_nodes_i entries (internal order)
+        that receives the element of each foot at every later step; None
+        turns the output off."""
+        if elems is None:
+            _check(_lib.slw_batch_set_elem_out(self.h, None), "slw_batch_set_elem_out")
+            self._elems = None
+            return
+        torch = _torch()
+        dev = self.ctx.device
+        n = len(self.meshes)
+        for i in range(n):
+            if tuple(elems[i].shape) != (self.meshes[i].n_nodes,):
+                raise ValueError(f"element buffer of mesh {i} must hold n_nodes ints")
+            _ptr(elems[i], torch.int32, dev, "elem")
+        pe = (ctypes.c_void_p * n)(*[t.data_ptr() for t in elems])
+        _check(_lib.slw_batch_set_elem_out(self.h, pe), "slw_batch_set_elem_out")
+        self._elems = list(elems)
 
     def set_step(self, n: int):
         _check(_lib.slw_batch_set_step(self.h, int(n)), "slw_batch_set_step")

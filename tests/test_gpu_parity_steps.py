@@ -1,0 +1,291 @@
+"""Index parity of the fused step's own elements (slw_step's elem output),
+strategy (b) over consecutive steps on moved feet, the graded mesh across
+its Courant range (5, 20, 50) with the chart and learned-index starts, and
+batches (a few small meshes, and the 64-mesh batch on a per-mesh sample).
+
+Where the GPU computes the feet itself (trigonometric fields), its feet
+agree with the oracle's to a few ulps but need not be identical; elements
+are then compared with check_elements_near: bit-exact wherever the oracle's
+foot is farther than that bound from every edge of its element, a triangle
+within the bound elsewhere (a handful of feet).  Where the feet are the same
+IEEE operations on both sides (constant fields), or are passed in, elements
+must be identical everywhere.
+"""
+import numpy as np
+import pytest
+
+from paper_2104_09189_amd import inputs as I
+from gpu_util import check_elements_near, ctx as _ctx, dev, host, rel_err
+
+pytestmark = pytest.mark.gpu
+
+# feet of FP64 meshes: the GPU's are within 8 ulp of the oracle's (unit
+# square coordinates); the bound used for elements is eight times that
+R64 = 64 * 2.0 ** -52
+# feet of float meshes: float coordinates, feet and field (relative 2^-24),
+# against the oracle's FP64 feet on the float-rounded mesh
+R32 = 1e-6
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2104_09189_amd import slwalk
+    return slwalk
+
+
+@pytest.fixture(scope="module")
+def C(S):
+    return _ctx()
+
+
+@pytest.fixture(scope="module")
+def graded5():
+    return I.graded_swirl(alpha=5.0)
+
+
+def _step_elems(S, mesh, w, t_n, v_in, mode=None, stats=False):
+    import torch
+    mode = S.START_STEERED if mode is None else mode
+    e = torch.empty(v_in.shape[0], dtype=torch.int32, device="cuda:0")
+    r = mesh.step(w.field, t_n, w.dt, w.scheme, v_in, start_mode=mode, elem=e, stats=stats)
+    if stats:
+        v, st = r
+        return host(v), host(e), st
+    return host(r), host(e)
+
+
+# ---------------------------------------------------------------------------
+# the headline step's own elements
+
+def test_headline_step_elements_full_graded(S, C, orc, graded5):
+    """Every one of the 2,002,225 elements of one fused step (strategy (a),
+    RK2, K = 16 FP32 fields, internal order: the benchmark's launch) against
+    the oracle on its own feet; values at every DOF to 1e-5."""
+    w = graded5
+    mesh = S.Mesh(C, w.xy, w.tri, S.INTERNAL_ORDER)
+    perm = mesh.dof_order()
+    t_n = 7 * w.dt
+    v0 = w.v0.astype(np.float32)
+    v, e, st = _step_elems(S, mesh, w, t_n, dev(v0[perm]), stats=True)
+    q_ref = orc.feet(w.xy, w.field, t_n + w.dt, w.dt, w.scheme)
+    e_ref, b_ref = orc.locate(w.xy, w.tri, q_ref)
+    e_user = np.empty_like(e)
+    e_user[perm] = e
+    n_amb = check_elements_near(w.xy, w.tri, q_ref, e_ref, e_user, R64)
+    print(f"near-edge feet: {n_amb}")
+    ref = orc.interp(1, w.tri, e_ref, b_ref, v0.astype(np.float64), w.xy.shape[0])
+    v_user = np.empty_like(v)
+    v_user[perm] = v
+    assert rel_err(v_user, ref, np.abs(v0).max()) < 1e-5
+    # the walk statistics describe the same step
+    assert st["feet"] == w.xy.shape[0]
+    assert sum(st["step_hist"]) == st["feet"]
+    assert st["walk_steps"] > 10 * st["feet"]
+
+
+@pytest.mark.parametrize("alpha", [20.0, 50.0])
+def test_graded_courant_range_indices_values_and_chart_starts(S, C, orc, alpha):
+    """The graded mesh at Courant 20 and 50 (walks of up to about 1,200
+    element changes): every foot located on the oracle's feet (identical
+    query points: bit-exact), from the steered start, the exact chart start
+    and the learned index; the fused step's elements and its 16 FP32 values
+    on a 20,000-DOF sample; the step's elements and values identical for the
+    three starts."""
+    w = I.graded_swirl(alpha=alpha)
+    mesh = S.Mesh(C, w.xy, w.tri, S.INTERNAL_ORDER)
+    perm = mesh.dof_order()
+    t_n = 7 * w.dt
+    feet = orc.feet(w.xy, w.field, t_n + w.dt, w.dt, w.scheme)
+    e_ref, b_ref = orc.locate(w.xy, w.tri, feet)
+    mesh.chart_build(2048)
+    net = S.Mlp(C, seed=0)        # untrained: its guesses are poor, the searches still end in the foot's cell
+    mesh.attach_mlp(net)
+    fd = dev(feet[perm])
+    for mode in (S.START_STEERED, S.START_CHART, S.START_LEARNED_INDEX):
+        out = mesh.locate_feet(feet=fd, feet_in=True, start_mode=mode, stats=True)
+        e = host(out["elem"])
+        assert (e == e_ref[perm]).all(), mode
+        assert np.abs(host(out["bary"]) - b_ref[perm]).max() < 1e-12
+        if mode == S.START_STEERED:
+            assert out["stats"]["max_steps"] > (100 if alpha == 50.0 else 30)
+    rng = np.random.default_rng(3030 + int(alpha))
+    sample = rng.choice(w.xy.shape[0], 20000, replace=False)     # internal positions
+    users = perm[sample]
+    v0 = w.v0.astype(np.float32)
+    vin = dev(v0[perm])
+    res = {}
+    for mode in (S.START_STEERED, S.START_CHART, S.START_LEARNED_INDEX):
+        res[mode] = _step_elems(S, mesh, w, t_n, vin, mode)
+    v, e = res[S.START_STEERED]
+    for mode in (S.START_CHART, S.START_LEARNED_INDEX):
+        assert np.array_equal(res[mode][0], v) and np.array_equal(res[mode][1], e), mode
+    q_ref = feet[users]
+    check_elements_near(w.xy, w.tri, q_ref, e_ref[users], e[sample], R64)
+    ref = orc.interp(1, w.tri, e_ref[users], b_ref[users], v0.astype(np.float64), w.xy.shape[0])
+    assert rel_err(v[sample], ref, np.abs(v0).max()) < 1e-5
+    mesh.attach_mlp(None)
+    net.free()
+
+
+# ---------------------------------------------------------------------------
+# strategy (b): the second of two steps walks from the first step's elements
+
+@pytest.mark.parametrize("shift,where", [
+    ((0.5, 0.0), "edge 0 (top of the cell)"),
+    ((1.0, 0.5), "edge 1 (left side of the cell)"),
+    ((0.5, 0.5), "edge 2 (the diagonal)"),
+    ((1.0, 1.0), "vertex 0"),
+    ((1.0, 0.0), "vertex 2"),
+    ((0.0, 0.0), "vertex 1"),
+    ((0.75, -0.3), "interior of the lower neighbour cell"),
+    ((-2.6, 3.4), "three cells away"),
+])
+def test_strategy_b_second_step_on_edges_and_vertices(S, C, orc, shift, where):
+    """Unjittered 65 x 65 grid (h = 1/64), constant fields, dt = 1 (feet are
+    the same IEEE operations on both sides: identical elements required
+    everywhere).  Step 1 puts every foot at (0.75 h, 0.9 h) inside the
+    upper-left triangle (v00, v11, v01) of the cell below-left of its node;
+    step 2 (strategy (b): from that element) moves the foot onto one of that
+    triangle's edges or vertices, into a neighbour, or further, so that each
+    branch of the first test on the previous element runs: one zero sign on
+    each local edge (tie with the neighbour across it), two zero signs (the
+    vertex's star), and a walk away from the previous element."""
+    n = 65
+    h = 1.0 / (n - 1)
+    xy = I.grid_nodes(n)
+    tri = I.grid_triangles(n)
+    mesh = S.Mesh(C, xy, tri)
+    v0 = I.gaussian_hill(xy, sigma=0.2)[:, None]
+    vin = dev(v0)
+
+    class W:
+        scheme = I.SCHEME_EULER
+        dt = 1.0
+    w1, w2 = W(), W()
+    w1.field = I.constant(0.25 * h, 0.1 * h)
+    w2.field = I.constant(shift[0] * h, shift[1] * h)
+    _, e1, _ = _step_elems(S, mesh, w1, 0.0, vin, S.START_PREV, stats=True)
+    q1 = orc.feet(xy, w1.field, 1.0, 1.0, I.SCHEME_EULER)
+    r1, _ = orc.locate(xy, tri, q1)
+    assert np.array_equal(e1, r1)
+    v2, e2, st = _step_elems(S, mesh, w2, 0.0, vin, S.START_PREV, stats=True)
+    ref, q2, r2, _ = orc.sl_step(xy, tri, v0, w2.field, 0.0, 1.0, I.SCHEME_EULER)
+    assert np.array_equal(e2, r2), where
+    assert rel_err(v2, ref, np.abs(v0).max()) < 1e-12
+    # interior nodes stop in their previous element at once (boundary nodes,
+    # whose first foot was outside, start steered and may move a little)
+    if "edge" in where:
+        assert st["edge_ties"] > 0.9 * (n - 2) ** 2 and st["walk_steps"] < 4 * n
+    elif "vertex" in where:
+        assert st["vertex_ties"] > 0.9 * (n - 2) ** 2 and st["walk_steps"] < 4 * n
+    else:
+        assert st["walk_steps"] > (n - 2) ** 2
+
+
+def test_strategy_b_moved_feet_full_500(S, C, orc):
+    """The 500 x 500 jittered mesh (random input order), swirl, Courant 20:
+    step 1 at t = 0.3, step 2 (from step 1's elements) at t = 0.6, so every
+    foot has moved; every element of step 2 against the oracle, FP64 values
+    to 1e-12."""
+    w = I.swirl_500(alpha=20.0, order="random")
+    mesh = S.Mesh(C, w.xy, w.tri)
+    vin = dev(w.v0)
+    _step_elems(S, mesh, w, 0.3, vin, S.START_PREV)
+    v, e, st = _step_elems(S, mesh, w, 0.6, vin, S.START_PREV, stats=True)
+    ref, q, r, _ = orc.sl_step(w.xy, w.tri, w.v0, w.field, 0.6, w.dt, w.scheme)
+    check_elements_near(w.xy, w.tri, q, r, e, R64)
+    assert rel_err(v, ref, np.abs(w.v0).max()) < 1e-12
+    assert st["walk_steps"] > w.xy.shape[0]            # the second step walks
+
+
+def test_strategy_b_moved_feet_graded(S, C, orc, graded5):
+    """The graded mesh, RK2, 16 FP32 fields: step 1 at 7 dt, step 2 at 9 dt
+    from step 1's elements; all 2,002,225 elements of step 2 against the
+    oracle; values on a sample."""
+    w = graded5
+    mesh = S.Mesh(C, w.xy, w.tri, S.INTERNAL_ORDER)
+    perm = mesh.dof_order()
+    v0 = w.v0.astype(np.float32)
+    vin = dev(v0[perm])
+    _step_elems(S, mesh, w, 7 * w.dt, vin, S.START_PREV)
+    v, e, st = _step_elems(S, mesh, w, 9 * w.dt, vin, S.START_PREV, stats=True)
+    assert st["walk_steps"] > 0.1 * st["feet"]
+    q = orc.feet(w.xy, w.field, 10 * w.dt, w.dt, w.scheme)
+    r, b = orc.locate(w.xy, w.tri, q)
+    e_user = np.empty_like(e)
+    e_user[perm] = e
+    check_elements_near(w.xy, w.tri, q, r, e_user, R64)
+    sample = np.random.default_rng(77).choice(w.xy.shape[0], 20000, replace=False)
+    users = perm[sample]
+    ref = orc.interp(1, w.tri, r[users], b[users], v0.astype(np.float64), w.xy.shape[0])
+    assert rel_err(v[sample], ref, np.abs(v0).max()) < 1e-5
+
+
+# ---------------------------------------------------------------------------
+# batches: elements per mesh
+
+def _batch(S, C, wl, flags):
+    import torch
+    meshes = [S.Mesh(C, w.xy, w.tri, S.INTERNAL_ORDER | flags) for w in wl]
+    perms = [m.dof_order() for m in meshes]
+    va = [dev(np.ascontiguousarray(w.v0[p].astype(np.float32))) for w, p in zip(wl, perms)]
+    vb = [torch.empty_like(a) for a in va]
+    el = [torch.empty(m.n_nodes, dtype=torch.int32, device="cuda:0") for m in meshes]
+    b = S.Batch(C, meshes)
+    b.set_fields([w.field for w in wl], [w.dt for w in wl])
+    b.set_values(va, vb)
+    b.set_elem_out(el)
+    return meshes, perms, va, vb, el, b
+
+
+def _small_batch():
+    out = []
+    for k, (n, period) in enumerate(((21, 0.7), (64, 1.3), (9, 2.0), (37, 0.5), (50, 1.0))):
+        xy, tri = I.jittered_grid(n, 4100 + k)
+        h = 1.0 / (n - 1)
+        out.append(I.Workload(f"b{k}", xy, tri, I.swirl(period), I.SCHEME_EULER, 5.0 * h, 10,
+                              I.gaussian_hill(xy)[:, None], h))
+    return out
+
+
+@pytest.mark.parametrize("f32", [False, True])
+def test_batch_elements_and_values_small(S, C, orc, f32):
+    """Five uneven meshes, every schedule and workgroup size: each mesh's
+    elements against the oracle (float meshes: the oracle on the
+    float-rounded mesh), values to 1e-5 of the same oracle step."""
+    wl = _small_batch()
+    meshes, perms, va, vb, el, b = _batch(S, C, wl, S.COORDS_F32 if f32 else 0)
+    for schedule, block in ((0, 256), (1, 128), (0, 64), (1, 512)):
+        b.set_schedule(schedule, block)
+        b.set_step(2)                                   # even: va -> vb, from 2 dt to 3 dt
+        b.step(S.SLW_EULER)
+        for w, p, e, out in zip(wl, perms, el, vb):
+            xy = w.xy.astype(np.float32).astype(np.float64) if f32 else w.xy
+            v0 = w.v0.astype(np.float32).astype(np.float64)
+            ref, q, r, _ = orc.sl_step(xy, w.tri, v0, w.field, 2 * w.dt, w.dt, I.SCHEME_EULER)
+            check_elements_near(xy, w.tri, q[p], r[p], host(e), R32 if f32 else R64, max_share=0.02)
+            assert rel_err(host(out), ref[p], 1.0) < 1e-5
+
+
+def test_batch_64_meshes_sampled(S, C, orc):
+    """The 64-mesh batch of the benchmark (8.5M triangles, float
+    coordinates, Hilbert order): one step; on each mesh 1,000 sampled nodes'
+    elements against the oracle on the float-rounded mesh and their values to
+    1e-5."""
+    wl = I.batch_meshes()
+    meshes, perms, va, vb, el, b = _batch(S, C, wl, S.COORDS_F32 | S.HILBERT)
+    b.set_step(4)
+    st = b.step(S.SLW_EULER, stats=True)
+    assert st["feet"] == sum(m.n_nodes for m in meshes)
+    rng = np.random.default_rng(6464)
+    n_amb = 0
+    for w, m, p, e, out in zip(wl, meshes, perms, el, vb):
+        sample = rng.choice(m.n_nodes, min(1000, m.n_nodes), replace=False)   # internal positions
+        users = p[sample]
+        xy = w.xy.astype(np.float32).astype(np.float64)
+        q = orc.feet(xy[users], w.field, 5 * w.dt, w.dt, I.SCHEME_EULER)
+        r, bb = orc.locate(xy, w.tri, q)
+        n_amb += check_elements_near(xy, w.tri, q, r, host(e)[sample], R32, max_share=0.02)
+        ref = orc.interp(1, w.tri, r, bb, w.v0.astype(np.float64), xy.shape[0])
+        assert rel_err(host(out)[sample], ref, 1.0) < 1e-5, w.name
+    print(f"near-edge feet in the 64 samples: {n_amb}")

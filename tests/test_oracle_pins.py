@@ -383,6 +383,27 @@ def test_bf16_rounding_and_adam_first_step():
     assert np.allclose(p1, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12)
 
 
+def test_adam_three_steps_hand_worked():
+    """Adam's moment rates, bias corrections and update over three steps with
+    distinct gradients (hand-worked fixture, Kingma & Ba 2015, Algorithm 1):
+    a swap of the two decay rates or a wrong correction exponent changes the
+    second and third steps."""
+    from oracle import mlp
+    rows = [ln.split() for ln in open(os.path.join(GOLDEN, "adam_three_steps.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    ref = np.array([[float(x) for x in r[1:]] for r in rows])
+    p, m, v = np.zeros(1), np.zeros(1), np.zeros(1)
+    for t, g in enumerate((1.0, -1.0, 2.0), start=1):
+        p, m, v = mlp.adam(p, np.array([g]), m, v, t, lr=0.01, b1=0.9, b2=0.999, eps=0.0)
+        mh, vh = m / (1 - 0.9 ** t), v / (1 - 0.999 ** t)
+        assert np.allclose([m[0], v[0], mh[0], vh[0], p[0]], ref[t - 1], rtol=1e-13, atol=0), t
+    # the fixture discriminates: the same gradients with the rates swapped
+    p2, m2, v2 = np.zeros(1), np.zeros(1), np.zeros(1)
+    for t, g in enumerate((1.0, -1.0), start=1):
+        p2, m2, v2 = mlp.adam(p2, np.array([g]), m2, v2, t, lr=0.01, b1=0.999, b2=0.9, eps=0.0)
+    assert abs(p2[0] - ref[1, 4]) > 1e-4
+
+
 # ---------------------------------------------------------------------------
 # variable step at the boundary
 
