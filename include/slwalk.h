@@ -281,6 +281,26 @@ slw_status slw_step(slw_mesh *mesh, const slw_field *field, double t_n, double d
                     int start_mode, const int32_t *start, const void *v_in, int vdtype, int k,
                     void *v_out, double outside_value, int32_t *elem, slw_stats *stats_h);
 
+/* slw_step for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, results and errors as slw_step, but it calls no hipMalloc,
+ * hipFree or allocating library routine: its statistics counters and the
+ * workspace that permutes v_in into the internal order (user-order meshes
+ * only) live in one static device array of 64 MiB that each GPU the library
+ * runs on holds until the process ends (its address is resolved per device
+ * by slw_ctx_create).  A user-order mesh needs rows x k x value-size bytes
+ * of it (rows = n_nodes for order 1, n_dofs for order 2); more than
+ * 64 MiB - 256 B fails with SLW_E_ARG before anything is launched
+ * (SLW_INTERNAL_ORDER meshes need none).  Every call on a GPU shares that
+ * GPU's array, and the array keeps the last call's contents (counters are
+ * cleared by a kernel at the start of each call that returns statistics):
+ * calls that overlap on one GPU -- on different streams or host threads --
+ * race, and must be serialised by the caller.  With stats_h the call
+ * synchronises the context's stream (as slw_step does). */
+slw_status slw_step_noalloc(slw_mesh *mesh, const slw_field *field, double t_n, double dt, int scheme, int order,
+                            int start_mode, const int32_t *start, const void *v_in, int vdtype, int k,
+                            void *v_out, double outside_value, int32_t *elem, slw_stats *stats_h);
+
 /* Permute a DOF-indexed array (n_dofs rows of row_bytes) between the user
  * order and the internal order (to_internal != 0: user -> internal). */
 slw_status slw_permute_rows(slw_mesh *mesh, const void *src, void *dst, int64_t row_bytes, int to_internal);

@@ -59,26 +59,12 @@ FieldDev to_dev(const slw_field *f)
     return d;
 }
 
-}  // namespace slw
-
-using namespace slw;
-
-namespace {
-
-slw_status begin_stats(slw_ctx *ctx, slw_stats *stats_h)
-{
-    if (!stats_h)
-        return SLW_OK;
-    // a fill kernel rather than a memset node keeps the call graph-capturable
-    return hip_check(launch_zero_stats(ctx->stream, ctx->stats), "zero stats");
-}
-
-slw_status end_stats(slw_ctx *ctx, slw_stats *stats_h)
+slw_status copy_stats(slw_ctx *ctx, const DevStats *counters, slw_stats *stats_h)
 {
     if (!stats_h)
         return SLW_OK;
     DevStats h;
-    slw_status st = hip_check(hipMemcpyAsync(&h, ctx->stats, sizeof h, hipMemcpyDeviceToHost, ctx->stream),
+    slw_status st = hip_check(hipMemcpyAsync(&h, counters, sizeof h, hipMemcpyDeviceToHost, ctx->stream),
                               "hipMemcpyAsync(stats)");
     if (st != SLW_OK)
         return st;
@@ -102,7 +88,105 @@ slw_status end_stats(slw_ctx *ctx, slw_stats *stats_h)
     return SLW_OK;
 }
 
+}  // namespace slw
+
+using namespace slw;
+
+namespace {
+
+slw_status begin_stats(slw_ctx *ctx, slw_stats *stats_h)
+{
+    if (!stats_h)
+        return SLW_OK;
+    // a fill kernel rather than a memset node keeps the call graph-capturable
+    return hip_check(launch_zero_stats(ctx->stream, ctx->stats), "zero stats");
+}
+
+slw_status end_stats(slw_ctx *ctx, slw_stats *stats_h) { return copy_stats(ctx, ctx->stats, stats_h); }
+
 }  // namespace
+
+namespace slw {
+
+// slw_step and slw_step_noalloc: checks, the permutation of v_in into the
+// internal order (user-order meshes), the step launch and the statistics.
+// With sc.stats == nullptr the context's counters and grow-only workspace are
+// used; otherwise sc.stats and sc.work (sc.work_bytes at most, never grown).
+slw_status step_impl(slw_mesh *mesh, const slw_field *field, double t_n, double dt, int scheme, int order,
+                     int start_mode, const int32_t *start, const void *v_in, int vdtype, int k, void *v_out,
+                     double outside_value, int32_t *elem, slw_stats *stats_h, const StepScratch &sc,
+                     const char *who)
+{
+    const std::string w(who);
+    if (!mesh || !field_ok(field) || !v_in || !v_out || k < 1)
+        return set_error(SLW_E_ARG, w + ": null pointer, bad field or k < 1");
+    if (order != 1 && order != 2)
+        return set_error(SLW_E_ARG, w + ": order must be 1 or 2");
+    if (order == 2 && !mesh->m.p2)
+        return set_error(SLW_E_UNSUPPORTED, w + ": P2 needs a mesh uploaded with SLW_P2");
+    if (scheme != SLW_EULER && scheme != SLW_RK2)
+        return set_error(SLW_E_ARG, w + ": unknown scheme");
+    if (vdtype != SLW_F64 && vdtype != SLW_F32)
+        return set_error(SLW_E_ARG, w + ": unknown vdtype");
+    if (start_mode < SLW_START_STEERED || start_mode > SLW_START_LEARNED_INDEX)
+        return set_error(SLW_E_ARG, w + ": unknown start mode");
+    if ((start_mode == SLW_START_GIVEN || start_mode == SLW_START_FIXED) && !start)
+        return set_error(SLW_E_ARG, w + ": start array required for this start mode");
+    if ((start_mode == SLW_START_LEARNED || start_mode == SLW_START_LEARNED_INDEX) && !mesh->m.mlp)
+        return set_error(SLW_E_ARG, w + ": learned starts need a network attached (slw_mesh_attach_mlp)");
+    if (start_mode == SLW_START_CHART && !mesh->m.chart_table)
+        return set_error(SLW_E_ARG, w + ": SLW_START_CHART needs a chart (slw_chart_build)");
+    const DevMesh &m = mesh->m;
+    if (m.bc_kind && start_mode == SLW_START_NEIGHBOR)
+        return set_error(SLW_E_UNSUPPORTED, w + ": boundary data with SLW_START_NEIGHBOR");
+    // P1 uses the vertex DOFs only (the first n_nodes of either order)
+    const int64_t rows = order == 1 ? m.n_nodes : m.n_dofs;
+    const size_t vsz = vdtype == SLW_F64 ? 8 : 4;
+    const size_t bytes = (size_t)rows * (size_t)k * vsz;
+    const char *vi = (const char *)v_in, *vo = (const char *)v_out;
+    if (vi < vo + bytes && vo < vi + bytes)
+        return set_error(SLW_E_ARG, w + ": v_in and v_out overlap");
+    const bool permute = !m.internal_order && m.reordered;
+    if (sc.stats && permute && bytes > sc.work_bytes)
+        return set_error(SLW_E_ARG, w + ": v_in needs " + std::to_string(bytes) +
+                                        " bytes of scratch for the permutation into the internal order, at most " +
+                                        std::to_string(sc.work_bytes) + " are available (use SLW_INTERNAL_ORDER)");
+    slw_ctx *ctx = mesh->ctx;
+    DeviceGuard g(ctx->device);
+    DevStats *counters = sc.stats ? sc.stats : ctx->stats;
+    slw_status st = SLW_OK;
+    if (stats_h)
+        st = hip_check(launch_zero_stats(ctx->stream, counters), "zero stats");
+    if (st != SLW_OK)
+        return st;
+    const void *vin_int = v_in;
+    const int32_t *out_map = nullptr;
+    if (permute) {
+        void *work = sc.work;
+        if (!sc.stats) {
+            st = ensure_work(ctx, bytes);
+            if (st != SLW_OK)
+                return st;
+            work = ctx->work;
+        }
+        st = hip_check(launch_permute_rows(ctx->stream, v_in, work, rows, (int64_t)(k * vsz), m.dof_user, 0),
+                       "permute v_in");
+        if (st != SLW_OK)
+            return st;
+        vin_int = work;
+        out_map = m.dof_user;
+    }
+    const bool write_prev = start_mode == SLW_START_PREV;
+    FieldDev fd = to_dev(field);
+    st = hip_check(launch_step(m, ctx->stream, fd, t_n, dt, scheme, order, start_mode, start, vin_int, vdtype, k,
+                               v_out, outside_value, write_prev, out_map, elem, stats_h ? counters : nullptr),
+                   who);
+    if (st != SLW_OK)
+        return st;
+    return copy_stats(ctx, counters, stats_h);
+}
+
+}  // namespace slw
 
 extern "C" {
 
@@ -143,6 +227,11 @@ slw_status slw_ctx_create(int device, void *hip_stream, slw_ctx **out)
         return set_error(SLW_E_NOMEM, "context");
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
+    slw_status sn = noalloc_init(device);
+    if (sn != SLW_OK) {
+        delete c;
+        return sn;
+    }
     e = hipMalloc((void **)&c->stats, sizeof(DevStats));
     if (e != hipSuccess) {
         delete c;
@@ -457,60 +546,9 @@ slw_status slw_step(slw_mesh *mesh, const slw_field *field, double t_n, double d
                     int start_mode, const int32_t *start, const void *v_in, int vdtype, int k, void *v_out,
                     double outside_value, int32_t *elem, slw_stats *stats_h)
 {
-    if (!mesh || !field_ok(field) || !v_in || !v_out || k < 1)
-        return set_error(SLW_E_ARG, "slw_step: null pointer, bad field or k < 1");
-    if (order != 1 && order != 2)
-        return set_error(SLW_E_ARG, "order must be 1 or 2");
-    if (order == 2 && !mesh->m.p2)
-        return set_error(SLW_E_UNSUPPORTED, "P2 needs a mesh uploaded with SLW_P2");
-    if (scheme != SLW_EULER && scheme != SLW_RK2)
-        return set_error(SLW_E_ARG, "unknown scheme");
-    if (vdtype != SLW_F64 && vdtype != SLW_F32)
-        return set_error(SLW_E_ARG, "unknown vdtype");
-    if (start_mode < SLW_START_STEERED || start_mode > SLW_START_LEARNED_INDEX)
-        return set_error(SLW_E_ARG, "unknown start mode");
-    if ((start_mode == SLW_START_GIVEN || start_mode == SLW_START_FIXED) && !start)
-        return set_error(SLW_E_ARG, "start array required for this start mode");
-    if ((start_mode == SLW_START_LEARNED || start_mode == SLW_START_LEARNED_INDEX) && !mesh->m.mlp)
-        return set_error(SLW_E_ARG, "learned starts need a network attached (slw_mesh_attach_mlp)");
-    if (start_mode == SLW_START_CHART && !mesh->m.chart_table)
-        return set_error(SLW_E_ARG, "SLW_START_CHART needs a chart (slw_chart_build)");
-    const DevMesh &m = mesh->m;
-    // P1 uses the vertex DOFs only (the first n_nodes of either order)
-    const int64_t rows = order == 1 ? m.n_nodes : m.n_dofs;
-    const size_t vsz = vdtype == SLW_F64 ? 8 : 4;
-    const size_t bytes = (size_t)rows * (size_t)k * vsz;
-    const char *vi = (const char *)v_in, *vo = (const char *)v_out;
-    if (vi < vo + bytes && vo < vi + bytes)
-        return set_error(SLW_E_ARG, "v_in and v_out overlap");
-    slw_ctx *ctx = mesh->ctx;
-    DeviceGuard g(ctx->device);
-    slw_status st = begin_stats(ctx, stats_h);
-    if (st != SLW_OK)
-        return st;
-    const void *vin_int = v_in;
-    const int32_t *out_map = nullptr;
-    if (!m.internal_order && m.reordered) {
-        st = ensure_work(ctx, bytes);
-        if (st != SLW_OK)
-            return st;
-        st = hip_check(launch_permute_rows(ctx->stream, v_in, ctx->work, rows, (int64_t)(k * vsz), m.dof_user, 0),
-                       "permute v_in");
-        if (st != SLW_OK)
-            return st;
-        vin_int = ctx->work;
-        out_map = m.dof_user;
-    }
-    if (m.bc_kind && start_mode == SLW_START_NEIGHBOR)
-        return set_error(SLW_E_UNSUPPORTED, "boundary data with SLW_START_NEIGHBOR");
-    const bool write_prev = start_mode == SLW_START_PREV;
-    FieldDev fd = to_dev(field);
-    st = hip_check(launch_step(m, ctx->stream, fd, t_n, dt, scheme, order, start_mode, start, vin_int, vdtype, k,
-                               v_out, outside_value, write_prev, out_map, elem, stats_h ? ctx->stats : nullptr),
-                   "slw_step");
-    if (st != SLW_OK)
-        return st;
-    return end_stats(ctx, stats_h);
+    StepScratch sc;  // the context's counters and grow-only workspace
+    return step_impl(mesh, field, t_n, dt, scheme, order, start_mode, start, v_in, vdtype, k, v_out, outside_value,
+                     elem, stats_h, sc, "slw_step");
 }
 
 slw_status slw_orient_sign_host(const double *pts_h, int64_t m, int8_t *out_h, int mode)

@@ -144,6 +144,23 @@ struct slw_mlp {
 };
 
 namespace slw {
+// where a step keeps its counters and its permutation workspace: stats ==
+// nullptr selects the context's (counters from slw_ctx_create, workspace
+// grown on demand); otherwise the given memory, work_bytes at most
+struct StepScratch {
+    DevStats *stats = nullptr;
+    void *work = nullptr;
+    size_t work_bytes = 0;
+};
+slw_status step_impl(slw_mesh *mesh, const slw_field *field, double t_n, double dt, int scheme, int order,
+                     int start_mode, const int32_t *start, const void *v_in, int vdtype, int k, void *v_out,
+                     double outside_value, int32_t *elem, slw_stats *stats_h, const StepScratch &sc,
+                     const char *who);
+slw_status copy_stats(slw_ctx *ctx, const DevStats *counters, slw_stats *stats_h);
+// resolves, once per device, the device address of the no-allocation
+// entry point's static scratch array (slw_noalloc.hip); the device must be
+// current
+slw_status noalloc_init(int device);
 slw_status set_error(slw_status s, const std::string &msg);
 slw_status hip_check(hipError_t e, const char *what);
 slw_status ensure_work(slw_ctx *ctx, size_t bytes);

@@ -112,6 +112,9 @@ _sig("slw_interpolate", ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _i64, _vp, c
 _sig("slw_step", ctypes.c_int, [_vp, ctypes.POINTER(slw_field), _dbl, _dbl, ctypes.c_int, ctypes.c_int,
                                 ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _dbl, _vp,
                                 ctypes.POINTER(slw_stats)])
+_sig("slw_step_noalloc", ctypes.c_int, [_vp, ctypes.POINTER(slw_field), _dbl, _dbl, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _dbl, _vp,
+                                        ctypes.POINTER(slw_stats)])
 _sig("slw_permute_rows", ctypes.c_int, [_vp, _vp, _vp, _i64, ctypes.c_int])
 _sig("slw_orient_sign_host", ctypes.c_int, [_vp, _i64, _vp, ctypes.c_int])
 _sig("slw_float_filter_host", ctypes.c_int, [_vp, _i64, _dbl, _dbl, _dbl, ctypes.c_int, _vp])
@@ -154,7 +157,7 @@ MLP_PARAMS = 5 * 64 + 64 + 64 * 64 + 64 + 64 * 2 + 2
 EXPORTED = ["slw_status_string", "slw_last_error", "slw_ctx_create", "slw_ctx_set_stream", "slw_ctx_destroy",
             "slw_mesh_upload", "slw_mesh_check", "slw_mesh_free", "slw_mesh_get_info", "slw_mesh_dof_coords", "slw_mesh_dof_order",
             "slw_mesh_set_walk_limits", "slw_mesh_set_repack", "slw_mesh_set_neighbour_codes", "slw_walk_codes_host", "slw_mesh_set_chain", "slw_mesh_set_boundary", "slw_locate", "slw_locate_feet", "slw_interpolate", "slw_step",
-            "slw_permute_rows", "slw_orient_sign_host",
+            "slw_step_noalloc", "slw_permute_rows", "slw_orient_sign_host",
             "slw_float_filter_host", "slw_batch_create", "slw_batch_free", "slw_batch_set_fields",
             "slw_batch_set_values", "slw_batch_set_elem_out", "slw_batch_set_step", "slw_batch_get_step", "slw_batch_set_schedule",
             "slw_batch_step", "slw_batch_graph_capture", "slw_graph_launch", "slw_graph_free", "slw_batch_autotune",
@@ -451,10 +454,10 @@ class Mesh:
         return v_out
 
     def step(self, field, t_n, dt, scheme, v_in, v_out=None, order=1, start_mode=START_STEERED, start=None,
-             outside_value=0.0, stats=False, elem=None):
-        """slw_step.  elem (optional int32 tensor, one entry per stepped DOF)
-        receives the element of each foot.  Returns v_out, or (v_out, stats)
-        with stats=True."""
+             outside_value=0.0, stats=False, elem=None, noalloc=False):
+        """slw_step (slw_step_noalloc with noalloc=True).  elem (optional
+        int32 tensor, one entry per stepped DOF) receives the element of each
+        foot.  Returns v_out, or (v_out, stats) with stats=True."""
         torch = _torch()
         dev = self.ctx.device
         vdtype = _vdtype(v_in)
@@ -469,11 +472,12 @@ class Mesh:
         if elem is not None and tuple(elem.shape) != (rows,):
             raise ValueError(f"elem must hold {rows} ints")
         st = slw_stats() if stats else None
-        _check(_lib.slw_step(self.h, ctypes.byref(make_field(field)), float(t_n), float(dt), int(scheme), int(order),
-                             int(start_mode), _ptr(start, torch.int32, dev, "start", True),
-                             _ptr(v_in, v_in.dtype, dev, "v_in"), vdtype, k, _ptr(v_out, v_in.dtype, dev, "v_out"),
-                             float(outside_value), _ptr(elem, torch.int32, dev, "elem", True),
-                             ctypes.byref(st) if st is not None else None), "slw_step")
+        fn, name = (_lib.slw_step_noalloc, "slw_step_noalloc") if noalloc else (_lib.slw_step, "slw_step")
+        _check(fn(self.h, ctypes.byref(make_field(field)), float(t_n), float(dt), int(scheme), int(order),
+                  int(start_mode), _ptr(start, torch.int32, dev, "start", True),
+                  _ptr(v_in, v_in.dtype, dev, "v_in"), vdtype, k, _ptr(v_out, v_in.dtype, dev, "v_out"),
+                  float(outside_value), _ptr(elem, torch.int32, dev, "elem", True),
+                  ctypes.byref(st) if st is not None else None), name)
         return (v_out, st.as_dict()) if stats else v_out
 
     def permute_rows(self, src, dst=None, to_internal=True):
