@@ -393,11 +393,22 @@ def measure_learned(alpha=50.0, n=1415, k=16, steps=10, samples_per_step=200_000
             "speedup_chart_vs_plain": base / res["chart_exact"]["ms_per_step"]}
 
 
+def torch_zeros_like_values(mesh, k=1):
+    import torch
+    return torch.zeros((mesh.n_nodes, k), dtype=torch.float32, device="cuda:0")
+
+
 def wave_walks(mesh, w, t_n, mode) -> dict:
     """Walk lengths of one step's feet (element changes per foot) as the step
     kernel's wavefronts see them: 64 consecutive internal-order DOFs per
     wavefront, each waiting for its longest walk."""
     from paper_2104_09189_amd import slwalk as S
+    if mode == S.START_NEIGHBOR:
+        # the step's own statistics (slw_locate_feet has no forest): the
+        # per-foot lengths are not available, only the mean and maximum
+        _, st = mesh.step(w.field, t_n, w.dt, w.scheme, torch_zeros_like_values(mesh), start_mode=mode, stats=True)
+        return {"mean": st["walk_steps"] / max(st["feet"], 1), "mean_wavefront_max": None, "p99": None,
+                "max": st["max_steps"]}
     if mode == S.START_PREV:
         # the previous element of every DOF from the step before
         mesh.locate_feet(w.field, t_n, w.dt, w.scheme, start_mode=mode, want_bary=False, want_elem=False)
@@ -425,7 +436,7 @@ def measure_courant_range(mesh, w, v0, steps=20, warmup=3, alphas=(1.0, 5.0, 20.
         wa = dataclasses.replace(w, dt=dt)
         line = {"dt": dt}
         for name, mode in (("a_steered", S.START_STEERED), ("b_previous", S.START_PREV),
-                           ("chart_exact", S.START_CHART)):
+                           ("c_tree", S.START_NEIGHBOR), ("chart_exact", S.START_CHART)):
             r = measure(mesh, wa, v0, steps, warmup, mode)
             ww = wave_walks(mesh, wa, 7 * dt, mode)
             line[name] = {"ms_per_step": r["ms_per_step"], "kernel_ms": r["kernel_ms"],
@@ -572,14 +583,19 @@ def main():
             "ms_per_step": rb["ms_per_step"], "kernel_ms": rb["kernel_ms"],
             "mean_walk_steps": stb["walk_steps"] / max(stb["feet"], 1),
             "roofline_frac": abytes / (rb["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
-        mesh.set_chain(2)
-        rc = measure(mesh, w, v0, args.steps, args.warmup, S.START_NEIGHBOR)
-        stc = rc["stats"]
-        out["strategy_c"] = {
-            "start": "element found for the preceding node of a 2-node Morton chain (nearer of it and the steered start)",
-            "value": n_feet / (rc["ms_per_step"] * 1e-3), "ms_per_step": rc["ms_per_step"],
-            "kernel_ms": rc["kernel_ms"], "mean_walk_steps": stc["walk_steps"] / max(stc["feet"], 1),
-            "roofline_frac": abytes / (rc["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        for chain, key, desc in ((0, "strategy_c", "element found for the parent node, an adjacent root of a "
+                                  "depth-one forest (when the parent is nearer than the node's own foot), else the "
+                                  "steered start; roots first, two launches"),
+                                 (2, "strategy_c_chain2", "element found for the preceding node of a 2-node Morton chain "
+                                  "(nearer of it and the steered start)")):
+            mesh.set_chain(chain)
+            rc = measure(mesh, w, v0, args.steps, args.warmup, S.START_NEIGHBOR)
+            stc = rc["stats"]
+            out[key] = {
+                "start": desc, "value": n_feet / (rc["ms_per_step"] * 1e-3), "ms_per_step": rc["ms_per_step"],
+                "kernel_ms": rc["kernel_ms"], "mean_walk_steps": stc["walk_steps"] / max(stc["feet"], 1),
+                "roofline_frac": abytes / (rc["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        mesh.set_chain(0)
         out["courant_range"] = measure_courant_range(mesh, w, v0)
         out["k_field_reuse"] = measure_k_reuse(mesh, w, v0)
         out["locators"] = measure_locators(mesh, w)

@@ -110,9 +110,9 @@ enum {
                               slw_mesh_attach_mlp (learned start; see below) */
     SLW_START_CHART = 5,   /* the start-table triangle of the foot's own chart cell
                               (exact chart lookup, no network; needs slw_chart_build) */
-    SLW_START_NEIGHBOR = 6, /* strategy (c): the element found for the preceding node of a
-                              chain of consecutive internal-order nodes (slw_step only;
-                              see slw_mesh_set_chain) */
+    SLW_START_NEIGHBOR = 6, /* strategy (c): the element found for a neighbouring node, its
+                              parent in a spanning forest of the internal-order nodes
+                              (slw_step only; see slw_mesh_set_chain) */
     SLW_START_LEARNED_INDEX = 7 /* a learned index: the network's chart cell as the guess of
                               galloping searches in the chart's quantile tables, which end
                               in the foot's own cell (the start of SLW_START_CHART) */
@@ -230,17 +230,29 @@ slw_status slw_mesh_set_neighbour_codes(slw_mesh *mesh, int bits);
  * g = p[0] (SLW_BC_CONSTANT) or g = p[0] + p[1] px + p[2] py + p[3] t
  * (SLW_BC_AFFINE), for every field.  SLW_BC_NONE (the default) gives such
  * feet outside_value.  Applied by the one-foot-per-lane step kernel (the
- * lane schedule is ignored while set); not available with
+ * lane schedule is ignored while set); not available with the chains of
  * SLW_START_NEIGHBOR (SLW_E_UNSUPPORTED).  p_h: 4 doubles (host), ignored for
  * SLW_BC_NONE. */
 enum { SLW_BC_NONE = 0, SLW_BC_CONSTANT = 1, SLW_BC_AFFINE = 2 };
 slw_status slw_mesh_set_boundary(slw_mesh *mesh, int kind, const double *p_h);
 /* Strategy (c) of Section 3 (SLW_START_NEIGHBOR) starts a walk from the
- * element that contains an adjacent node's foot.  The spanning forest used
- * here is made of chains of `length` consecutive nodes of the internal
- * (Morton) order, one chain per lane: the first foot of a chain starts as
- * strategy (a), each later one from the element found for its predecessor.
- * length in {2, 4, 8, 16}; default 4. */
+ * element that contains an adjacent node's foot (its parent in a spanning
+ * tree).  The paper's breadth-first tree has about sqrt(N) sequential levels;
+ * the spanning forests used here are shallow:
+ *   length 0 (the default): a forest of depth one built at upload.  Its
+ *     roots are a maximal independent set of the mesh's nodes (greedy in
+ *     internal order: about a quarter of them); every other DOF is a child of
+ *     the nearest root among the vertices of its incident triangles.  The
+ *     roots are stepped first (strategy (a) start), then the children, each
+ *     from its parent's element unless its own node lies nearer its foot than
+ *     the parent node (then strategy (a)): two kernel launches per step.
+ *     Boundary data (slw_mesh_set_boundary) apply.
+ *   length 2, 4, 8 or 16: chains of that many consecutive internal-order
+ *     nodes, one chain per lane: the first foot of a chain starts as strategy
+ *     (a), each later one from the element found for its predecessor unless
+ *     its own steered start lies nearer (no boundary data:
+ *     SLW_E_UNSUPPORTED).
+ * Results never depend on the forest. */
 slw_status slw_mesh_set_chain(slw_mesh *mesh, int length);
 
 /* General point location, the analogue of the paper's [I, B] =

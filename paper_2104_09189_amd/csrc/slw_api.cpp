@@ -137,8 +137,8 @@ slw_status step_impl(slw_mesh *mesh, const slw_field *field, double t_n, double 
     if (start_mode == SLW_START_CHART && !mesh->m.chart_table)
         return set_error(SLW_E_ARG, w + ": SLW_START_CHART needs a chart (slw_chart_build)");
     const DevMesh &m = mesh->m;
-    if (m.bc_kind && start_mode == SLW_START_NEIGHBOR)
-        return set_error(SLW_E_UNSUPPORTED, w + ": boundary data with SLW_START_NEIGHBOR");
+    if (m.bc_kind && start_mode == SLW_START_NEIGHBOR && m.chain != 0)
+        return set_error(SLW_E_UNSUPPORTED, w + ": boundary data with SLW_START_NEIGHBOR on chains");
     // P1 uses the vertex DOFs only (the first n_nodes of either order)
     const int64_t rows = order == 1 ? m.n_nodes : m.n_dofs;
     const size_t vsz = vdtype == SLW_F64 ? 8 : 4;
@@ -441,8 +441,8 @@ slw_status slw_mesh_set_chain(slw_mesh *mesh, int length)
 {
     if (!mesh)
         return set_error(SLW_E_ARG, "mesh is NULL");
-    if (length != 2 && length != 4 && length != 8 && length != 16)
-        return set_error(SLW_E_ARG, "slw_mesh_set_chain: length must be 2, 4, 8 or 16");
+    if (length != 0 && length != 2 && length != 4 && length != 8 && length != 16)
+        return set_error(SLW_E_ARG, "slw_mesh_set_chain: length must be 0 (the mesh forest), 2, 4, 8 or 16");
     mesh->m.chain = length;
     return SLW_OK;
 }

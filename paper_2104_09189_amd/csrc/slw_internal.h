@@ -99,7 +99,18 @@ struct DevMesh {
     int32_t step_cap = 4096;
     int32_t hard_limit = 1 << 22;
     int repack = 0;  // step kernel: 0 one foot per lane; 2, 4, 8: chunks of 64 x repack feet per wavefront
-    int chain = 4;   // strategy (c): Morton chain length per lane (2, 4, 8, 16)
+    int chain = 0;   // strategy (c): 0 the mesh forest below; 2, 4, 8, 16 Morton chains of that length per lane
+    // strategy (c)'s forest (depth one): roots = a maximal independent set of
+    // the nodes (greedy in internal order), every other DOF a child of an
+    // adjacent root.  List = roots then children, each part in internal
+    // order; out = the output row of each list entry (user DOF id for
+    // user-order meshes, else the internal id); parent = internal id of the
+    // root of each child (-1: none adjacent).  Suffix 1: the nodes (P1);
+    // 2: every DOF (P2 meshes).  elem: the element found for each root.
+    int32_t *forest_list1 = nullptr, *forest_out1 = nullptr, *forest_parent1 = nullptr;
+    int32_t *forest_list2 = nullptr, *forest_out2 = nullptr, *forest_parent2 = nullptr;
+    int64_t forest_nr1 = 0, forest_nr2 = 0;
+    int32_t *forest_elem = nullptr;  // [n_dofs]
 };
 
 // Device counters accumulated by the kernels (all int64, see slw_stats).
@@ -200,6 +211,17 @@ FilterConst filter_constants(bool f32, double cx, double cy, double cmax);
 std::vector<WalkRec> walk_records(const std::vector<GeoRec> &geo, int bits);
 
 // launchers (slw_kernels.hip)
+
+// A step over a list of DOFs instead of all of them (strategy (c)'s roots or
+// children): list[pos] = internal DOF id, out[pos] = its output row,
+// parent[pos] = the root whose element it starts from (children only),
+// elem[d] = element found for root d.
+struct ForestView {
+    const int32_t *list = nullptr;
+    const int32_t *out = nullptr;
+    const int32_t *parent = nullptr;
+    int32_t *elem = nullptr;
+};
 
 // Everything a kernel needs to know about a mesh (device pointers, sizes,
 // filter constants), passed by value.

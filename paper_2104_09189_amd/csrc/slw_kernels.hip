@@ -1332,17 +1332,28 @@ __device__ inline bool boundary_value(const MeshView &mv, bool f32, double xx, d
 // cooperatively.  Every lane of the wavefront calls it.  KIND: -1 the start
 // given by `mode`; -2 strategy (b) (its own instantiation: the first test
 // reads the full record of the previous element, which holds registers the
-// other starts do not need); 0 / 2 chart starts computed here.
+// other starts do not need); 0 / 2 chart starts computed here; -3 / -4 the
+// roots / the other DOFs of strategy (c)'s forest: positions index the
+// forest's lists (fv), not the DOFs.
 template <bool F32, typename V, int NA, int KIND = -1>
 __device__ inline void step_wave(const MeshView &mv, const FieldDev &f, double dt, double t_np1, int scheme, int mode,
                                  const int32_t *__restrict__ start, const V *__restrict__ vin, int k,
                                  V *__restrict__ vout, double outside, int write_prev,
                                  const int32_t *__restrict__ out_map, int32_t *__restrict__ elem_out,
-                                 int64_t n_iter, int64_t base, DevStats *st)
+                                 int64_t n_iter, int64_t base, DevStats *st, ForestView fv = ForestView())
 {
     using R = typename CT<F32>::R;
     using R2 = typename CT<F32>::R2;
-    const int64_t d = base + (threadIdx.x & (kWave - 1));
+    constexpr bool FOREST = KIND == -3 || KIND == -4;
+    const int64_t pos = base + (threadIdx.x & (kWave - 1));
+    const bool valid = pos < n_iter;
+    int64_t d = pos;
+    if constexpr (FOREST) {
+        d = valid ? (int64_t)fv.list[pos] : 0;
+        out_map = fv.out;  // output row of each list position
+    }
+    // output row of this lane's DOF
+    const int64_t orow = FOREST ? (valid ? (int64_t)fv.out[pos] : 0) : (out_map && valid ? (int64_t)out_map[d] : d);
     LaneStats ls;
     int32_t row[NA];
     V wgt[NA];
@@ -1357,32 +1368,55 @@ __device__ inline void step_wave(const MeshView &mv, const FieldDev &f, double d
     x.x = x.y = (R)0;
     R qx = (R)0, qy = (R)0;
     int32_t sid = -1;
-    if (d < n_iter) {
+    if (valid) {
         x = ((const R2 *)mv.dof_xy)[d];
-        if constexpr (KIND < 0) {
+        int32_t p = -1;
+        if constexpr (KIND == -4) {
+            // strategy (c): the element found for this DOF's parent (a root
+            // adjacent to it in the mesh) by the roots' launch
+            p = fv.parent[pos];
+            sid = p >= 0 ? fv.elem[p] : -1;
+        } else if constexpr (KIND < 0 && KIND != -3) {
             const int64_t api = (mode == SLW_START_GIVEN && !mv.internal_order) ? mv.dof_user[d] : d;
             sid = start_id(mv, d, api, mode, start);
         }
         foot_of<R>(f, scheme, x.x, x.y, (R)dt, qx, qy);
+        if constexpr (KIND == -4) {
+            if (sid >= 0) {
+                // the parent's foot lies about as far from this foot as the
+                // parent node from this node: start from the parent's element
+                // unless this node is nearer its own foot (then its own
+                // steered start, strategy (a))
+                const R2 xp = ((const R2 *)mv.dof_xy)[p];
+                const float ex = (float)(xp.x - x.x), ey = (float)(xp.y - x.y);
+                const float ux = (float)(qx - x.x), uy = (float)(qy - x.y);
+                if (ex * ex + ey * ey >= ux * ux + uy * uy)
+                    sid = -1;
+            }
+        }
     }
     // with boundary data every finite foot is walked (to learn where it leaves)
-    const bool run = d < n_iter && (mv.bc_kind ? (isfinite((double)qx) && isfinite((double)qy))
-                                              : in_box<R>(qx, qy, mv.bb));
+    const bool run = valid && (mv.bc_kind ? (isfinite((double)qx) && isfinite((double)qy))
+                                          : in_box<R>(qx, qy, mv.bb));
     int32_t jc = 0;
     if constexpr (KIND >= 0)  // chart starts computed here, for the whole wavefront
         jc = chart_start<F32, KIND>(mv, run, d, x, qx, qy, t_np1);
-    if (d < n_iter) {
+    if (valid) {
         WalkResult<R> w = outside_result<R>(0, 0);
         if (run) {
             int32_t j0 = jc;
-            if constexpr (KIND < 0)
+            if constexpr (KIND == -3 || KIND == -4)
+                j0 = sid >= 0 ? sid : quadrant_start(mv.qstart[d], (float)(qx - x.x), (float)(qy - x.y));
+            else if constexpr (KIND < 0)
                 j0 = start_pick(mv, d, sid, mode, (float)(qx - x.x), (float)(qy - x.y));
             w = walk<F32>(mv, j0, qx, qy, (uint32_t)d * 2654435761u, ls.c, KIND == -2);
         }
+        if constexpr (KIND == -3)
+            fv.elem[d] = w.elem;
         if (write_prev)
             store_stream(mv.prev + d, w.elem);
         if (elem_out)
-            elem_out[out_map ? (int64_t)out_map[d] : d] = w.elem >= 0 ? (mv.tri_uf[w.elem] & kUidMask) : -1;
+            elem_out[orow] = w.elem >= 0 ? (mv.tri_uf[w.elem] & kUidMask) : -1;
         if (st) {
             ls.add(w);
             hist_add(st, w.steps);
@@ -1420,11 +1454,12 @@ template <bool F32, typename V, int NA, int KIND = -1>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(step_waves_per_eu(KIND))))
     k_step(MeshView mv, FieldDev f, double dt, double t_np1, int scheme, int mode, const int32_t *__restrict__ start,
            const V *__restrict__ vin, int k, V *__restrict__ vout, double outside, int write_prev,
-           const int32_t *__restrict__ out_map, int32_t *__restrict__ elem_out, int64_t n_iter, DevStats *st)
+           const int32_t *__restrict__ out_map, int32_t *__restrict__ elem_out, int64_t n_iter, DevStats *st,
+           ForestView fv)
 {
     const int64_t base = xcd_tile(blockIdx.x, gridDim.x) * kBlock + (threadIdx.x & ~(kWave - 1));
     step_wave<F32, V, NA, KIND>(mv, f, dt, t_np1, scheme, mode, start, vin, k, vout, outside, write_prev, out_map,
-                                elem_out, n_iter, base, st);
+                                elem_out, n_iter, base, st, fv);
 }
 
 // ---------------------------------------------------------------------------
@@ -2024,9 +2059,9 @@ hipError_t launch_step(const DevMesh &m, hipStream_t st, const FieldDev &f0, dou
     unsigned g;
     if (!tiles_for(n_iter, g))
         return hipErrorInvalidValue;
-    // boundary data are applied by the one-foot-per-lane kernel only
+    // boundary data are applied by the one-foot-per-lane kernels only
     const int rp = m.bc_kind ? 0 : m.repack;
-    if (m.bc_kind && mode == SLW_START_NEIGHBOR)
+    if (m.bc_kind && mode == SLW_START_NEIGHBOR && m.chain != 0)
         return hipErrorNotSupported;
     const bool chart_mode = mode == SLW_START_LEARNED || mode == SLW_START_CHART || mode == SLW_START_LEARNED_INDEX;
     const int kind = mode == SLW_START_CHART ? 0 : (mode == SLW_START_LEARNED ? 1 : 2);
@@ -2036,7 +2071,8 @@ hipError_t launch_step(const DevMesh &m, hipStream_t st, const FieldDev &f0, dou
         // lower the occupancy of its long walks; its own kernel runs first)
 #define SLW_STEP_CHART(F32, V, KD)                                                                                \
     hipLaunchKernelGGL((k_step<F32, V, 3, KD>), dim3(g), dim3(kBlock), 0, st, mv, f, dt, t_n + dt, scheme, mode,    \
-                       start, (const V *)v_in, k, (V *)v_out, outside, (int)write_prev, out_map, elem_out, n_iter, stats)
+                       start, (const V *)v_in, k, (V *)v_out, outside, (int)write_prev, out_map, elem_out, n_iter, stats, \
+                       ForestView())
 #define SLW_STEP_CHART_K(F32, V)                                                                                  \
     do {                                                                                                          \
         if (kind == 0) SLW_STEP_CHART(F32, V, 0); else SLW_STEP_CHART(F32, V, 2);                                 \
@@ -2057,6 +2093,47 @@ hipError_t launch_step(const DevMesh &m, hipStream_t st, const FieldDev &f0, dou
         if (e != hipSuccess)
             return e;
         start = m.learned_start;
+    }
+    if (mode == SLW_START_NEIGHBOR && m.chain == 0) {
+        // strategy (c) on the mesh's forest: the roots first, then every
+        // other DOF from its parent's element (two launches, stream order)
+        const int64_t nr = order == 1 ? m.forest_nr1 : m.forest_nr2;
+        const int64_t nl = n_iter - nr;
+        const int32_t *roots = order == 1 ? m.forest_list1 : m.forest_list2;
+        const int32_t *routs = order == 1 ? m.forest_out1 : m.forest_out2;
+        if (!roots)
+            return hipErrorInvalidValue;
+        ForestView fr{roots, routs, nullptr, m.forest_elem};
+        ForestView fl{roots + nr, routs + nr, (order == 1 ? m.forest_parent1 : m.forest_parent2), m.forest_elem};
+        unsigned gr, gl;
+        if (!tiles_for(nr, gr) || !tiles_for(nl, gl))
+            return hipErrorInvalidValue;
+#define SLW_STEP_FOREST(F32, V, NA)                                                                               \
+    do {                                                                                                          \
+        if (nr > 0)                                                                                               \
+            hipLaunchKernelGGL((k_step<F32, V, NA, -3>), dim3(gr), dim3(kBlock), 0, st, mv, f, dt, t_n + dt, scheme, \
+                               mode, start, (const V *)v_in, k, (V *)v_out, outside, 0, out_map, elem_out, nr, stats, \
+                               fr);                                                                               \
+        if (nl > 0)                                                                                               \
+            hipLaunchKernelGGL((k_step<F32, V, NA, -4>), dim3(gl), dim3(kBlock), 0, st, mv, f, dt, t_n + dt, scheme, \
+                               mode, start, (const V *)v_in, k, (V *)v_out, outside, 0, out_map, elem_out, nl, stats, \
+                               fl);                                                                               \
+    } while (0)
+        if (m.coords_f32) {
+            if (vdtype == SLW_F32) {
+                if (order == 1) SLW_STEP_FOREST(true, float, 3); else SLW_STEP_FOREST(true, float, 6);
+            } else {
+                if (order == 1) SLW_STEP_FOREST(true, double, 3); else SLW_STEP_FOREST(true, double, 6);
+            }
+        } else {
+            if (vdtype == SLW_F32) {
+                if (order == 1) SLW_STEP_FOREST(false, float, 3); else SLW_STEP_FOREST(false, float, 6);
+            } else {
+                if (order == 1) SLW_STEP_FOREST(false, double, 3); else SLW_STEP_FOREST(false, double, 6);
+            }
+        }
+#undef SLW_STEP_FOREST
+        return hipGetLastError();
     }
     if (mode == SLW_START_NEIGHBOR) {
         const int L = m.chain;
@@ -2122,11 +2199,11 @@ hipError_t launch_step(const DevMesh &m, hipStream_t st, const FieldDev &f0, dou
         if (mode == SLW_START_PREV)                                                                            \
             hipLaunchKernelGGL((k_step<F32, V, NA, -2>), dim3(g), dim3(kBlock), 0, st, mv, f, dt, t_n + dt, scheme, \
                                mode, start, (const V *)v_in, k, (V *)v_out, outside, (int)write_prev, out_map,   \
-                               elem_out, n_iter, stats);                                                       \
+                               elem_out, n_iter, stats, ForestView());                                         \
         else                                                                                                   \
             hipLaunchKernelGGL((k_step<F32, V, NA>), dim3(g), dim3(kBlock), 0, st, mv, f, dt, t_n + dt, scheme, mode, \
                                start, (const V *)v_in, k, (V *)v_out, outside, (int)write_prev, out_map, elem_out, \
-                               n_iter, stats);                                                                 \
+                               n_iter, stats, ForestView());                                                   \
     }                                                                                                          \
     } while (0)
     if (m.coords_f32) {

@@ -187,7 +187,9 @@ void free_mesh(DevMesh &m)
 {
     void *ptrs[] = {m.geo, m.wrec, m.tri_uf, m.tedge, m.dof_xy, m.qstart, m.vmin, m.dof_user,
                     m.dof_int, m.tri_int, m.prev_elem, m.jump, m.chart_uv, m.chart_node, m.chart_table,
-                    m.chart_qx, m.chart_qy, m.learned_start, m.bnext, m.bprev, m.qt_nodes, m.qt_lists};
+                    m.chart_qx, m.chart_qy, m.learned_start, m.bnext, m.bprev, m.qt_nodes, m.qt_lists,
+                    m.forest_list1, m.forest_out1, m.forest_parent1, m.forest_list2, m.forest_out2,
+                    m.forest_parent2, m.forest_elem};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -631,6 +633,72 @@ slw_status build_mesh(slw_ctx *ctx, const double *xy, int64_t n, const int32_t *
         UP(bn, m.bnext);
         UP(bp, m.bprev);
         m.n_boundary = n_bnd;
+    }
+    {
+        // strategy (c)'s forest: roots = a maximal independent set of the
+        // nodes (greedy in internal order); every other DOF is a child of the
+        // nearest root among the vertices of its incident triangles
+        std::vector<char> is_root(ndof, 0);
+        for (int64_t d = 0; d < n; ++d) {
+            bool taken = false;
+            for (int32_t s2 = sptr[d]; s2 < sptr[d + 1] && !taken; ++s2)
+                for (int k = 0; k < 3; ++k) {
+                    const int32_t v = geo[star[s2].tri].v[k];
+                    if (v != d && is_root[v]) {
+                        taken = true;
+                        break;
+                    }
+                }
+            is_root[d] = !taken;
+        }
+        auto ixy = [&](int64_t d, int c) { return dof_user_xy[2 * dof_u[d] + c]; };
+        auto forest = [&](int64_t nd, std::vector<int32_t> &list, std::vector<int32_t> &outr,
+                          std::vector<int32_t> &par) {
+            list.clear();
+            par.clear();
+            for (int64_t d = 0; d < nd; ++d)
+                if (is_root[d])
+                    list.push_back((int32_t)d);
+            const int64_t nr = (int64_t)list.size();
+            for (int64_t d = 0; d < nd; ++d) {
+                if (is_root[d])
+                    continue;
+                int32_t best = -1;
+                double bd = 0.0;
+                for (int32_t s2 = sptr[d]; s2 < sptr[d + 1]; ++s2)
+                    for (int k = 0; k < 3; ++k) {
+                        const int32_t v = geo[star[s2].tri].v[k];
+                        if (v == d || !is_root[v])
+                            continue;
+                        const double ex = ixy(v, 0) - ixy(d, 0), ey = ixy(v, 1) - ixy(d, 1);
+                        const double dd = ex * ex + ey * ey;
+                        if (best < 0 || dd < bd) {
+                            best = v;
+                            bd = dd;
+                        }
+                    }
+                list.push_back((int32_t)d);
+                par.push_back(best);
+            }
+            outr.resize(list.size());
+            const bool user_rows = reorder && !(flags & SLW_INTERNAL_ORDER);
+            for (size_t i = 0; i < list.size(); ++i)
+                outr[i] = user_rows ? dof_u[list[i]] : list[i];
+            return nr;
+        };
+        std::vector<int32_t> list, outr, par;
+        m.forest_nr1 = forest(n, list, outr, par);
+        UP(list, m.forest_list1);
+        UP(outr, m.forest_out1);
+        UP(par, m.forest_parent1);
+        if (p2) {
+            m.forest_nr2 = forest(ndof, list, outr, par);
+            UP(list, m.forest_list2);
+            UP(outr, m.forest_out2);
+            UP(par, m.forest_parent2);
+        }
+        std::vector<int32_t> fe(ndof, -1);
+        UP(fe, m.forest_elem);
     }
 #undef UP
     m.device_bytes = bytes;

@@ -1,12 +1,13 @@
 """Strategy (c) of Section 3 (start from the element found for a
-neighbouring node, along Morton chains): the oracle's values, the steered
-start's bits, every chain length, ragged tails; and shorter walks than
-strategy (a) once the Courant number is large."""
+neighbouring node: on the mesh's depth-one forest, or along Morton
+chains): the oracle's values and elements, the steered start's bits, every
+forest, ragged tails, boundary data; and shorter walks than strategy (a) once
+the Courant number is large."""
 import numpy as np
 import pytest
 
 from paper_2104_09189_amd import inputs as I
-from gpu_util import ctx as _ctx, dev, host, rel_err
+from gpu_util import check_elements_near, ctx as _ctx, dev, host, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -31,7 +32,7 @@ def test_neighbor_start_same_bits_every_chain(S, C, orc, flags):
     v0 = np.stack([I.gaussian_hill(xy), xy[:, 0] * xy[:, 1]], axis=1)[perm].astype(np.float32)
     ref, st_a = mesh.step(fld, 0.1, dt, S.SLW_RK2, dev(v0), stats=True)
     ref = host(ref).copy()
-    for L in (2, 4, 8, 16):
+    for L in (0, 2, 4, 8, 16):
         mesh.set_chain(L)
         v, st = mesh.step(fld, 0.1, dt, S.SLW_RK2, dev(v0), start_mode=S.START_NEIGHBOR, stats=True)
         assert np.array_equal(host(v), ref), L
@@ -48,12 +49,56 @@ def test_neighbor_start_p2_fp64_and_outside(S, C, orc):
     mesh = S.Mesh(C, xy, tri, S.P2)
     fld = I.constant(-0.25, 0.15)
     v0 = I.gaussian_hill(p2.xy)[:, None]
-    mesh.set_chain(8)
-    v = host(mesh.step(fld, 0.0, 0.2, S.SLW_EULER, dev(v0), order=2, start_mode=S.START_NEIGHBOR,
-                       outside_value=3.0))
-    ref, _, _, _ = orc.sl_step(xy, tri, v0, fld, 0.0, 0.2, I.SCHEME_EULER, order=2, p2=p2, outside_value=3.0)
-    assert rel_err(v, ref, 1.0) < 1e-12
-    assert (v == 3.0).sum() > 50
+    ref, _, r, _ = orc.sl_step(xy, tri, v0, fld, 0.0, 0.2, I.SCHEME_EULER, order=2, p2=p2, outside_value=3.0)
+    for L in (8, 0):
+        mesh.set_chain(L)
+        e = dev(np.zeros(mesh.n_dofs, np.int32))
+        v = host(mesh.step(fld, 0.0, 0.2, S.SLW_EULER, dev(v0), order=2, start_mode=S.START_NEIGHBOR,
+                           outside_value=3.0, elem=e))
+        assert rel_err(v, ref, 1.0) < 1e-12
+        assert (v == 3.0).sum() > 50
+        assert np.array_equal(host(e), r)        # constant field: the same feet on both sides
+
+
+def test_neighbor_tree_boundary_data_same_bits_as_steered(S, C):
+    xy, tri = I.jittered_grid(45, 704)
+    mesh = S.Mesh(C, xy, tri)
+    mesh.set_boundary(S.BC_AFFINE, (0.5, 0.25, -0.75, 0.1))
+    fld = I.constant(0.3, -0.2)
+    v0 = dev(I.gaussian_hill(xy)[:, None])
+    a = host(mesh.step(fld, 0.2, 0.25, S.SLW_RK2, v0)).copy()
+    mesh.set_chain(0)
+    c = host(mesh.step(fld, 0.2, 0.25, S.SLW_RK2, v0, start_mode=S.START_NEIGHBOR))
+    assert np.array_equal(a, c)
+    mesh.set_chain(2)
+    with pytest.raises(S.SlwError):
+        mesh.step(fld, 0.2, 0.25, S.SLW_RK2, v0, start_mode=S.START_NEIGHBOR)
+
+
+@pytest.mark.parametrize("alpha", [5.0, 50.0])
+def test_neighbor_tree_graded_full_against_oracle(S, C, orc, alpha):
+    """The graded mesh (2,002,225 nodes), RK2, 16 FP32 fields, the benchmark's
+    launch: every element of a strategy (c) step on the mesh forest (roots,
+    then the other nodes from an adjacent root's element) against the
+    oracle, and fewer walk steps than strategy (a)."""
+    w = I.graded_swirl(alpha=alpha)
+    mesh = S.Mesh(C, w.xy, w.tri, S.INTERNAL_ORDER)
+    perm = mesh.dof_order()
+    v0 = w.v0.astype(np.float32)
+    vin = dev(v0[perm])
+    t_n = 7 * w.dt
+    e = dev(np.zeros(mesh.n_nodes, np.int32))
+    v, st = mesh.step(w.field, t_n, w.dt, w.scheme, vin, start_mode=S.START_NEIGHBOR, elem=e, stats=True)
+    _, st_a = mesh.step(w.field, t_n, w.dt, w.scheme, vin, stats=True)
+    assert st["walk_steps"] < (0.4 if alpha > 20 else 0.6) * st_a["walk_steps"]
+    q = orc.feet(w.xy, w.field, t_n + w.dt, w.dt, w.scheme)
+    r, b = orc.locate(w.xy, w.tri, q)
+    e_user = np.empty(mesh.n_nodes, np.int32)
+    e_user[perm] = host(e)
+    check_elements_near(w.xy, w.tri, q, r, e_user, 64 * 2.0 ** -52)
+    sample = np.random.default_rng(91).choice(mesh.n_nodes, 20000, replace=False)
+    ref = orc.interp(1, w.tri, r[perm[sample]], b[perm[sample]], v0.astype(np.float64), w.xy.shape[0])
+    assert rel_err(host(v)[sample], ref, np.abs(v0).max()) < 1e-5
 
 
 def test_neighbor_start_rejected_by_locate_feet(S, C):
