@@ -135,8 +135,9 @@ def measure(mesh, w, v0, steps, warmup, start_mode):
     v_b = torch.empty_like(v_a)
     # walk statistics of one step (the counting variant of the kernel)
     t_stats = 0.0
-    if start_mode == S.START_PREV:
-        # strategy (b): the first step starts as (a); measure the one after it
+    if start_mode in (S.START_PREV, S.START_HYBRID):
+        # strategy (b) and the hybrid: the first step has no previous
+        # elements; measure the one after it
         mesh.step(w.field, 0.0, w.dt, w.scheme, v_a, v_b, start_mode=start_mode)
         t_stats = w.dt
     _, st = mesh.step(w.field, t_stats, w.dt, w.scheme, v_a, v_b, start_mode=start_mode, stats=True)
@@ -403,9 +404,9 @@ def wave_walks(mesh, w, t_n, mode) -> dict:
     kernel's wavefronts see them: 64 consecutive internal-order DOFs per
     wavefront, each waiting for its longest walk."""
     from paper_2104_09189_amd import slwalk as S
-    if mode == S.START_NEIGHBOR:
-        # the step's own statistics (slw_locate_feet has no forest): the
-        # per-foot lengths are not available, only the mean and maximum
+    if mode in (S.START_NEIGHBOR, S.START_HYBRID):
+        # the step's own statistics (slw_locate_feet has neither the forest
+        # nor the hybrid choice): the mean and maximum, no per-foot lengths
         _, st = mesh.step(w.field, t_n, w.dt, w.scheme, torch_zeros_like_values(mesh), start_mode=mode, stats=True)
         return {"mean": st["walk_steps"] / max(st["feet"], 1), "mean_wavefront_max": None, "p99": None,
                 "max": st["max_steps"]}
@@ -418,7 +419,7 @@ def wave_walks(mesh, w, t_n, mode) -> dict:
     return _walk_histogram(st)
 
 
-def measure_courant_range(mesh, w, v0, steps=20, warmup=3, alphas=(1.0, 5.0, 20.0, 50.0), chart_g=2048):
+def measure_courant_range(mesh, w, v0, steps=20, warmup=3, alphas=(1.0, 5.0, 20.0, 50.0, 100.0), chart_g=2048):
     """The graded mesh across its Courant range: strategy (a) (steered
     incident start), strategy (b) (previous element) and the exact chart
     start, each with ms per step, kernel time, HBM-roofline fraction and the
@@ -436,14 +437,25 @@ def measure_courant_range(mesh, w, v0, steps=20, warmup=3, alphas=(1.0, 5.0, 20.
         wa = dataclasses.replace(w, dt=dt)
         line = {"dt": dt}
         for name, mode in (("a_steered", S.START_STEERED), ("b_previous", S.START_PREV),
-                           ("c_tree", S.START_NEIGHBOR), ("chart_exact", S.START_CHART)):
+                           ("c_forest", S.START_NEIGHBOR), ("chart_exact", S.START_CHART),
+                           ("hybrid", S.START_HYBRID)):
+            tuned = None
+            if mode == S.START_HYBRID:
+                # the threshold of the per-foot choice, picked by the autotuner
+                # (previous elements from the step before)
+                mesh.step(wa.field, 6 * dt, dt, wa.scheme, v0, start_mode=mode)
+                tuned = mesh.autotune_step(wa.field, 7 * dt, dt, wa.scheme, v0, start_mode=mode)
             r = measure(mesh, wa, v0, steps, warmup, mode)
-            ww = wave_walks(mesh, wa, 7 * dt, mode)
+            # walk lengths of the step ending near t = 1/4 (the swirl's time
+            # factor cos(pi t) is 0.7 there; it vanishes at t = 1/2)
+            ww = wave_walks(mesh, wa, max(round(0.25 / dt) - 1, 0) * dt, mode)
             line[name] = {"ms_per_step": r["ms_per_step"], "kernel_ms": r["kernel_ms"],
                           "feet_per_s": mesh.n_nodes / (r["ms_per_step"] * 1e-3),
                           "roofline_frac": abytes / (r["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
                           "mean_walk_steps": ww["mean"], "mean_wavefront_max": ww["mean_wavefront_max"],
                           "p99": ww["p99"], "max": ww["max"]}
+            if tuned is not None:
+                line[name]["tuned_hybrid_far"] = tuned[0]
         out[f"alpha_{alpha:g}"] = line
     return out
 

@@ -113,9 +113,14 @@ enum {
     SLW_START_NEIGHBOR = 6, /* strategy (c): the element found for a neighbouring node, its
                               parent in a spanning forest of the internal-order nodes
                               (slw_step only; see slw_mesh_set_chain) */
-    SLW_START_LEARNED_INDEX = 7 /* a learned index: the network's chart cell as the guess of
+    SLW_START_LEARNED_INDEX = 7, /* a learned index: the network's chart cell as the guess of
                               galloping searches in the chart's quantile tables, which end
                               in the foot's own cell (the start of SLW_START_CHART) */
+    SLW_START_HYBRID = 8   /* chosen per foot from how far it moved (slw_step only; see
+                              slw_mesh_set_hybrid): the previous element (as SLW_START_PREV)
+                              when the foot is in it or near it, else the foot's chart cell
+                              (as SLW_START_CHART) when the mesh has a chart, else the
+                              steered start; keeps the previous elements as SLW_START_PREV */
 };
 /* slw_mesh_upload flags */
 #define SLW_COORDS_F32 0x1u     /* store coordinates as float (FP32 walk, FP64/exact fallback) */
@@ -254,6 +259,18 @@ slw_status slw_mesh_set_boundary(slw_mesh *mesh, int kind, const double *p_h);
  *     SLW_E_UNSUPPORTED).
  * Results never depend on the forest. */
 slw_status slw_mesh_set_chain(slw_mesh *mesh, int length);
+/* The per-foot choice of SLW_START_HYBRID, after the hybrid idea that closes
+ * the numerical section (Section 4) of the paper: the start is chosen from
+ * the local dynamics, i.e. from how far the foot moved since the previous
+ * step.  The foot is first tested against the element found for the DOF at
+ * the previous SLW_START_PREV / SLW_START_HYBRID step; if it lies outside,
+ * theta_min, its smallest barycentric coordinate there, measures how far
+ * (about -theta_min heights of that element beyond its nearest side).  With
+ * theta_min > -far the walk continues from the previous element; otherwise
+ * (and without a previous element) it starts from the foot's chart cell
+ * when slw_chart_build was called, else from the steered start.  far > 0;
+ * default 8.  Results never depend on it. */
+slw_status slw_mesh_set_hybrid(slw_mesh *mesh, float far);
 
 /* General point location, the analogue of the paper's [I, B] =
  * pointLocationBW(TBW, Q, s): m query points q (m x 2, mesh coordinate type)
@@ -292,6 +309,29 @@ slw_status slw_interpolate(slw_mesh *mesh, int order, const int32_t *elem, const
 slw_status slw_step(slw_mesh *mesh, const slw_field *field, double t_n, double dt, int scheme, int order,
                     int start_mode, const int32_t *start, const void *v_in, int vdtype, int k,
                     void *v_out, double outside_value, int32_t *elem, slw_stats *stats_h);
+
+/* Autotuner of slw_step's schedule: for the given step (arguments as
+ * slw_step) it times every candidate value of the knob that matters for
+ * start_mode -- the lane schedule of slw_mesh_set_repack (1, 2, 4, 8 feet
+ * per lane) for the steered, given, fixed, previous, chart and learned
+ * starts; the threshold of slw_mesh_set_hybrid (2 ... 64) for
+ * SLW_START_HYBRID; the forest or chain length of slw_mesh_set_chain (0, 2,
+ * 4, 8, 16) for SLW_START_NEIGHBOR -- each over five launches (the median),
+ * keeps only candidates whose step is bit-identical to the one of the
+ * mesh's current setting, applies the fastest to the mesh and records it in
+ * the JSON file cache_path (nullable) under a signature of the step (size,
+ * types, k, order, start mode, scheme, and the walk-length regime: the
+ * mean walk of strategy (a) on this step, in powers of two); a later call
+ * with a cached signature applies the
+ * cached value without timing.  Every candidate starts from the mesh's
+ * current previous elements (SLW_START_PREV, SLW_START_HYBRID), which are
+ * restored afterwards; the caller's v_in is only read.  Allocates a private
+ * output buffer; synchronous.  value_out / ms_out (nullable): the value
+ * chosen and its median time per step (ms; the cached time when the cache
+ * answered). */
+slw_status slw_step_autotune(slw_mesh *mesh, const slw_field *field, double t_n, double dt, int scheme, int order,
+                             int start_mode, const int32_t *start, const void *v_in, int vdtype, int k,
+                             const char *cache_path, double *value_out, double *ms_out);
 
 /* slw_step for callers that cannot allocate device memory: code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same

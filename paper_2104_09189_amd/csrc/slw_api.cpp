@@ -1,6 +1,8 @@
 // C-ABI entry points: argument checks, context/stream handling, statistics.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
@@ -128,7 +130,7 @@ slw_status step_impl(slw_mesh *mesh, const slw_field *field, double t_n, double 
         return set_error(SLW_E_ARG, w + ": unknown scheme");
     if (vdtype != SLW_F64 && vdtype != SLW_F32)
         return set_error(SLW_E_ARG, w + ": unknown vdtype");
-    if (start_mode < SLW_START_STEERED || start_mode > SLW_START_LEARNED_INDEX)
+    if (start_mode < SLW_START_STEERED || start_mode > SLW_START_HYBRID)
         return set_error(SLW_E_ARG, w + ": unknown start mode");
     if ((start_mode == SLW_START_GIVEN || start_mode == SLW_START_FIXED) && !start)
         return set_error(SLW_E_ARG, w + ": start array required for this start mode");
@@ -434,6 +436,16 @@ slw_status slw_mesh_set_boundary(slw_mesh *mesh, int kind, const double *p_h)
     mesh->m.bc_kind = kind;
     for (int i = 0; i < 4; ++i)
         mesh->m.bc_p[i] = kind == SLW_BC_NONE ? 0.0 : p_h[i];
+    return SLW_OK;
+}
+
+slw_status slw_mesh_set_hybrid(slw_mesh *mesh, float far)
+{
+    if (!mesh)
+        return set_error(SLW_E_ARG, "mesh is NULL");
+    if (!(far > 0.0f) || !std::isfinite(far))
+        return set_error(SLW_E_ARG, "slw_mesh_set_hybrid: far must be a positive finite number");
+    mesh->m.hybrid_far = far;
     return SLW_OK;
 }
 
@@ -1099,5 +1111,271 @@ extern "C" slw_status slw_batch_autotune(slw_batch *b, int scheme, const char *c
         *schedule_out = b->schedule;
     if (block_out)
         *block_out = b->block;
+    return SLW_OK;
+}
+
+// ===========================================================================
+// autotuning of slw_step's schedule knobs
+
+namespace {
+
+// value of "key" in the cache entry of signature sig (false if absent)
+bool cache_lookup_num(const char *path, const std::string &sig, const char *key, double &val)
+{
+    std::ifstream f(path);
+    if (!f)
+        return false;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string txt = ss.str();
+    const size_t at = txt.find("\"" + sig + "\"");
+    if (at == std::string::npos)
+        return false;
+    const size_t end = txt.find('}', at);
+    const size_t k = txt.find(std::string("\"") + key + "\":", at);
+    if (k == std::string::npos || k > end)
+        return false;
+    val = std::atof(txt.c_str() + k + std::strlen(key) + 3);
+    return true;
+}
+
+// replaces or adds the entry "sig": {body} (body without braces)
+void cache_store_entry(const char *path, const std::string &sig, const std::string &body)
+{
+    std::string txt;
+    {
+        std::ifstream f(path);
+        if (f) {
+            std::stringstream ss;
+            ss << f.rdbuf();
+            txt = ss.str();
+        }
+    }
+    const std::string entry = "\"" + sig + "\": {" + body + "}";
+    const size_t at = txt.find("\"" + sig + "\"");
+    if (at != std::string::npos) {
+        const size_t end = txt.find('}', at);
+        txt.replace(at, end + 1 - at, entry);
+    } else {
+        const size_t close = txt.rfind('}');
+        if (txt.empty() || close == std::string::npos)
+            txt = "{\n  " + entry + "\n}\n";
+        else {
+            const bool empty = txt.find('"') == std::string::npos;
+            txt.insert(close, (empty ? "  " : ",\n  ") + entry + "\n");
+        }
+    }
+    std::ofstream f(path);
+    f << txt;
+}
+
+// the knob a start mode is tuned on, and its candidate values
+const char *knob_name(int mode)
+{
+    if (mode == SLW_START_HYBRID)
+        return "hybrid_far";
+    if (mode == SLW_START_NEIGHBOR)
+        return "chain";
+    return "feet_per_lane";
+}
+
+std::vector<double> knob_values(int mode, bool bc)
+{
+    if (mode == SLW_START_HYBRID)
+        return {2, 4, 8, 16, 32, 64};
+    if (mode == SLW_START_NEIGHBOR)
+        return bc ? std::vector<double>{0} : std::vector<double>{0, 2, 4, 8, 16};
+    if (mode == SLW_START_LEARNED_INDEX || bc)
+        return {1};  // one-foot-per-lane kernels only
+    return {1, 2, 4, 8};
+}
+
+double knob_get(const DevMesh &m, int mode)
+{
+    if (mode == SLW_START_HYBRID)
+        return m.hybrid_far;
+    if (mode == SLW_START_NEIGHBOR)
+        return m.chain;
+    return m.repack ? m.repack : 1;
+}
+
+void knob_set(DevMesh &m, int mode, double v)
+{
+    if (mode == SLW_START_HYBRID)
+        m.hybrid_far = (float)v;
+    else if (mode == SLW_START_NEIGHBOR)
+        m.chain = (int)v;
+    else
+        m.repack = (int)v <= 1 ? 0 : (int)v;
+}
+
+}  // namespace
+
+extern "C" slw_status slw_step_autotune(slw_mesh *mesh, const slw_field *field, double t_n, double dt, int scheme,
+                                        int order, int start_mode, const int32_t *start, const void *v_in,
+                                        int vdtype, int k, const char *cache_path, double *value_out,
+                                        double *ms_out)
+{
+    if (!mesh || !v_in)
+        return set_error(SLW_E_ARG, "slw_step_autotune: mesh or v_in is NULL");
+    DevMesh &m = mesh->m;
+    slw_ctx *ctx = mesh->ctx;
+    DeviceGuard g(ctx->device);
+    const int64_t rows = order == 1 ? m.n_nodes : m.n_dofs;
+    const size_t vsz = vdtype == SLW_F64 ? 8 : 4;
+    const size_t bytes = (size_t)rows * (size_t)(k > 0 ? k : 1) * vsz;
+    const double saved = knob_get(m, start_mode);
+    const bool keeps_prev = start_mode == SLW_START_PREV || start_mode == SLW_START_HYBRID;
+    void *vout = nullptr;
+    int32_t *prev0 = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    std::vector<char> ref_h, out_h;
+    slw_stats st0;
+    slw_status st = SLW_OK;
+    auto release = [&]() {
+        if (vout)
+            (void)hipFree(vout);
+        if (prev0)
+            (void)hipFree(prev0);
+        if (e0)
+            (void)hipEventDestroy(e0);
+        if (e1)
+            (void)hipEventDestroy(e1);
+    };
+    if (hipMalloc(&vout, bytes) != hipSuccess ||
+        (keeps_prev && hipMalloc((void **)&prev0, (size_t)m.n_dofs * sizeof(int32_t)) != hipSuccess)) {
+        release();
+        return set_error(SLW_E_NOMEM, "slw_step_autotune: workspace");
+    }
+    st = hip_check(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    if (st == SLW_OK && keeps_prev)  // the caller's previous elements: every candidate starts from them
+        st = hip_check(hipMemcpy(prev0, m.prev_elem, (size_t)m.n_dofs * sizeof(int32_t), hipMemcpyDeviceToDevice),
+                       "save previous elements");
+    if (st == SLW_OK)
+        st = hip_check(hipEventCreate(&e0), "hipEventCreate");
+    if (st == SLW_OK)
+        st = hip_check(hipEventCreate(&e1), "hipEventCreate");
+    auto restore_prev = [&]() -> slw_status {
+        if (!keeps_prev)
+            return SLW_OK;
+        return hip_check(hipMemcpyAsync(m.prev_elem, prev0, (size_t)m.n_dofs * sizeof(int32_t),
+                                        hipMemcpyDeviceToDevice, ctx->stream),
+                         "restore previous elements");
+    };
+    // the regime of the step for the cache signature: the walk lengths of
+    // strategy (a) (the feet's displacement in cells), whatever the knobs
+    if (st == SLW_OK)
+        st = step_impl(mesh, field, t_n, dt, scheme, order, SLW_START_STEERED, nullptr, v_in, vdtype, k, vout, 0.0,
+                       nullptr, &st0, StepScratch(), "slw_step_autotune");
+    // the reference: the mesh's current setting
+    if (st == SLW_OK)
+        st = restore_prev();
+    if (st == SLW_OK)
+        st = step_impl(mesh, field, t_n, dt, scheme, order, start_mode, start, v_in, vdtype, k, vout, 0.0, nullptr,
+                       nullptr, StepScratch(), "slw_step_autotune");
+    if (st == SLW_OK) {
+        ref_h.resize(bytes);
+        st = hip_check(hipMemcpy(ref_h.data(), vout, bytes, hipMemcpyDeviceToHost), "copy reference");
+    }
+    std::string sig;
+    if (st == SLW_OK) {
+        int nb = 0, wb = 0;
+        while (((int64_t)1 << (nb + 1)) <= rows)
+            ++nb;
+        const double mean = st0.feet ? (double)st0.walk_steps / (double)st0.feet : 0.0;
+        while ((double)((int64_t)1 << (wb + 1)) <= 1.0 + mean)
+            ++wb;
+        std::ostringstream os;
+        os << "step_dofs2^" << nb << "_c" << (m.coords_f32 ? "f32" : "f64") << "_v" << (vdtype == SLW_F32 ? "f32" : "f64")
+           << "_k" << k << "_o" << order << "_mode" << start_mode << "_s" << scheme << "_walk2^" << wb
+           << (m.bc_kind ? "_bc" : "");
+        sig = os.str();
+        double cached = 0.0, cms = 0.0;
+        if (cache_path && cache_lookup_num(cache_path, sig, knob_name(start_mode), cached)) {
+            (void)cache_lookup_num(cache_path, sig, "ms", cms);
+            const std::vector<double> ok = knob_values(start_mode, m.bc_kind != 0);
+            bool valid = false;
+            for (double v : ok)
+                valid = valid || v == cached;
+            if (valid) {
+                st = restore_prev();
+                if (st == SLW_OK)
+                    st = hip_check(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+                release();
+                if (st != SLW_OK)
+                    return st;
+                knob_set(m, start_mode, cached);
+                if (value_out)
+                    *value_out = cached;
+                if (ms_out)
+                    *ms_out = cms;
+                return SLW_OK;
+            }
+        }
+    }
+    double best_v = saved, best_ms = 1e300;
+    for (double v : knob_values(start_mode, m.bc_kind != 0)) {
+        if (st != SLW_OK)
+            break;
+        knob_set(m, start_mode, v);
+        // parity guard: the candidate's step from the same state must give
+        // the reference's bits
+        st = restore_prev();
+        if (st == SLW_OK)
+            st = step_impl(mesh, field, t_n, dt, scheme, order, start_mode, start, v_in, vdtype, k, vout, 0.0,
+                           nullptr, nullptr, StepScratch(), "slw_step_autotune");
+        if (st == SLW_OK) {
+            out_h.resize(bytes);
+            st = hip_check(hipMemcpy(out_h.data(), vout, bytes, hipMemcpyDeviceToHost), "copy candidate");
+        }
+        if (st != SLW_OK)
+            break;
+        if (std::memcmp(out_h.data(), ref_h.data(), bytes) != 0)
+            continue;  // never chosen
+        // timing: five launches, each from the caller's previous elements; the median
+        std::vector<float> ts;
+        for (int r = 0; r < 5 && st == SLW_OK; ++r) {
+            st = restore_prev();
+            if (st == SLW_OK)
+                st = hip_check(hipEventRecord(e0, ctx->stream), "event");
+            if (st == SLW_OK)
+                st = step_impl(mesh, field, t_n, dt, scheme, order, start_mode, start, v_in, vdtype, k, vout, 0.0,
+                               nullptr, nullptr, StepScratch(), "slw_step_autotune");
+            if (st == SLW_OK)
+                st = hip_check(hipEventRecord(e1, ctx->stream), "event");
+            if (st == SLW_OK)
+                st = hip_check(hipEventSynchronize(e1), "event sync");
+            float ms = 0.f;
+            if (st == SLW_OK)
+                st = hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+            ts.push_back(ms);
+        }
+        if (st != SLW_OK)
+            break;
+        std::sort(ts.begin(), ts.end());
+        if (ts[2] < best_ms) {
+            best_ms = ts[2];
+            best_v = v;
+        }
+    }
+    // the caller's previous elements are left as they were
+    slw_status st2 = restore_prev();
+    if (st2 == SLW_OK)
+        st2 = hip_check(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    release();
+    knob_set(m, start_mode, st == SLW_OK ? best_v : saved);
+    if (st != SLW_OK)
+        return st;
+    if (st2 != SLW_OK)
+        return st2;
+    if (cache_path) {
+        std::ostringstream body;
+        body << "\"" << knob_name(start_mode) << "\": " << best_v << ", \"ms\": " << best_ms;
+        cache_store_entry(cache_path, sig, body.str());
+    }
+    if (value_out)
+        *value_out = best_v;
+    if (ms_out)
+        *ms_out = best_ms;
     return SLW_OK;
 }

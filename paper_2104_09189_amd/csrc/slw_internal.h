@@ -98,6 +98,7 @@ struct DevMesh {
     int64_t device_bytes = 0;
     int32_t step_cap = 4096;
     int32_t hard_limit = 1 << 22;
+    float hybrid_far = 8.0f;  // SLW_START_HYBRID: feet farther than this many heights of their previous element use the chart
     int repack = 0;  // step kernel: 0 one foot per lane; 2, 4, 8: chunks of 64 x repack feet per wavefront
     int chain = 0;   // strategy (c): 0 the mesh forest below; 2, 4, 8, 16 Morton chains of that length per lane
     // strategy (c)'s forest (depth one): roots = a maximal independent set of
@@ -244,6 +245,7 @@ struct MeshView {
     double bb[4];
     FilterConst fc;
     int32_t step_cap, hard_limit;
+    float hybrid_far;
     // variable step at the boundary (bc_kind 0: off)
     const int32_t *bnext, *bprev;
     int64_t n_boundary;

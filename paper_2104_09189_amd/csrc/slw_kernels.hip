@@ -148,6 +148,7 @@ MeshView view_of(const DevMesh &m)
     v.fc = m.fc;
     v.step_cap = m.step_cap;
     v.hard_limit = m.hard_limit;
+    v.hybrid_far = m.hybrid_far;
     v.bnext = m.bnext;
     v.bprev = m.bprev;
     v.n_boundary = m.n_boundary;
@@ -578,6 +579,38 @@ __device__ inline WalkResult<typename CT<F32>::R> walk_end(const MeshView &mv, i
         return w;
     }
     return finish_walk_rec<F32>(mv, j, r, zmask, steps, flags, qx, qy);
+}
+
+// The first test of a walk on a likely start j (the previous element):
+// 1 = the foot is in j (res holds the located result, tie rule and weights
+// done), 0 = it is not; then theta_min is the smallest barycentric
+// coordinate of the foot in j (float, from the filter's determinants): the
+// foot lies about -theta_min heights of j beyond its nearest side.
+template <bool F32>
+__device__ inline int first_test(const MeshView &mv, int32_t j, typename CT<F32>::R qx, typename CT<F32>::R qy,
+                                 float &theta_min, WalkResult<typename CT<F32>::R> &res, Counters &c)
+{
+    const float qfx = F32 ? (float)qx : (float)((double)qx - mv.fc.cx);
+    const float qfy = F32 ? (float)qy : (float)((double)qy - mv.fc.cy);
+    const float4 p01 = ((const float4 *)(mv.geo + j))[0];
+    const float2 p2 = ((const float2 *)(mv.geo + j))[2];
+    const int4 tv = tri_verts(mv, j);  // {nb[2], v[0], v[1], v[2]}
+    const float2 pj[3] = {make_float2(p01.x, p01.y), make_float2(p01.z, p01.w), p2};
+    float o[3];
+    int s[3];
+    Counters c0;
+    edge_signs<F32>(mv, j, pj, qfx, qfy, qx, qy, o, s, c0);
+    if (s[0] >= 0 && s[1] >= 0 && s[2] >= 0) {
+        c.exact += c0.exact;
+        c.fp64 += c0.fp64;
+        const int zm = (int)(s[0] == 0) | ((int)(s[1] == 0) << 1) | ((int)(s[2] == 0) << 2);
+        const int32_t nbz = zm == 4 ? tv.x : ((zm == 1 || zm == 2) ? mv.geo[j].nb[zm >> 1] : -1);
+        res = finish_walk<F32>(mv, j, pj, nbz, zm, 0, 0, qx, qy, true, tv);
+        return 1;
+    }
+    const float sum = o[0] + o[1] + o[2];  // twice the area (> 0)
+    theta_min = fminf(fminf(o[0], o[1]), o[2]) / sum;
+    return 0;
 }
 
 // Barycentric walk of Section 2.2 from triangle j to the foot q, then the tie
@@ -1376,6 +1409,8 @@ __device__ inline void step_wave(const MeshView &mv, const FieldDev &f, double d
             // adjacent to it in the mesh) by the roots' launch
             p = fv.parent[pos];
             sid = p >= 0 ? fv.elem[p] : -1;
+        } else if constexpr (KIND == -5) {
+            sid = load_stream(mv.prev + d);  // the previous step's element (strategy (b))
         } else if constexpr (KIND < 0 && KIND != -3) {
             const int64_t api = (mode == SLW_START_GIVEN && !mv.internal_order) ? mv.dof_user[d] : d;
             sid = start_id(mv, d, api, mode, start);
@@ -1403,7 +1438,32 @@ __device__ inline void step_wave(const MeshView &mv, const FieldDev &f, double d
         jc = chart_start<F32, KIND>(mv, run, d, x, qx, qy, t_np1);
     if (valid) {
         WalkResult<R> w = outside_result<R>(0, 0);
-        if (run) {
+        if constexpr (KIND == -5) {
+            // Hybrid start, chosen per foot from how far it moved: the
+            // previous element first (strategy (b)); a foot inside it is
+            // located at once.  A foot less than hybrid_far heights of that
+            // element beyond it walks on from there; a farther one, or one
+            // without a previous element, starts from its chart cell when the
+            // mesh has a chart (the nearer of that cell's triangle and the
+            // steered start), else from the steered start (strategy (a)).
+            if (run) {
+                bool done = false;
+                int32_t j0 = -1;
+                if (sid >= 0) {
+                    float tmin = 0.f;
+                    done = first_test<F32>(mv, sid, qx, qy, tmin, w, ls.c) != 0;
+                    if (!done && tmin > -mv.hybrid_far)
+                        j0 = sid;
+                }
+                if (!done) {
+                    if (j0 < 0)
+                        j0 = mv.chart_table ? chart_start<F32, 0>(mv, true, d, x, qx, qy, t_np1)
+                                            : quadrant_start(mv.qstart[d], (float)(qx - x.x), (float)(qy - x.y));
+                    w = walk<F32>(mv, j0, qx, qy, (uint32_t)d * 2654435761u, ls.c);
+                }
+            }
+            store_stream(mv.prev + d, w.elem);
+        } else if (run) {
             int32_t j0 = jc;
             if constexpr (KIND == -3 || KIND == -4)
                 j0 = sid >= 0 ? sid : quadrant_start(mv.qstart[d], (float)(qx - x.x), (float)(qy - x.y));
@@ -2093,6 +2153,27 @@ hipError_t launch_step(const DevMesh &m, hipStream_t st, const FieldDev &f0, dou
         if (e != hipSuccess)
             return e;
         start = m.learned_start;
+    }
+    if (mode == SLW_START_HYBRID) {
+#define SLW_STEP_HYB(F32, V, NA)                                                                                  \
+    hipLaunchKernelGGL((k_step<F32, V, NA, -5>), dim3(g), dim3(kBlock), 0, st, mv, f, dt, t_n + dt, scheme, mode, \
+                       start, (const V *)v_in, k, (V *)v_out, outside, 0, out_map, elem_out, n_iter, stats,        \
+                       ForestView())
+        if (m.coords_f32) {
+            if (vdtype == SLW_F32) {
+                if (order == 1) SLW_STEP_HYB(true, float, 3); else SLW_STEP_HYB(true, float, 6);
+            } else {
+                if (order == 1) SLW_STEP_HYB(true, double, 3); else SLW_STEP_HYB(true, double, 6);
+            }
+        } else {
+            if (vdtype == SLW_F32) {
+                if (order == 1) SLW_STEP_HYB(false, float, 3); else SLW_STEP_HYB(false, float, 6);
+            } else {
+                if (order == 1) SLW_STEP_HYB(false, double, 3); else SLW_STEP_HYB(false, double, 6);
+            }
+        }
+#undef SLW_STEP_HYB
+        return hipGetLastError();
     }
     if (mode == SLW_START_NEIGHBOR && m.chain == 0) {
         // strategy (c) on the mesh's forest: the roots first, then every

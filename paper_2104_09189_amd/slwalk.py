@@ -34,6 +34,7 @@ SLW_F64, SLW_F32 = 0, 1
 SLW_EULER, SLW_RK2 = 0, 1
 START_STEERED, START_GIVEN, START_PREV, START_FIXED, START_LEARNED, START_CHART, START_NEIGHBOR = 0, 1, 2, 3, 4, 5, 6
 START_LEARNED_INDEX = 7
+START_HYBRID = 8
 BC_NONE, BC_CONSTANT, BC_AFFINE = 0, 1, 2
 COORDS_F32, P2, NO_REORDER, INTERNAL_ORDER, HILBERT = 0x1, 0x2, 0x4, 0x8, 0x10
 FEET_IN = 0x1
@@ -103,6 +104,7 @@ _sig("slw_mesh_set_repack", ctypes.c_int, [_vp, ctypes.c_int])
 _sig("slw_mesh_set_neighbour_codes", ctypes.c_int, [_vp, ctypes.c_int])
 _sig("slw_walk_codes_host", ctypes.c_int, [_vp, _i64, ctypes.c_int, _vp])
 _sig("slw_mesh_set_chain", ctypes.c_int, [_vp, ctypes.c_int])
+_sig("slw_mesh_set_hybrid", ctypes.c_int, [_vp, ctypes.c_float])
 _sig("slw_mesh_set_boundary", ctypes.c_int, [_vp, ctypes.c_int, _vp])
 _sig("slw_locate", ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, _vp, _vp])
 _sig("slw_locate_feet", ctypes.c_int, [_vp, ctypes.POINTER(slw_field), _dbl, _dbl, ctypes.c_int, ctypes.c_int, _vp,
@@ -115,6 +117,9 @@ _sig("slw_step", ctypes.c_int, [_vp, ctypes.POINTER(slw_field), _dbl, _dbl, ctyp
 _sig("slw_step_noalloc", ctypes.c_int, [_vp, ctypes.POINTER(slw_field), _dbl, _dbl, ctypes.c_int, ctypes.c_int,
                                         ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _dbl, _vp,
                                         ctypes.POINTER(slw_stats)])
+_sig("slw_step_autotune", ctypes.c_int, [_vp, ctypes.POINTER(slw_field), _dbl, _dbl, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_char_p,
+                                         ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)])
 _sig("slw_permute_rows", ctypes.c_int, [_vp, _vp, _vp, _i64, ctypes.c_int])
 _sig("slw_orient_sign_host", ctypes.c_int, [_vp, _i64, _vp, ctypes.c_int])
 _sig("slw_float_filter_host", ctypes.c_int, [_vp, _i64, _dbl, _dbl, _dbl, ctypes.c_int, _vp])
@@ -156,8 +161,8 @@ MLP_PARAMS = 5 * 64 + 64 + 64 * 64 + 64 + 64 * 2 + 2
 
 EXPORTED = ["slw_status_string", "slw_last_error", "slw_ctx_create", "slw_ctx_set_stream", "slw_ctx_destroy",
             "slw_mesh_upload", "slw_mesh_check", "slw_mesh_free", "slw_mesh_get_info", "slw_mesh_dof_coords", "slw_mesh_dof_order",
-            "slw_mesh_set_walk_limits", "slw_mesh_set_repack", "slw_mesh_set_neighbour_codes", "slw_walk_codes_host", "slw_mesh_set_chain", "slw_mesh_set_boundary", "slw_locate", "slw_locate_feet", "slw_interpolate", "slw_step",
-            "slw_step_noalloc", "slw_permute_rows", "slw_orient_sign_host",
+            "slw_mesh_set_walk_limits", "slw_mesh_set_repack", "slw_mesh_set_neighbour_codes", "slw_walk_codes_host", "slw_mesh_set_chain", "slw_mesh_set_hybrid", "slw_mesh_set_boundary", "slw_locate", "slw_locate_feet", "slw_interpolate", "slw_step",
+            "slw_step_noalloc", "slw_step_autotune", "slw_permute_rows", "slw_orient_sign_host",
             "slw_float_filter_host", "slw_batch_create", "slw_batch_free", "slw_batch_set_fields",
             "slw_batch_set_values", "slw_batch_set_elem_out", "slw_batch_set_step", "slw_batch_get_step", "slw_batch_set_schedule",
             "slw_batch_step", "slw_batch_graph_capture", "slw_graph_launch", "slw_graph_free", "slw_batch_autotune",
@@ -315,6 +320,9 @@ class Mesh:
 
     def set_chain(self, length: int):
         _check(_lib.slw_mesh_set_chain(self.h, int(length)), "slw_mesh_set_chain")
+
+    def set_hybrid(self, far: float):
+        _check(_lib.slw_mesh_set_hybrid(self.h, float(far)), "slw_mesh_set_hybrid")
 
     def set_boundary(self, kind: int, params=(0.0, 0.0, 0.0, 0.0)):
         """Boundary data g for feet that leave the domain: BC_NONE, BC_CONSTANT
@@ -479,6 +487,20 @@ class Mesh:
                   float(outside_value), _ptr(elem, torch.int32, dev, "elem", True),
                   ctypes.byref(st) if st is not None else None), name)
         return (v_out, st.as_dict()) if stats else v_out
+
+    def autotune_step(self, field, t_n, dt, scheme, v_in, order=1, start_mode=START_STEERED, start=None,
+                      cache_path=None):
+        """slw_step_autotune: returns (value chosen, median ms per step)."""
+        torch = _torch()
+        dev = self.ctx.device
+        k = 1 if v_in.ndim == 1 else v_in.shape[1]
+        val, ms = ctypes.c_double(), ctypes.c_double()
+        _check(_lib.slw_step_autotune(self.h, ctypes.byref(make_field(field)), float(t_n), float(dt), int(scheme),
+                                      int(order), int(start_mode), _ptr(start, torch.int32, dev, "start", True),
+                                      _ptr(v_in, v_in.dtype, dev, "v_in"), _vdtype(v_in), k,
+                                      None if cache_path is None else str(cache_path).encode(),
+                                      ctypes.byref(val), ctypes.byref(ms)), "slw_step_autotune")
+        return float(val.value), float(ms.value)
 
     def permute_rows(self, src, dst=None, to_internal=True):
         torch = _torch()
