@@ -64,8 +64,15 @@
  *     exit hook registered after the runtime was loaded, which runs first.
  *   - The mesh must be conforming (every edge shared by at most two
  *     triangles, consistently oriented), free of zero-area triangles, and
- *     its domain convex (one boundary loop with no reflex corner), so that
- *     "outside" is decided exactly by a boundary edge.
+ *     its boundary a manifold (no node where the boundary passes twice).
+ *     When the domain is one convex disk (one boundary loop, no reflex
+ *     corner), a walk that meets the boundary with the foot beyond it
+ *     proves the foot outside.  Otherwise (reflex corners, holes, several
+ *     pieces: slw_mesh_info.nonconvex) the foot may lie across a notch or a
+ *     hole: such a walk ends in an exact search (a quadtree over the
+ *     triangles, built at upload, whose leaf is scanned with the walk's exact
+ *     signs: the smallest user id among the closed containers, or outside
+ *     when there is none), so results are the same as on convex meshes.
  */
 #ifndef SLWALK_H
 #define SLWALK_H
@@ -156,7 +163,9 @@ typedef struct slw_stats {
     int64_t fallback_walks; /* walks that reached the step cap and finished randomised */
     int64_t edge_ties;      /* feet on an edge shared by two triangles */
     int64_t vertex_ties;    /* feet on a mesh vertex */
-    int64_t reserved[7];
+    int64_t boundary_searches; /* non-convex domains: walks blocked by the boundary and ended by
+                                  the exact search (located inside, or proven outside) */
+    int64_t reserved[6];
     /* Walks by length (Section 2.2 walk steps = element changes): bin 0 counts
      * walks with no change (feet outside the bounding box included), bin b
      * for 1 <= b <= 14 those with [2^(b-1), 2^b) changes, bin 15 those with
@@ -169,6 +178,8 @@ typedef struct slw_mesh_info {
     int64_t n_nodes, n_tris, n_edges, n_dofs; /* n_edges, n_dofs: P2 only (else 0, n_nodes) */
     int64_t device_bytes;                     /* device memory held by the handle */
     int32_t coords_f32, p2, reordered, internal_order;
+    int32_t nonconvex;                        /* 1: the domain is not one convex disk (see conventions) */
+    int32_t boundary_loops;                   /* number of boundary loops (1 + holes, for one piece) */
     double bbox[4];                           /* xmin, ymin, xmax, ymax */
 } slw_mesh_info;
 

@@ -83,6 +83,7 @@ slw_status copy_stats(slw_ctx *ctx, const DevStats *counters, slw_stats *stats_h
     stats_h->fallback_walks = (int64_t)h.fallback_walks;
     stats_h->edge_ties = (int64_t)h.edge_ties;
     stats_h->vertex_ties = (int64_t)h.vertex_ties;
+    stats_h->boundary_searches = (int64_t)h.boundary_searches;
     for (int b = 0; b < kHistBins; ++b)
         stats_h->step_hist[b] = (int64_t)h.step_hist[b];
     if (h.hard_fail)
@@ -305,6 +306,8 @@ slw_status slw_mesh_check(const double *xy_h, int64_t n_nodes, const int32_t *tr
         info_h->p2 = m.p2;
         info_h->reordered = m.reordered;
         info_h->internal_order = m.internal_order;
+        info_h->nonconvex = m.nonconvex;
+        info_h->boundary_loops = m.n_loops;
         for (int i = 0; i < 4; ++i)
             info_h->bbox[i] = m.bbox[i];
     }
@@ -337,6 +340,8 @@ slw_status slw_mesh_get_info(const slw_mesh *mesh, slw_mesh_info *out_h)
     out_h->p2 = m.p2;
     out_h->reordered = m.reordered;
     out_h->internal_order = m.internal_order;
+    out_h->nonconvex = m.nonconvex;
+    out_h->boundary_loops = m.n_loops;
     for (int i = 0; i < 4; ++i)
         out_h->bbox[i] = m.bbox[i];
     return SLW_OK;
@@ -1188,7 +1193,7 @@ std::vector<double> knob_values(int mode, bool bc)
     if (mode == SLW_START_LEARNED_INDEX || bc)
         return {1};  // one-foot-per-lane kernels only
     return {1, 2, 4, 8};
-}
+}  // bc: boundary data or a non-convex domain (one-foot-per-lane kernels only)
 
 double knob_get(const DevMesh &m, int mode)
 {
@@ -1293,7 +1298,7 @@ extern "C" slw_status slw_step_autotune(slw_mesh *mesh, const slw_field *field, 
         double cached = 0.0, cms = 0.0;
         if (cache_path && cache_lookup_num(cache_path, sig, knob_name(start_mode), cached)) {
             (void)cache_lookup_num(cache_path, sig, "ms", cms);
-            const std::vector<double> ok = knob_values(start_mode, m.bc_kind != 0);
+            const std::vector<double> ok = knob_values(start_mode, m.bc_kind != 0 || m.nonconvex != 0);
             bool valid = false;
             for (double v : ok)
                 valid = valid || v == cached;
@@ -1314,7 +1319,7 @@ extern "C" slw_status slw_step_autotune(slw_mesh *mesh, const slw_field *field, 
         }
     }
     double best_v = saved, best_ms = 1e300;
-    for (double v : knob_values(start_mode, m.bc_kind != 0)) {
+    for (double v : knob_values(start_mode, m.bc_kind != 0 || m.nonconvex != 0)) {
         if (st != SLW_OK)
             break;
         knob_set(m, start_mode, v);

@@ -78,6 +78,13 @@ struct DevMesh {
     int32_t *bnext = nullptr;     // [n_nodes] next boundary node, counter-clockwise (-1: interior node)
     int32_t *bprev = nullptr;     // [n_nodes] previous boundary node
     int64_t n_boundary = 0;
+    // a domain that is not one convex disk (reflex corners, holes, several
+    // pieces): a walk blocked by the boundary ends in an exact search (the
+    // quadtree below, built at upload); boundary crossings of the variable
+    // step scan every boundary edge
+    int nonconvex = 0;
+    int n_loops = 0;               // boundary loops
+    int32_t *bedge = nullptr;      // [n_boundary] internal node a of every boundary edge a -> bnext[a]
     // boundary data for feet outside the domain (variable step); kind 0: none
     int bc_kind = 0;
     double bc_p[4] = {0, 0, 0, 0};
@@ -120,7 +127,7 @@ struct DevMesh {
 constexpr int kHistBins = 16;
 struct DevStats {
     unsigned long long feet, outside, walk_steps, max_steps, exact_tests, fp64_tests, fallback_walks,
-        edge_ties, vertex_ties, hard_fail, pad[6];
+        edge_ties, vertex_ties, hard_fail, boundary_searches, pad[5];
     unsigned long long step_hist[kHistBins];
 };
 
@@ -204,6 +211,9 @@ constexpr int kMlpPartials = 1024;                                   // workgrou
 slw_status build_mesh(slw_ctx *ctx, const double *xy, int64_t n, const int32_t *tri, int64_t nt, uint32_t flags,
                       DevMesh &out, bool to_device);
 void free_mesh(DevMesh &m);
+// quadtree over the triangles geo (internal order; exact coordinates from the
+// mesh's host copies): see slw_quadtree_build
+slw_status build_quadtree(DevMesh &m, const std::vector<GeoRec> &geo, int leaf_cap, int max_depth);
 // coefficients of the walk's float filter for a mesh whose float coordinates
 // are fl32(x - (cx, cy)) with |x - c| <= cmax (f32: coordinates already float)
 FilterConst filter_constants(bool f32, double cx, double cy, double cmax);
@@ -249,6 +259,14 @@ struct MeshView {
     // variable step at the boundary (bc_kind 0: off)
     const int32_t *bnext, *bprev;
     int64_t n_boundary;
+    // non-convex domains: exact search of a blocked foot (quadtree) and the
+    // boundary edges for crossings
+    int nonconvex;
+    const int4 *qt_nodes;
+    const int32_t *qt_lists;
+    double qt_box[3];
+    int qt_depth;
+    const int32_t *bedge;
     int bc_kind;
     double bc_p[4];
     // chart starts (null without a chart / network)

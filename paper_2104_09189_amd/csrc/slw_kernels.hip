@@ -155,6 +155,13 @@ MeshView view_of(const DevMesh &m)
     v.bc_kind = m.bc_kind;
     for (int i = 0; i < 4; ++i)
         v.bc_p[i] = m.bc_p[i];
+    v.nonconvex = m.nonconvex;
+    v.qt_nodes = m.qt_nodes;
+    v.qt_lists = m.qt_lists;
+    for (int i = 0; i < 3; ++i)
+        v.qt_box[i] = m.qt_box[i];
+    v.qt_depth = m.qt_depth;
+    v.bedge = m.bedge;
     v.chart_node = m.chart_node;
     v.chart_qx = m.chart_qx;
     v.chart_qy = m.chart_qy;
@@ -556,6 +563,47 @@ __device__ inline int det_move(const MeshView &mv, int32_t &j, const WalkRec &r,
     return 0;
 }
 
+// Exact point location without a walk (the quadtree of Section 2.1): descend
+// to the leaf that holds q (a point on a split line goes to the upper/right
+// child; a triangle is listed in every leaf its closed bounding box touches,
+// so every closed container of q is in q's leaf), test every listed triangle
+// with the walk's exact signs, keep the smallest user id among the closed
+// containers: the walk's answer by definition.  Returns its internal id (rb:
+// its walk record), or -1 when no triangle contains q.  Needs mv.qt_nodes.
+template <bool F32>
+__device__ inline int32_t qt_find(const MeshView &mv, typename CT<F32>::R qx, typename CT<F32>::R qy,
+                                        WalkRec &rb, Counters &c)
+{
+    const float qfx = F32 ? (float)qx : (float)((double)qx - mv.fc.cx);
+    const float qfy = F32 ? (float)qy : (float)((double)qy - mv.fc.cy);
+    double bx = mv.qt_box[0], by = mv.qt_box[1], s = mv.qt_box[2];
+    int4 nd = mv.qt_nodes[0];
+    for (int depth = 0; nd.x >= 0 && depth < mv.qt_depth; ++depth) {
+        s *= 0.5;
+        const int right = (double)qx >= bx + s, top = (double)qy >= by + s;
+        bx += right ? s : 0.0;
+        by += top ? s : 0.0;
+        nd = mv.qt_nodes[nd.x + right + 2 * top];
+    }
+    int32_t best = -1, best_uid = 0x7fffffff;
+    for (int32_t k = 0; k < nd.z; ++k) {
+        const int32_t t = mv.qt_lists[nd.y + k];
+        const WalkRec r = mv.wrec[t];
+        float o[3];
+        int sg[3];
+        edge_signs<F32>(mv, t, r.p, qfx, qfy, qx, qy, o, sg, c);
+        if (sg[0] >= 0 && sg[1] >= 0 && sg[2] >= 0) {
+            const int32_t uid = mv.tri_uf[t] & kUidMask;
+            if (uid < best_uid) {
+                best_uid = uid;
+                best = t;
+                rb = r;
+            }
+        }
+    }
+    return best;
+}
+
 // End of a walk whose deterministic moves stopped with status st (0: the step
 // cap was reached; the walk goes on with the randomised choice and the hard
 // limit), then the outside result or the tie rule and the weights.
@@ -568,6 +616,28 @@ __device__ inline WalkResult<typename CT<F32>::R> walk_end(const MeshView &mv, i
     using R = typename CT<F32>::R;
     while (st == 0)
         st = walk_move<F32>(mv, j, r, zmask, qfx, qfy, qx, qy, seed, steps, flags, c);
+    if (st == 2 && zmask >= 0 && mv.nonconvex) {
+        // blocked by the boundary of a domain that is not one convex disk:
+        // the foot may lie across a notch or a hole, so the exact search
+        // decides (flag bit 5)
+        WalkRec rb;
+        const int32_t e = qt_find<F32>(mv, qx, qy, rb, c);
+        flags |= 32;
+        if (e < 0) {
+            WalkResult<R> w = outside_result<R>(steps, flags | 16);  // crossing: scanned by the caller
+            return w;
+        }
+        const int4 tv = tri_verts(mv, e);
+        WalkResult<R> w;
+        w.elem = e;
+        w.steps = steps;
+        w.flags = flags;
+        w.v[0] = tv.y;
+        w.v[1] = tv.z;
+        w.v[2] = tv.w;
+        exact_weights<F32>(mv, rb.p, w.v, qx, qy, w.th);
+        return w;
+    }
     if (st == 2) {
         WalkResult<R> w = outside_result<R>(steps, flags);
         if (zmask >= 0) {  // the boundary edge opposite vertex zmask, counter-clockwise
@@ -677,7 +747,8 @@ __device__ inline unsigned long long wave_max(unsigned long long v)
 }
 
 struct LaneStats {
-    uint32_t feet = 0, outside = 0, steps = 0, max_steps = 0, fallback = 0, edge = 0, vertex = 0, hard = 0;
+    uint32_t feet = 0, outside = 0, steps = 0, max_steps = 0, fallback = 0, edge = 0, vertex = 0, hard = 0,
+             search = 0;
     Counters c;
     template <typename R>
     __device__ void add(const WalkResult<R> &w)
@@ -690,6 +761,7 @@ struct LaneStats {
         hard += (w.flags & 2) != 0;
         edge += (w.flags & 4) != 0;
         vertex += (w.flags & 8) != 0;
+        search += (w.flags & 32) != 0;
     }
     // a walk's end (inside or outside) and, separately, its tie flags
     __device__ void add_walk(bool inside, int32_t st, int32_t flags)
@@ -711,14 +783,14 @@ struct LaneStats {
 // called by every lane of the wavefront
 __device__ inline void flush_stats(const LaneStats &ls, DevStats *st)
 {
-    unsigned long long v[10] = {ls.feet, ls.outside, ls.steps, ls.max_steps, ls.c.exact, ls.c.fp64, ls.fallback,
-                                ls.edge, ls.vertex, ls.hard};
-    unsigned long long *dst[10] = {&st->feet, &st->outside, &st->walk_steps, &st->max_steps, &st->exact_tests,
+    unsigned long long v[11] = {ls.feet, ls.outside, ls.steps, ls.max_steps, ls.c.exact, ls.c.fp64, ls.fallback,
+                                ls.edge, ls.vertex, ls.hard, ls.search};
+    unsigned long long *dst[11] = {&st->feet, &st->outside, &st->walk_steps, &st->max_steps, &st->exact_tests,
                                    &st->fp64_tests, &st->fallback_walks, &st->edge_ties, &st->vertex_ties,
-                                   &st->hard_fail};
+                                   &st->hard_fail, &st->boundary_searches};
     const bool lead = (threadIdx.x & 63) == 0;
 #pragma unroll
-    for (int i = 0; i < 10; ++i) {
+    for (int i = 0; i < 11; ++i) {
         unsigned long long r = (i == 3) ? wave_max(v[i]) : wave_sum(v[i]);
         if (lead && r != 0) {
             if (i == 3)
@@ -842,58 +914,27 @@ __global__ void __launch_bounds__(kBlock) k_locate(MeshView mv, const typename C
         flush_stats(ls, st);
 }
 
-// Non-walking locator for comparison (the quadtree of Section 2.1): descend
-// to the leaf that holds q (a point on a split line goes to the upper/right
-// child; triangles are listed in every leaf their closed bounding box
-// touches, so every closed container of q is in q's leaf), then test every
-// listed triangle with the walk's exact signs and keep the smallest user id
-// among the closed containers: the same answer as the walk, by definition.
+// Non-walking locator for comparison (the quadtree of Section 2.1): every
+// query by the exact search qt_find, no walk.
 template <bool F32>
 __global__ void __launch_bounds__(kBlock)
-    k_qt_locate(MeshView mv, const int4 *__restrict__ nodes, const int32_t *__restrict__ lists, double ox,
-                double oy, double side, int max_depth, const typename CT<F32>::R2 *__restrict__ q, int64_t m,
-                int32_t *__restrict__ elem, typename CT<F32>::R *__restrict__ bary, DevStats *st)
+    k_qt_locate(MeshView mv, const typename CT<F32>::R2 *__restrict__ q, int64_t m, int32_t *__restrict__ elem,
+                typename CT<F32>::R *__restrict__ bary, DevStats *st)
 {
     using R = typename CT<F32>::R;
     LaneStats ls;
     const int64_t i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (i < m) {
         const R qx = q[i].x, qy = q[i].y;
-        int32_t best = -1, best_uid = 0x7fffffff;
+        int32_t best = -1;
         WalkRec rb;
-        if (in_box<R>(qx, qy, mv.bb)) {
-            const float qfx = F32 ? (float)qx : (float)((double)qx - mv.fc.cx);
-            const float qfy = F32 ? (float)qy : (float)((double)qy - mv.fc.cy);
-            double bx = ox, by = oy, s = side;
-            int4 nd = nodes[0];
-            for (int depth = 0; nd.x >= 0 && depth < max_depth; ++depth) {
-                s *= 0.5;
-                const int right = (double)qx >= bx + s, top = (double)qy >= by + s;
-                bx += right ? s : 0.0;
-                by += top ? s : 0.0;
-                nd = nodes[nd.x + right + 2 * top];
-            }
-            for (int32_t c = 0; c < nd.z; ++c) {
-                const int32_t t = lists[nd.y + c];
-                const WalkRec r = mv.wrec[t];
-                float o[3];
-                int sg[3];
-                edge_signs<F32>(mv, t, r.p, qfx, qfy, qx, qy, o, sg, ls.c);
-                if (sg[0] >= 0 && sg[1] >= 0 && sg[2] >= 0) {
-                    const int32_t uid = mv.tri_uf[t] & kUidMask;
-                    if (uid < best_uid) {
-                        best_uid = uid;
-                        best = t;
-                        rb = r;
-                    }
-                }
-            }
-        }
+        if (in_box<R>(qx, qy, mv.bb))
+            best = qt_find<F32>(mv, qx, qy, rb, ls.c);
         if (st) {
             ++ls.feet;
             ls.outside += best < 0;
         }
-        elem[i] = best >= 0 ? best_uid : -1;
+        elem[i] = best >= 0 ? (mv.tri_uf[best] & kUidMask) : -1;
         if (bary) {
             if (best >= 0) {
                 R th[3], ub[3];
@@ -1359,6 +1400,40 @@ __device__ inline bool boundary_value(const MeshView &mv, bool f32, double xx, d
     return false;
 }
 
+// boundary_value for a domain that is not one convex disk: the segment
+// x -> q may leave and re-enter, so every boundary edge is scanned for the
+// first crossing from inside to outside (smallest theta).  False when the
+// segment crosses no boundary edge outwards (degenerate input).
+__device__ inline bool boundary_value_scan(const MeshView &mv, bool f32, double xx, double xy, double qx, double qy,
+                                           double t_np1, double dt, double &g)
+{
+    const double wx = qx - xx, wy = qy - xy;
+    double best = INFINITY;
+    for (int64_t i = 0; i < mv.n_boundary; ++i) {
+        const int32_t a = mv.bedge[i], b = mv.bnext[a];
+        double ax, ay, bx, by;
+        if (f32) {
+            const float2 A = ((const float2 *)mv.dof_xy)[a], B = ((const float2 *)mv.dof_xy)[b];
+            ax = A.x, ay = A.y, bx = B.x, by = B.y;
+        } else {
+            const double2 A = ((const double2 *)mv.dof_xy)[a], B = ((const double2 *)mv.dof_xy)[b];
+            ax = A.x, ay = A.y, bx = B.x, by = B.y;
+        }
+        const double ex = bx - ax, ey = by - ay, rx = ax - xx, ry = ay - xy;
+        const double den = wx * ey - wy * ex;  // > 0: the segment crosses this edge's line outwards
+        if (!(den > 0.0))
+            continue;
+        const double la = (rx * wy - ry * wx) / den, th = (rx * ey - ry * ex) / den;
+        if (la >= 0.0 && la <= 1.0 && th >= -1e-12 && th <= 1.0 + 1e-12)
+            best = fmin(best, th < 0.0 ? 0.0 : (th > 1.0 ? 1.0 : th));
+    }
+    if (!(best <= 1.0))
+        return false;
+    const double px = xx + best * wx, py = xy + best * wy, t = t_np1 - best * dt;
+    g = mv.bc_kind == 1 ? mv.bc_p[0] : mv.bc_p[0] + mv.bc_p[1] * px + mv.bc_p[2] * py + mv.bc_p[3] * t;
+    return true;
+}
+
 // The fused step (Algorithm 2, one pass of its loop) for the 64 DOFs
 // [base, base + 64) of one wavefront: one lane per foot for foot -> start ->
 // walk -> tie rule -> weights; then the wavefront computes its feet's values
@@ -1485,8 +1560,11 @@ __device__ inline void step_wave(const MeshView &mv, const FieldDev &f, double d
             lagrange<R, V, NA>(mv, w.elem, w.v, w.th, row, wgt);
         } else if (mv.bc_kind && (w.flags & 16)) {
             double gv;
-            if (boundary_value(mv, F32, (double)x.x, (double)x.y, (double)qx, (double)qy, w.v[0], w.v[1], t_np1,
-                               dt, gv)) {
+            const bool hit = mv.nonconvex ? boundary_value_scan(mv, F32, (double)x.x, (double)x.y, (double)qx,
+                                                                (double)qy, t_np1, dt, gv)
+                                          : boundary_value(mv, F32, (double)x.x, (double)x.y, (double)qx, (double)qy,
+                                                           w.v[0], w.v[1], t_np1, dt, gv);
+            if (hit) {
                 row[0] = -2;  // value given in wgt[0]
                 wgt[0] = (V)gv;
             }
@@ -2051,11 +2129,11 @@ hipError_t launch_qt_locate(const DevMesh &m, hipStream_t st, const void *q, int
         return hipErrorInvalidValue;
     MeshView mv = view_of(m);
     if (m.coords_f32)
-        hipLaunchKernelGGL(k_qt_locate<true>, dim3(g), dim3(kBlock), 0, st, mv, m.qt_nodes, m.qt_lists, m.qt_box[0],
-                           m.qt_box[1], m.qt_box[2], m.qt_depth, (const float2 *)q, mp, elem, (float *)bary, stats);
+        hipLaunchKernelGGL(k_qt_locate<true>, dim3(g), dim3(kBlock), 0, st, mv, (const float2 *)q, mp, elem,
+                           (float *)bary, stats);
     else
-        hipLaunchKernelGGL(k_qt_locate<false>, dim3(g), dim3(kBlock), 0, st, mv, m.qt_nodes, m.qt_lists, m.qt_box[0],
-                           m.qt_box[1], m.qt_box[2], m.qt_depth, (const double2 *)q, mp, elem, (double *)bary, stats);
+        hipLaunchKernelGGL(k_qt_locate<false>, dim3(g), dim3(kBlock), 0, st, mv, (const double2 *)q, mp, elem,
+                           (double *)bary, stats);
     return hipGetLastError();
 }
 
@@ -2119,8 +2197,9 @@ hipError_t launch_step(const DevMesh &m, hipStream_t st, const FieldDev &f0, dou
     unsigned g;
     if (!tiles_for(n_iter, g))
         return hipErrorInvalidValue;
-    // boundary data are applied by the one-foot-per-lane kernels only
-    const int rp = m.bc_kind ? 0 : m.repack;
+    // boundary data and the exact search of non-convex domains are applied
+    // by the one-foot-per-lane kernels only
+    const int rp = (m.bc_kind || m.nonconvex) ? 0 : m.repack;
     if (m.bc_kind && mode == SLW_START_NEIGHBOR && m.chain != 0)
         return hipErrorNotSupported;
     const bool chart_mode = mode == SLW_START_LEARNED || mode == SLW_START_CHART || mode == SLW_START_LEARNED_INDEX;

@@ -189,7 +189,7 @@ void free_mesh(DevMesh &m)
                     m.dof_int, m.tri_int, m.prev_elem, m.jump, m.chart_uv, m.chart_node, m.chart_table,
                     m.chart_qx, m.chart_qy, m.learned_start, m.bnext, m.bprev, m.qt_nodes, m.qt_lists,
                     m.forest_list1, m.forest_out1, m.forest_parent1, m.forest_list2, m.forest_out2,
-                    m.forest_parent2, m.forest_elem};
+                    m.forest_parent2, m.forest_elem, m.bedge};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -295,7 +295,8 @@ slw_status build_mesh(slw_ctx *ctx, const double *xy, int64_t n, const int32_t *
         } else {
             int32_t a = from_of(e0), b = (int32_t)(a == (int32_t)lo ? hi : lo);
             if (bnext[a] >= 0)
-                return set_error(SLW_E_MESH_NONCONVEX, "boundary passes twice through node " + std::to_string(a));
+                return set_error(SLW_E_MESH_NONCONVEX,
+                                 "non-manifold boundary: it passes twice through node " + std::to_string(a));
             bnext[a] = b;
             ++n_bnd;
             if (a == (int32_t)lo)
@@ -313,7 +314,11 @@ slw_status build_mesh(slw_ctx *ctx, const double *xy, int64_t n, const int32_t *
         }
         i = j;
     }
-    // a disk (V - E + F = 1) whose single boundary loop turns left everywhere
+    // Convex: a disk (V - E + F = 1) whose single boundary loop turns left
+    // (or goes straight) at every corner; then a walk that meets the
+    // boundary with the foot beyond it proves the foot outside.  Any other
+    // manifold boundary (reflex corners, holes, several pieces) makes the
+    // mesh non-convex: such walks end in an exact search instead.
     int64_t n_edge_total = 0;
     {
         int64_t ne = 0;
@@ -322,30 +327,33 @@ slw_status build_mesh(slw_ctx *ctx, const double *xy, int64_t n, const int32_t *
                 ++ne;
         n_edge_total = ne;
     }
-    if (n - n_edge_total + nt != 1)
-        return set_error(SLW_E_MESH_NONCONVEX, "the mesh is not a single disk (V - E + F != 1)");
+    bool nonconvex = n - n_edge_total + nt != 1;
+    int n_loops = 0;
     {
-        int32_t start = -1;
-        for (int64_t i = 0; i < n && start < 0; ++i)
-            if (bnext[i] >= 0)
-                start = (int32_t)i;
-        int64_t cnt = 0;
-        int32_t a = start;
-        do {
-            int32_t b = bnext[a];
-            if (b < 0)
-                return set_error(SLW_E_MESH_NONCONVEX, "open boundary");
-            int32_t c = bnext[b];
-            if (c < 0)
-                return set_error(SLW_E_MESH_NONCONVEX, "open boundary");
-            if (orient_sign64(X[2 * a], X[2 * a + 1], X[2 * b], X[2 * b + 1], X[2 * c], X[2 * c + 1]) < 0)
-                return set_error(SLW_E_MESH_NONCONVEX, "reflex boundary corner at node " + std::to_string(b));
-            a = b;
-            if (++cnt > n_bnd)
-                break;
-        } while (a != start);
-        if (cnt != n_bnd)
-            return set_error(SLW_E_MESH_NONCONVEX, "the boundary is not a single loop");
+        std::vector<char> seen(n, 0);
+        for (int64_t s0 = 0; s0 < n; ++s0) {
+            if (bnext[s0] < 0 || seen[s0])
+                continue;
+            ++n_loops;
+            int32_t a = (int32_t)s0;
+            int64_t cnt = 0;
+            do {
+                seen[a] = 1;
+                const int32_t b = bnext[a];
+                if (b < 0)
+                    return set_error(SLW_E_MESH_NONCONVEX, "open boundary");
+                const int32_t c = bnext[b];
+                if (c < 0)
+                    return set_error(SLW_E_MESH_NONCONVEX, "open boundary");
+                if (orient_sign64(X[2 * a], X[2 * a + 1], X[2 * b], X[2 * b + 1], X[2 * c], X[2 * c + 1]) < 0)
+                    nonconvex = true;  // reflex corner at b
+                a = b;
+                if (++cnt > n_bnd)
+                    return set_error(SLW_E_MESH_NONCONVEX, "boundary loop does not close");
+            } while (a != (int32_t)s0);
+        }
+        if (n_loops != 1)
+            nonconvex = true;
     }
 
     // ---------------- orders ----------------
@@ -565,6 +573,8 @@ slw_status build_mesh(slw_ctx *ctx, const double *xy, int64_t n, const int32_t *
         out.p2 = p2;
         out.reordered = reorder;
         out.internal_order = (flags & SLW_INTERNAL_ORDER) ? 1 : 0;
+        out.nonconvex = nonconvex;
+        out.n_loops = n_loops;
         for (int i = 0; i < 4; ++i)
             out.bbox[i] = bb[i];
         return SLW_OK;
@@ -577,6 +587,8 @@ slw_status build_mesh(slw_ctx *ctx, const double *xy, int64_t n, const int32_t *
     m.p2 = p2;
     m.reordered = reorder;
     m.internal_order = (flags & SLW_INTERNAL_ORDER) ? 1 : 0;
+    m.nonconvex = nonconvex;
+    m.n_loops = n_loops;
     for (int i = 0; i < 4; ++i)
         m.bbox[i] = bb[i];
     m.jump_g = g;
@@ -633,6 +645,11 @@ slw_status build_mesh(slw_ctx *ctx, const double *xy, int64_t n, const int32_t *
         UP(bn, m.bnext);
         UP(bp, m.bprev);
         m.n_boundary = n_bnd;
+        std::vector<int32_t> be;
+        for (int64_t a = 0; a < n; ++a)
+            if (bn[a] >= 0)
+                be.push_back((int32_t)a);
+        UP(be, m.bedge);
     }
     {
         // strategy (c)'s forest: roots = a maximal independent set of the
@@ -701,9 +718,24 @@ slw_status build_mesh(slw_ctx *ctx, const double *xy, int64_t n, const int32_t *
         UP(fe, m.forest_elem);
     }
 #undef UP
-    m.device_bytes = bytes;
     m.dof_xy_user_h = std::move(dof_user_xy);
     m.dof_user_h = std::move(dof_u);
+    if (nonconvex) {
+        // the exact search that ends walks blocked by the boundary: leaves
+        // as small as the list budget allows
+        st = SLW_E_NOMEM;
+        for (int cap = 16; st != SLW_OK && cap <= (1 << 30); cap *= 4) {
+            st = build_quadtree(m, geo, cap, 24);
+            if (cap >= nt)
+                break;
+        }
+        if (st != SLW_OK) {
+            free_mesh(m);
+            return st;
+        }
+        bytes += m.qt_n_nodes * (int64_t)sizeof(int4) + m.qt_n_list * (int64_t)sizeof(int32_t);
+    }
+    m.device_bytes = bytes;
     out = std::move(m);
     return SLW_OK;
 }

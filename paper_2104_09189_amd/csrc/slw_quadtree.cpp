@@ -33,21 +33,11 @@ struct Pending {
 
 }  // namespace
 
-extern "C" {
+namespace slw {
 
-slw_status slw_quadtree_build(slw_mesh *mesh, int leaf_cap, int max_depth)
+slw_status build_quadtree(DevMesh &m, const std::vector<GeoRec> &geo, int leaf_cap, int max_depth)
 {
-    if (!mesh || leaf_cap < 1 || max_depth < 0 || max_depth > 30)
-        return set_error(SLW_E_ARG, "slw_quadtree_build: leaf_cap >= 1 and max_depth in [0, 30]");
-    DevMesh &m = mesh->m;
-    DeviceGuard gd(mesh->ctx->device);
     const int64_t nt = m.n_tris;
-    std::vector<GeoRec> geo(nt);
-    slw_status st = hip_check(hipStreamSynchronize(mesh->ctx->stream), "hipStreamSynchronize");
-    if (st == SLW_OK)
-        st = hip_check(hipMemcpy(geo.data(), m.geo, nt * sizeof(GeoRec), hipMemcpyDeviceToHost), "copy records");
-    if (st != SLW_OK)
-        return st;
     // closed bounding boxes on the exact coordinates (float meshes: the floats)
     std::vector<double> box(4 * (size_t)nt);
     for (int64_t t = 0; t < nt; ++t) {
@@ -120,12 +110,12 @@ slw_status slw_quadtree_build(slw_mesh *mesh, int leaf_cap, int max_depth)
             if (most == p.tris.size())
                 leaf = true;
             else if ((listed += (int64_t)added - (int64_t)p.tris.size()) > budget)
-                return set_error(SLW_E_NOMEM, "slw_quadtree_build: more than 16 list entries per triangle "
+                return set_error(SLW_E_NOMEM, "quadtree: more than 16 list entries per triangle "
                                               "(raise leaf_cap or lower max_depth)");
         }
         if (leaf) {
             if (lists.size() + p.tris.size() > (size_t)INT32_MAX)
-                return set_error(SLW_E_NOMEM, "slw_quadtree_build: lists exceed 2^31 entries");
+                return set_error(SLW_E_NOMEM, "quadtree: lists exceed 2^31 entries");
             nodes[p.node] = make_int4(-1, (int32_t)lists.size(), (int32_t)p.tris.size(), 0);
             lists.insert(lists.end(), p.tris.begin(), p.tris.end());
             depth_max = std::max(depth_max, p.depth);
@@ -148,13 +138,13 @@ slw_status slw_quadtree_build(slw_mesh *mesh, int leaf_cap, int max_depth)
         hipMalloc((void **)&ls, lists.size() * sizeof(int32_t)) != hipSuccess) {
         if (nd)
             (void)hipFree(nd);
-        return set_error(SLW_E_NOMEM, "slw_quadtree_build: device arrays");
+        return set_error(SLW_E_NOMEM, "quadtree: device arrays");
     }
     if (hipMemcpy(nd, nodes.data(), nodes.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(ls, lists.data(), lists.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipFree(nd);
         (void)hipFree(ls);
-        return set_error(SLW_E_HIP, "slw_quadtree_build: copy to the device");
+        return set_error(SLW_E_HIP, "quadtree: copy to the device");
     }
     if (m.qt_nodes)
         (void)hipFree(m.qt_nodes);
@@ -169,6 +159,26 @@ slw_status slw_quadtree_build(slw_mesh *mesh, int leaf_cap, int max_depth)
     m.qt_n_nodes = (int64_t)nodes.size();
     m.qt_n_list = (int64_t)lists.size();
     return SLW_OK;
+}
+
+}  // namespace slw
+
+extern "C" {
+
+slw_status slw_quadtree_build(slw_mesh *mesh, int leaf_cap, int max_depth)
+{
+    if (!mesh || leaf_cap < 1 || max_depth < 0 || max_depth > 30)
+        return set_error(SLW_E_ARG, "slw_quadtree_build: leaf_cap >= 1 and max_depth in [0, 30]");
+    DevMesh &m = mesh->m;
+    DeviceGuard gd(mesh->ctx->device);
+    const int64_t nt = m.n_tris;
+    std::vector<GeoRec> geo(nt);
+    slw_status st = hip_check(hipStreamSynchronize(mesh->ctx->stream), "hipStreamSynchronize");
+    if (st == SLW_OK)
+        st = hip_check(hipMemcpy(geo.data(), m.geo, nt * sizeof(GeoRec), hipMemcpyDeviceToHost), "copy records");
+    if (st != SLW_OK)
+        return st;
+    return build_quadtree(m, geo, leaf_cap, max_depth);
 }
 
 slw_status slw_quadtree_info(const slw_mesh *mesh, int64_t *n_nodes_h, int64_t *n_list_h, int *depth_h)

@@ -120,6 +120,36 @@ def jittered_grid(n: int, seed: int, jitter: float = 0.2, x0=0.0, x1=1.0):
     return xy, grid_triangles(n)
 
 
+def _drop_cells(xy: np.ndarray, tri: np.ndarray, n: int, keep_cell):
+    """The triangles of the cells (l, m) with keep_cell(l, m) (grid_triangles
+    numbering: triangles 2c, 2c + 1 of cell c = (n-1) m + l), the unused nodes
+    removed and the rest renumbered in order."""
+    c = np.arange(tri.shape[0]) // 2
+    l, m = c % (n - 1), c // (n - 1)
+    t = tri[keep_cell(l, m)]
+    used = np.unique(t)
+    new = np.full(xy.shape[0], -1, dtype=np.int64)
+    new[used] = np.arange(used.size)
+    return np.ascontiguousarray(xy[used]), new[t].astype(np.int32)
+
+
+def l_shaped(n: int, seed: int, jitter: float = 0.2):
+    """The unit square without its upper-right quarter (an L, one reflex
+    corner at (1/2, 1/2)), from the jittered n x n grid (n odd); the nodes of
+    the notch's sides keep the jitter of interior nodes."""
+    xy, tri = jittered_grid(n, seed, jitter)
+    half = (n - 1) // 2
+    return _drop_cells(xy, tri, n, lambda l, m: ~((l >= half) & (m >= half)))
+
+
+def square_with_hole(n: int, seed: int, jitter: float = 0.2):
+    """The unit square without the square hole [3/8, 5/8]^2 (two boundary
+    loops), from the jittered n x n grid (n - 1 divisible by 8)."""
+    xy, tri = jittered_grid(n, seed, jitter)
+    a, b = 3 * (n - 1) // 8, 5 * (n - 1) // 8
+    return _drop_cells(xy, tri, n, lambda l, m: ~((l >= a) & (l < b) & (m >= a) & (m < b)))
+
+
 def _graded_S(rho, rho0, A, delta):
     return rho + A * np.tanh((rho - rho0) / delta) + A * np.tanh(rho0 / delta)
 

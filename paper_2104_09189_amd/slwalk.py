@@ -59,7 +59,8 @@ class slw_field(ctypes.Structure):
 class slw_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "feet", "outside", "walk_steps", "max_steps", "exact_tests", "fp64_tests", "fallback_walks",
-        "edge_ties", "vertex_ties")] + [("reserved", ctypes.c_int64 * 7), ("step_hist", ctypes.c_int64 * 16)]
+        "edge_ties", "vertex_ties", "boundary_searches")] + [("reserved", ctypes.c_int64 * 6),
+                                                             ("step_hist", ctypes.c_int64 * 16)]
 
     def as_dict(self):
         d = {n: int(getattr(self, n)) for n, _ in self._fields_ if n not in ("reserved", "step_hist")}
@@ -71,7 +72,7 @@ class slw_mesh_info(ctypes.Structure):
     _fields_ = [("n_nodes", ctypes.c_int64), ("n_tris", ctypes.c_int64), ("n_edges", ctypes.c_int64),
                 ("n_dofs", ctypes.c_int64), ("device_bytes", ctypes.c_int64), ("coords_f32", ctypes.c_int32),
                 ("p2", ctypes.c_int32), ("reordered", ctypes.c_int32), ("internal_order", ctypes.c_int32),
-                ("bbox", ctypes.c_double * 4)]
+                ("nonconvex", ctypes.c_int32), ("boundary_loops", ctypes.c_int32), ("bbox", ctypes.c_double * 4)]
 
 
 _vp = ctypes.c_void_p
@@ -294,6 +295,8 @@ class Mesh:
         self.coords_f32 = bool(info.coords_f32)
         self.p2 = bool(info.p2)
         self.internal_order = bool(info.internal_order)
+        self.nonconvex = bool(info.nonconvex)
+        self.boundary_loops = int(info.boundary_loops)
         self.bbox = tuple(info.bbox)
         self.cdtype = _torch().float32 if self.coords_f32 else _torch().float64
         self.chart_g = 0
@@ -732,7 +735,7 @@ def slw_mesh_check(xy, tri, flags: int = 0) -> dict:
     _check(_lib.slw_mesh_check(xy.ctypes.data_as(_vp), xy.shape[0], tri.ctypes.data_as(_vp), tri.shape[0], flags,
                                ctypes.byref(info)), "slw_mesh_check")
     return {"n_nodes": info.n_nodes, "n_tris": info.n_tris, "n_edges": info.n_edges, "n_dofs": info.n_dofs,
-            "bbox": tuple(info.bbox)}
+            "nonconvex": bool(info.nonconvex), "boundary_loops": int(info.boundary_loops), "bbox": tuple(info.bbox)}
 
 
 def slw_orient_sign_host(pts, mode: int = 0) -> np.ndarray:

@@ -98,6 +98,10 @@ def test_boundary_with_chart_start_and_rejections(S, C):
     mesh.set_repack(4)                              # ignored while boundary data are set
     v = host(mesh.step(I.constant(AX, AY), t_n, dt, S.SLW_EULER, dev(v0), start_mode=S.START_CHART))
     assert np.abs(v[:, 0] - _u(xy[:, 0], xy[:, 1], t_n + dt)).max() < 1e-12
+    # strategy (c) on the mesh forest applies boundary data; on chains it refuses
+    v = host(mesh.step(I.constant(AX, AY), t_n, dt, S.SLW_EULER, dev(v0), start_mode=S.START_NEIGHBOR))
+    assert np.abs(v[:, 0] - _u(xy[:, 0], xy[:, 1], t_n + dt)).max() < 1e-12
+    mesh.set_chain(4)
     with pytest.raises(S.SlwError):
         mesh.step(I.constant(AX, AY), t_n, dt, S.SLW_EULER, dev(v0), start_mode=S.START_NEIGHBOR)
     with pytest.raises(S.SlwError):

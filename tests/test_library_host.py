@@ -74,12 +74,22 @@ def test_invalid_meshes_are_rejected(S):
     assert _code(S, x3, tri) == "SLW_E_MESH_DEGENERATE"
     # a triangle listed twice: an edge in more than two triangles
     assert _code(S, xy, np.concatenate([tri, tri[:1]])) == "SLW_E_MESH_NONCONFORMING"
-    # a hole (one interior triangle removed): not a convex disk
+    # a hole (one interior triangle removed) and a reflex corner (one corner
+    # cell's triangle removed): accepted, marked non-convex
     n = 6
     hole = (n - 1) * 2 + 2
-    assert _code(S, xy, np.delete(tri, [2 * hole], axis=0)) == "SLW_E_MESH_NONCONVEX"
-    # a reflex corner: remove one corner cell's triangle
-    assert _code(S, xy, np.delete(tri, [1], axis=0)) == "SLW_E_MESH_NONCONVEX"
+    info = S.slw_mesh_check(xy, np.delete(tri, [2 * hole], axis=0))
+    assert info["nonconvex"] and info["boundary_loops"] == 2
+    info = S.slw_mesh_check(xy, np.delete(tri, [1], axis=0))
+    assert info["nonconvex"] and info["boundary_loops"] == 1
+    assert not S.slw_mesh_check(xy, tri)["nonconvex"]
+    # a boundary that passes twice through a node: two triangles meeting at a vertex only
+    xb = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0], [-1.0, 0.0], [0.0, -1.0]])
+    assert _code(S, xb, np.array([[0, 1, 2], [0, 3, 4]], np.int32)) == "SLW_E_MESH_NONCONVEX"
+    # the L and the square with a hole of the input generators
+    for xy2, tri2, loops in (I.l_shaped(17, 4) + (1,), I.square_with_hole(17, 5) + (2,)):
+        info = S.slw_mesh_check(xy2, tri2)
+        assert info["nonconvex"] and info["boundary_loops"] == loops
     # coordinates outside the exactness domain
     x4 = xy.copy()
     x4[0, 0] = np.nan
