@@ -353,13 +353,29 @@ def measure_learned(alpha=50.0, n=1415, k=16, steps=10, samples_per_step=200_000
     net = S.Mlp(ctx, seed=0)
     net.fit_normalization(X)
     t0 = time.perf_counter()
-    plan = [(3e-3, 4096, 8), (1e-3, 4096, 4)]
+    # minibatches of 65,536 samples (each fills the device: 1,024 workgroups)
+    plan = [(3e-3, 65536, 24), (1e-3, 65536, 12)]
     for i, (lr, bs, ep) in enumerate(plan):
         loss = net.train(X, Y, epochs=ep, batch=bs, lr=lr, seed=seed + i)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     mesh.attach_mlp(net)
     del X, Y
+    # the network's error on fresh feet (a step it was not trained on), in
+    # chart cells: how far its proposal lands from the foot's element
+    ids = torch.from_numpy(rng.integers(0, nd, 200_000).astype(np.int32)).to("cuda:0")
+    Xe = torch.empty((ids.shape[0], 5), dtype=torch.float32, device="cuda:0")
+    Ye = torch.empty((ids.shape[0], 2), dtype=torch.float32, device="cuda:0")
+    mesh.learned_gather(w.field, (train_steps + 3.5) * w.dt, w.dt, w.scheme, ids, Xe, Ye)
+    pe = net.forward(Xe).cpu().numpy()
+    ye = Ye.cpu().numpy()
+    ok = np.isfinite(ye[:, 0])
+    err = np.abs(pe[ok] - ye[ok]) * g
+    net_error = {"samples": int(ok.sum()), "unit": "chart cells (1/G)",
+                 "du": {q: float(np.percentile(err[:, 0], p)) for q, p in (("p50", 50), ("p90", 90), ("p99", 99))},
+                 "dv": {q: float(np.percentile(err[:, 1], p)) for q, p in (("p50", 50), ("p90", 90), ("p99", 99))},
+                 "rms_chart_units": float(np.sqrt(np.mean((pe[ok] - ye[ok]) ** 2)))}
+    del Xe, Ye
     v0 = torch.from_numpy(np.ascontiguousarray(w.v0[mesh.dof_order()])).to("cuda:0")
     stream = torch.cuda.current_stream()
     t_n = 7 * w.dt
@@ -388,6 +404,7 @@ def measure_learned(alpha=50.0, n=1415, k=16, steps=10, samples_per_step=200_000
             "alpha": w.extra.get("alpha", alpha),
             "k_fields": k, "chart_g": g, "chart_build_s": chart_s, "training_samples": m,
             "gather_s": gather_s, "train_s": train_s, "train_plan": plan, "final_minibatch_loss": loss,
+            "network_error": net_error,
             "starts": res, "identical_bits": identical,
             "speedup_learned_vs_plain": base / res["learned"]["ms_per_step"],
             "speedup_learned_index_vs_plain": base / res["learned_index"]["ms_per_step"],

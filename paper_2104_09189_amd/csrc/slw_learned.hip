@@ -212,15 +212,35 @@ __global__ void __launch_bounds__(64)
 }
 
 // out[e] = sum over workgroups b, in order, of partial[b][e]
-__global__ void k_mlp_reduce(const float *__restrict__ partial, int nb, float *__restrict__ out, int n)
+// Sum of the nb partial gradients, entry by entry, in a fixed order: a
+// workgroup takes 64 consecutive entries; its 4 wavefronts each add every
+// 4th partial (8 loads in flight per lane), then the four sums are added in
+// wavefront order.
+__global__ void __launch_bounds__(256) k_mlp_reduce(const float *__restrict__ partial, int nb, float *__restrict__ out,
+                                                    int n)
 {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n)
-        return;
+    __shared__ float s4[4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int e = blockIdx.x * 64 + lane;
     float s = 0.f;
-    for (int b = 0; b < nb; ++b)
-        s += partial[(int64_t)b * kPartialStride + e];
-    out[e] = s;
+    if (e < n) {
+        int b = wv;
+        for (; b + 28 < nb; b += 32) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                v[u] = partial[(int64_t)(b + 4 * u) * kPartialStride + e];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                s += v[u];
+        }
+        for (; b < nb; b += 4)
+            s += partial[(int64_t)b * kPartialStride + e];
+    }
+    s4[wv][lane] = s;
+    __syncthreads();
+    if (wv == 0 && e < n)
+        out[e] = ((s4[0][lane] + s4[1][lane]) + s4[2][lane]) + s4[3][lane];
 }
 
 // Adam with bias corrections c1 = 1 - b1^t, c2 = 1 - b2^t
@@ -282,34 +302,58 @@ __global__ void __launch_bounds__(kBlock)
         out[i] = uv;
 }
 
-// feature means and inverse standard deviations (one workgroup per feature,
-// FP64 sums)
-__global__ void __launch_bounds__(kBlock) k_fit_norm(const float *__restrict__ X, int64_t m, float *__restrict__ norm)
+// feature means and inverse standard deviations: per-workgroup FP64 sums of
+// x and x^2 of every feature over a contiguous slice of the samples
+// (kNormParts workgroups), then one workgroup adds the partial sums in a
+// fixed order (bit-reproducible)
+constexpr int kNormParts = 512;
+__global__ void __launch_bounds__(kBlock) k_fit_norm_partial(const float *__restrict__ X, int64_t m,
+                                                             double *__restrict__ part)
 {
-    __shared__ double s1[kBlock], s2[kBlock];
-    const int c = blockIdx.x;
-    double a = 0.0, b = 0.0;
-    for (int64_t i = threadIdx.x; i < m; i += kBlock) {
-        const double x = X[5 * i + c];
-        a += x;
-        b += x * x;
+    __shared__ double s[10][kBlock];
+    const int64_t per = (m + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)blockIdx.x * per, hi = min(m, lo + per);
+    double a[5] = {0, 0, 0, 0, 0}, b[5] = {0, 0, 0, 0, 0};
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            const double x = X[5 * i + c];
+            a[c] += x;
+            b[c] += x * x;
+        }
     }
-    s1[threadIdx.x] = a;
-    s2[threadIdx.x] = b;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        s[c][threadIdx.x] = a[c];
+        s[5 + c][threadIdx.x] = b[c];
+    }
     __syncthreads();
     for (int off = kBlock / 2; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) {
-            s1[threadIdx.x] += s1[threadIdx.x + off];
-            s2[threadIdx.x] += s2[threadIdx.x + off];
-        }
+        if ((int)threadIdx.x < off)
+#pragma unroll
+            for (int c = 0; c < 10; ++c)
+                s[c][threadIdx.x] += s[c][threadIdx.x + off];
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        const double mean = m > 0 ? s1[0] / (double)m : 0.0;
-        const double var = m > 0 ? fmax(s2[0] / (double)m - mean * mean, 0.0) : 0.0;
-        norm[c] = (float)mean;
-        norm[5 + c] = var > 0.0 ? (float)(1.0 / sqrt(var)) : 1.0f;
+    if (threadIdx.x < 10)
+        part[10 * blockIdx.x + threadIdx.x] = s[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(64) k_fit_norm_final(const double *__restrict__ part, int parts, int64_t m,
+                                                       float *__restrict__ norm)
+{
+    const int c = threadIdx.x;
+    if (c >= 5)
+        return;
+    double a = 0.0, b = 0.0;
+    for (int p = 0; p < parts; ++p) {
+        a += part[10 * p + c];
+        b += part[10 * p + 5 + c];
     }
+    const double mean = m > 0 ? a / (double)m : 0.0;
+    const double var = m > 0 ? fmax(b / (double)m - mean * mean, 0.0) : 0.0;
+    norm[c] = (float)mean;
+    norm[5 + c] = var > 0.0 ? (float)(1.0 / sqrt(var)) : 1.0f;
 }
 
 uint64_t splitmix64(uint64_t &s)
@@ -331,14 +375,15 @@ slw_status gradient_pass(slw_mlp *n, const float *X, const float *Y, int64_t m, 
 {
     hipStream_t st = n->ctx->stream;
     // about 64 samples per workgroup, at most kMlpPartials workgroups (a
-    // function of count only: the sums stay bit-reproducible)
+    // function of count only: the sums stay bit-reproducible); minibatches
+    // of 65,536 samples fill the device
     const int nb = (int)std::min<int64_t>(kMlpPartials, std::max<int64_t>(1, (count + 63) / 64));
     hipLaunchKernelGGL(k_mlp_partial, dim3(nb), dim3(64), 0, st, n->params, n->norm, X, (const float2 *)Y, m, first,
                        count, pa, pc, inv_batch, n->partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return hip_check(e, "gradient partials");
-    hipLaunchKernelGGL(k_mlp_reduce, dim3((kPartialStride + 255) / 256), dim3(256), 0, st, n->partial, nb, n->grad,
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((kPartialStride + 63) / 64), dim3(256), 0, st, n->partial, nb, n->grad,
                        kPartialStride);
     return hip_check(hipGetLastError(), "gradient reduction");
 }
@@ -663,7 +708,15 @@ slw_status slw_mlp_fit_normalization(slw_mlp *n, const float *X, int64_t m)
     if (!n || m < 1 || !X)
         return set_error(SLW_E_ARG, "slw_mlp_fit_normalization: null pointer or no samples");
     DeviceGuard gd(n->ctx->device);
-    hipLaunchKernelGGL(k_fit_norm, dim3(5), dim3(kBlock), 0, n->ctx->stream, X, m, n->norm);
+    // the partial sums live in the gradient partials' workspace (idle here)
+    double *part = (double *)n->partial;
+    static_assert((size_t)kNormParts * 10 * sizeof(double) <= (size_t)kMlpPartials * kPartialStride * sizeof(float),
+                  "normalisation partials fit the gradient workspace");
+    hipLaunchKernelGGL(k_fit_norm_partial, dim3(kNormParts), dim3(kBlock), 0, n->ctx->stream, X, m, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return hip_check(e, "slw_mlp_fit_normalization");
+    hipLaunchKernelGGL(k_fit_norm_final, dim3(1), dim3(64), 0, n->ctx->stream, part, kNormParts, m, n->norm);
     return hip_check(hipGetLastError(), "slw_mlp_fit_normalization");
 }
 
