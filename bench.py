@@ -531,6 +531,8 @@ def main():
     ap.add_argument("--only-b", action="store_true",
                     help="measure strategy (b) only (a short line, for hardware-counter runs)")
     ap.add_argument("--no-batch", action="store_true", help="skip the multi-mesh batch measurement")
+    ap.add_argument("--only-batch", action="store_true",
+                    help="measure the multi-mesh batch only (a short line, for hardware-counter runs)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-start measurement")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -556,6 +558,9 @@ def main():
     from paper_2104_09189_amd import inputs as I
     from paper_2104_09189_amd import slwalk as S
 
+    if args.only_batch:
+        print(json.dumps({"batch": measure_batch()}), flush=True)
+        return
     w = I.graded_swirl(alpha=args.alpha, n=args.n, k_fields=args.k)
     ctx = S.Context(0)
     t0 = time.perf_counter()

@@ -57,6 +57,7 @@ struct DevMesh {
     GeoRec *geo = nullptr;        // [n_tris]
     WalkRec *wrec = nullptr;      // [n_tris] the walk's copy of geo (packed neighbours)
     int code_bits = kCodeBits;    // widest neighbour offset coded in wrec (narrower: more escapes)
+    int4 *tri_v = nullptr;        // [n_tris] {nb[2], v[0], v[1], v[2]} of geo, compact (read where walks end)
     int32_t *tri_uf = nullptr;    // [n_tris] user id | (1 << 31 if vertices 1, 2 were swapped to make it CCW)
     int4 *tedge = nullptr;        // [n_tris] P2: internal DOF ids of the edge opposite vertex k
     void *dof_xy = nullptr;       // double2/float2 [n_dofs], exact coordinates
@@ -239,6 +240,7 @@ struct ForestView {
 struct MeshView {
     const GeoRec *geo;
     const WalkRec *wrec;
+    const int4 *tri_v;
     const int32_t *tri_uf;
     const int4 *tedge;
     const void *dof_xy;

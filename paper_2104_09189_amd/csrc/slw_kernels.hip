@@ -130,6 +130,7 @@ MeshView view_of(const DevMesh &m)
     MeshView v;
     v.geo = m.geo;
     v.wrec = m.wrec;
+    v.tri_v = m.tri_v;
     v.tri_uf = m.tri_uf;
     v.tedge = m.tedge;
     v.dof_xy = m.dof_xy;
@@ -337,7 +338,12 @@ __device__ inline int32_t nb_of(const MeshView &mv, int32_t j, int k, int32_t co
 }
 
 // {nb[2], v[0], v[1], v[2]} of triangle j: the vertex ids with one load
-__device__ inline int4 tri_verts(const MeshView &mv, int32_t j) { return ((const int4 *)(mv.geo + j))[2]; }
+// {nb[2], v[0], v[1], v[2]} of triangle j: the vertex ids with one load, from
+// the compact 16-byte copy (a walk's end reads eight triangles per cache
+// line instead of the 48-byte records' two or three)
+__device__ inline int4 tri_verts(const MeshView &mv, int32_t j) { return mv.tri_v[j]; }
+// the same four ids inside the 48-byte record, for reads of the whole record
+__device__ inline int4 geo_verts(const MeshView &mv, int32_t j) { return ((const int4 *)(mv.geo + j))[2]; }
 
 __device__ inline int32_t sel3(int k, int32_t a, int32_t b, int32_t c) { return k == 0 ? a : (k == 1 ? b : c); }
 
@@ -664,7 +670,7 @@ __device__ inline int first_test(const MeshView &mv, int32_t j, typename CT<F32>
     const float qfy = F32 ? (float)qy : (float)((double)qy - mv.fc.cy);
     const float4 p01 = ((const float4 *)(mv.geo + j))[0];
     const float2 p2 = ((const float2 *)(mv.geo + j))[2];
-    const int4 tv = tri_verts(mv, j);  // {nb[2], v[0], v[1], v[2]}
+    const int4 tv = geo_verts(mv, j);  // {nb[2], v[0], v[1], v[2]}
     const float2 pj[3] = {make_float2(p01.x, p01.y), make_float2(p01.z, p01.w), p2};
     float o[3];
     int s[3];
@@ -698,7 +704,7 @@ __device__ WalkResult<typename CT<F32>::R> walk(const MeshView &mv, int32_t j, t
     if (likely_stop) {
         const float4 p01 = ((const float4 *)(mv.geo + j))[0];
         const float2 p2 = ((const float2 *)(mv.geo + j))[2];
-        const int4 tv = tri_verts(mv, j);  // {nb[2], v[0], v[1], v[2]}
+        const int4 tv = geo_verts(mv, j);  // {nb[2], v[0], v[1], v[2]}
         const float2 pj[3] = {make_float2(p01.x, p01.y), make_float2(p01.z, p01.w), p2};
         float o[3];
         int s[3];

@@ -185,7 +185,7 @@ std::vector<WalkRec> walk_records(const std::vector<GeoRec> &geo, int bits)
 
 void free_mesh(DevMesh &m)
 {
-    void *ptrs[] = {m.geo, m.wrec, m.tri_uf, m.tedge, m.dof_xy, m.qstart, m.vmin, m.dof_user,
+    void *ptrs[] = {m.geo, m.wrec, m.tri_v, m.tri_uf, m.tedge, m.dof_xy, m.qstart, m.vmin, m.dof_user,
                     m.dof_int, m.tri_int, m.prev_elem, m.jump, m.chart_uv, m.chart_node, m.chart_table,
                     m.chart_qx, m.chart_qy, m.learned_start, m.bnext, m.bprev, m.qt_nodes, m.qt_lists,
                     m.forest_list1, m.forest_out1, m.forest_parent1, m.forest_list2, m.forest_out2,
@@ -607,6 +607,10 @@ slw_status build_mesh(slw_ctx *ctx, const double *xy, int64_t n, const int32_t *
     {
         std::vector<WalkRec> wr = walk_records(geo, kCodeBits);
         UP(wr, m.wrec);
+        std::vector<int4> tv(nt);
+        for (int64_t t = 0; t < nt; ++t)
+            tv[t] = make_int4(geo[t].nb[2], geo[t].v[0], geo[t].v[1], geo[t].v[2]);
+        UP(tv, m.tri_v);
     }
     UP(tri_uf, m.tri_uf);
     if (f32) {
