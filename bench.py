@@ -533,6 +533,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the multi-mesh batch measurement")
     ap.add_argument("--only-batch", action="store_true",
                     help="measure the multi-mesh batch only (a short line, for hardware-counter runs)")
+    ap.add_argument("--only-learned", action="store_true",
+                    help="measure the learned start on the graded mesh only (training included; for traces)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-start measurement")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -560,6 +562,9 @@ def main():
 
     if args.only_batch:
         print(json.dumps({"batch": measure_batch()}), flush=True)
+        return
+    if args.only_learned:
+        print(json.dumps({"learned": measure_learned()}), flush=True)
         return
     w = I.graded_swirl(alpha=args.alpha, n=args.n, k_fields=args.k)
     ctx = S.Context(0)

@@ -486,3 +486,62 @@ def test_variable_step_reproduces_the_exact_solution(orc, scheme):
     # without boundary data those nodes get the outside value instead
     v2, _, _, _ = orc.sl_step(xy, tri, v0, I.constant(ax, ay), t_n, dt, scheme, outside_value=-5.0)
     assert (v2[elem < 0] == -5.0).all()
+
+
+def _first_exit_closed_form(x, q, holes):
+    """First parameter s in [0, 1] at which x + s (q - x) leaves the closed
+    set [0, 1]^2 minus the open boxes in holes ((x0, x1, y0, y1) each):
+    the smallest of the exit from the square and the entry into each box
+    (the segment is inside an open box on the intersection of the two open
+    intervals of s where each coordinate lies strictly between its bounds)."""
+    w = q - x
+    with np.errstate(divide="ignore", invalid="ignore"):
+        sq = np.stack([np.where(w[:, 0] > 0, (1 - x[:, 0]) / w[:, 0], np.inf),
+                       np.where(w[:, 0] < 0, (0 - x[:, 0]) / w[:, 0], np.inf),
+                       np.where(w[:, 1] > 0, (1 - x[:, 1]) / w[:, 1], np.inf),
+                       np.where(w[:, 1] < 0, (0 - x[:, 1]) / w[:, 1], np.inf)], axis=1).min(axis=1)
+        best = np.where(sq <= 1, sq, np.inf)
+        for (x0, x1, y0, y1) in holes:
+            lo, hi = np.zeros(len(x)), np.ones(len(x))
+            for k, (a, b) in enumerate(((x0, x1), (y0, y1))):
+                ta, tb = (a - x[:, k]) / w[:, k], (b - x[:, k]) / w[:, k]
+                t0, t1 = np.minimum(ta, tb), np.maximum(ta, tb)
+                inside_const = (x[:, k] > a) & (x[:, k] < b)
+                t0 = np.where(w[:, k] == 0, np.where(inside_const, -np.inf, np.inf), t0)
+                t1 = np.where(w[:, k] == 0, np.where(inside_const, np.inf, -np.inf), t1)
+                lo, hi = np.maximum(lo, t0), np.minimum(hi, t1)
+            best = np.where(lo < hi, np.minimum(best, lo), best)
+    return np.where(np.isfinite(best), best, np.nan)
+
+
+@pytest.mark.parametrize("name", ["L", "hole"])
+def test_boundary_crossing_first_exit_on_nonconvex_domains(orc, name):
+    """Unjittered L-shaped and holed squares have closed-form boundaries:
+    the oracle's first exit (over every boundary edge) equals the first
+    parameter at which the segment leaves [0, 1]^2 or enters the removed
+    open box, also for segments that leave and re-enter the domain; the
+    boundary edge count is the perimeter in cells."""
+    if name == "L":
+        xy, tri = I.l_shaped(17, 3, jitter=0.0)
+        holes, nb = [(0.5, 1.0, 0.5, 1.0)], 4 * 16
+    else:
+        xy, tri = I.square_with_hole(17, 3, jitter=0.0)
+        holes, nb = [(0.375, 0.625, 0.375, 0.625)], 4 * 16 + 4 * 4
+    e = orc.boundary_edges(xy, tri)
+    assert e.shape[0] == nb
+    rng = np.random.default_rng(23)
+    x = rng.uniform(0.02, 0.98, (4000, 2))
+    for (x0, x1, y0, y1) in holes:                   # starts in the closed domain, off its boundary
+        x = x[~((x[:, 0] > x0 - 0.01) & (x[:, 0] < x1 + 0.01) & (x[:, 1] > y0 - 0.01) & (x[:, 1] < y1 + 0.01))]
+    q = x + rng.normal(0, 0.5, x.shape)
+    theta, p = orc.boundary_crossing(xy, e, x, q)
+    ref = _first_exit_closed_form(x, q, holes)
+    assert np.array_equal(np.isnan(theta), np.isnan(ref))
+    ok = ~np.isnan(ref)
+    assert ok.sum() > 1000 and (~ok).sum() > 100
+    assert np.abs(theta[ok] - ref[ok]).max() < 1e-12
+    # some segments cross the removed box and end inside the domain again
+    back = ok & ~((q < 0) | (q > 1)).any(axis=1)
+    for (x0, x1, y0, y1) in holes:
+        back &= ~((q[:, 0] > x0) & (q[:, 0] < x1) & (q[:, 1] > y0) & (q[:, 1] < y1))
+    assert back.sum() > 20
