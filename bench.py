@@ -456,12 +456,12 @@ def measure_courant_range(mesh, w, v0, steps=20, warmup=3, alphas=(1.0, 5.0, 20.
         for name, mode in (("a_steered", S.START_STEERED), ("b_previous", S.START_PREV),
                            ("c_forest", S.START_NEIGHBOR), ("chart_exact", S.START_CHART),
                            ("hybrid", S.START_HYBRID)):
-            tuned = None
-            if mode == S.START_HYBRID:
-                # the threshold of the per-foot choice, picked by the autotuner
-                # (previous elements from the step before)
-                mesh.step(wa.field, 6 * dt, dt, wa.scheme, v0, start_mode=mode)
-                tuned = mesh.autotune_step(wa.field, 7 * dt, dt, wa.scheme, v0, start_mode=mode)
+            # the library's defaults: one foot per lane, the forest, hybrid
+            # threshold 8, chunks of 64 tiles per XCD turn
+            mesh.set_repack(0)
+            mesh.set_chain(0)
+            mesh.set_hybrid(8.0)
+            mesh.set_xcd_chunk(64)
             r = measure(mesh, wa, v0, steps, warmup, mode)
             # walk lengths of the step ending near t = 1/4 (the swirl's time
             # factor cos(pi t) is 0.7 there; it vanishes at t = 1/2)
@@ -471,8 +471,20 @@ def measure_courant_range(mesh, w, v0, steps=20, warmup=3, alphas=(1.0, 5.0, 20.
                           "roofline_frac": abytes / (r["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
                           "mean_walk_steps": ww["mean"], "mean_wavefront_max": ww["mean_wavefront_max"],
                           "p99": ww["p99"], "max": ww["max"]}
-            if tuned is not None:
-                line[name]["tuned_hybrid_far"] = tuned[0]
+            # the same after slw_step_autotune (the mode's knob, then the XCD
+            # chunk), timed on the step from 7 dt (previous elements from the
+            # step before)
+            if mode in (S.START_PREV, S.START_HYBRID):
+                mesh.step(wa.field, 6 * dt, dt, wa.scheme, v0, start_mode=mode)
+            knob, chunk, _ = mesh.autotune_step(wa.field, 7 * dt, dt, wa.scheme, v0, start_mode=mode,
+                                                with_chunk=True)
+            rt = measure(mesh, wa, v0, steps, warmup, mode)
+            line[name]["tuned"] = {"knob": knob, "xcd_chunk": chunk, "ms_per_step": rt["ms_per_step"],
+                                   "kernel_ms": rt["kernel_ms"]}
+        mesh.set_repack(0)
+        mesh.set_chain(0)
+        mesh.set_hybrid(8.0)
+        mesh.set_xcd_chunk(64)
         out[f"alpha_{alpha:g}"] = line
     return out
 
@@ -603,6 +615,9 @@ def main():
         "config": {"workload": w.name, "n_nodes": int(n_feet), "n_tris": int(mesh.n_tris), "alpha": args.alpha,
                    "k_fields": args.k, "coords": "f64", "values": "f32", "order": 1, "scheme": "rk2",
                    "start": "strategy (a): incident triangle facing the foot", "parallelism": "none (1 GPU)"},
+        "schedule": {"feet_per_lane": 1, "xcd_chunk": 64,
+                     "note": "library defaults: one foot per lane; chunks of 64 tiles of 256 nodes dealt to the "
+                             "8 XCDs in turn"},
         "field_values_per_s": value * args.k,
         "mean_walk_steps": st["walk_steps"] / max(st["feet"], 1),
         "walk": {**{k: st[k] for k in ("max_steps", "outside", "exact_tests", "fp64_tests", "fallback_walks",

@@ -270,6 +270,16 @@ slw_status slw_mesh_set_boundary(slw_mesh *mesh, int kind, const double *p_h);
  *     SLW_E_UNSUPPORTED).
  * Results never depend on the forest. */
 slw_status slw_mesh_set_chain(slw_mesh *mesh, int length);
+
+/* Schedule knob: how the tiles of 256 consecutive internal-order DOFs are
+ * spread over the 8 XCDs (workgroups go to the XCDs in turn).  chunk 0: one
+ * contiguous range of tiles per XCD (locality in each XCD's L2); chunk C in
+ * 1 ... 4096: chunks of C consecutive tiles dealt to the XCDs in turn (even
+ * work per XCD where walk lengths differ between regions of the mesh).
+ * Default 64.  Applies to the step, location and interpolation kernels of
+ * this mesh, not to batches.  Results never depend on it;
+ * SLW_E_ARG outside 0 ... 4096. */
+slw_status slw_mesh_set_xcd_chunk(slw_mesh *mesh, int chunk);
 /* The per-foot choice of SLW_START_HYBRID, after the hybrid idea that closes
  * the numerical section (Section 4) of the paper: the start is chosen from
  * the local dynamics, i.e. from how far the foot moved since the previous
@@ -327,9 +337,11 @@ slw_status slw_step(slw_mesh *mesh, const slw_field *field, double t_n, double d
  * per lane) for the steered, given, fixed, previous, chart and learned
  * starts; the threshold of slw_mesh_set_hybrid (2 ... 64) for
  * SLW_START_HYBRID; the forest or chain length of slw_mesh_set_chain (0, 2,
- * 4, 8, 16) for SLW_START_NEIGHBOR -- each over five launches (the median),
- * keeps only candidates whose step is bit-identical to the one of the
- * mesh's current setting, applies the fastest to the mesh and records it in
+ * 4, 8, 16) for SLW_START_NEIGHBOR -- then, for the value chosen, the XCD
+ * chunk of slw_mesh_set_xcd_chunk (0, 16, 32, 64, 128); each candidate over
+ * five launches (the median).  It keeps only candidates whose step is
+ * bit-identical to the one of the mesh's current setting, applies the
+ * fastest to the mesh and records it in
  * the JSON file cache_path (nullable) under a signature of the step (size,
  * types, k, order, start mode, scheme, and the walk-length regime: the
  * mean walk of strategy (a) on this step, in powers of two); a later call
@@ -337,12 +349,12 @@ slw_status slw_step(slw_mesh *mesh, const slw_field *field, double t_n, double d
  * cached value without timing.  Every candidate starts from the mesh's
  * current previous elements (SLW_START_PREV, SLW_START_HYBRID), which are
  * restored afterwards; the caller's v_in is only read.  Allocates a private
- * output buffer; synchronous.  value_out / ms_out (nullable): the value
- * chosen and its median time per step (ms; the cached time when the cache
- * answered). */
+ * output buffer; synchronous.  value_out / xcd_chunk_out / ms_out
+ * (nullable): the knob value and XCD chunk chosen and their median time per
+ * step (ms; the cached time when the cache answered). */
 slw_status slw_step_autotune(slw_mesh *mesh, const slw_field *field, double t_n, double dt, int scheme, int order,
                              int start_mode, const int32_t *start, const void *v_in, int vdtype, int k,
-                             const char *cache_path, double *value_out, double *ms_out);
+                             const char *cache_path, double *value_out, int32_t *xcd_chunk_out, double *ms_out);
 
 /* slw_step for callers that cannot allocate device memory: code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
@@ -374,7 +386,9 @@ slw_status slw_permute_rows(slw_mesh *mesh, const void *src, void *dst, int64_t 
  * as slw_step with SLW_START_STEERED would).  Work items are the meshes'
  * 256-DOF tiles (block-sized tiles), concatenated; schedule 0 gives each
  * workgroup one tile in an XCD-contiguous order, schedule 1 runs persistent
- * workgroups that pull tiles from per-XCD queues.  The step index lives on
+ * workgroups that pull tiles from per-XCD queues, schedule 2 gives each
+ * workgroup one tile with chunks of 16,384 DOFs' tiles dealt to the XCDs in
+ * turn.  The step index lives on
  * the device: step n of mesh i advances its values from t0_i + n dt_i to
  * t0_i + (n + 1) dt_i, reading va_i and writing vb_i when n is even and the
  * reverse when n is odd, then the index is incremented -- so a captured
@@ -399,7 +413,8 @@ slw_status slw_batch_set_elem_out(slw_batch *b, int32_t *const *elem_h);
 /* set / read the device step index (both synchronise the context's stream) */
 slw_status slw_batch_set_step(slw_batch *b, int64_t n);
 slw_status slw_batch_get_step(slw_batch *b, int64_t *n_h);
-/* schedule 0 (static, XCD-contiguous) or 1 (persistent queues); workgroup size 64, 128, 256 or 512 */
+/* schedule 0 (static, XCD-contiguous), 1 (persistent queues) or 2 (static, XCD chunks); workgroup size
+ * 64, 128, 256 or 512 */
 slw_status slw_batch_set_schedule(slw_batch *b, int schedule, int block);
 /* one step of every mesh (asynchronous unless stats_h is given) */
 slw_status slw_batch_step(slw_batch *b, int scheme, double outside_value, slw_stats *stats_h);

@@ -454,6 +454,16 @@ slw_status slw_mesh_set_hybrid(slw_mesh *mesh, float far)
     return SLW_OK;
 }
 
+slw_status slw_mesh_set_xcd_chunk(slw_mesh *mesh, int chunk)
+{
+    if (!mesh)
+        return set_error(SLW_E_ARG, "mesh is NULL");
+    if (chunk < 0 || chunk > 4096)
+        return set_error(SLW_E_ARG, "slw_mesh_set_xcd_chunk: chunk must be 0 ... 4096");
+    mesh->m.xcd_chunk = chunk;
+    return SLW_OK;
+}
+
 slw_status slw_mesh_set_chain(slw_mesh *mesh, int length)
 {
     if (!mesh)
@@ -818,8 +828,8 @@ slw_status slw_batch_get_step(slw_batch *b, int64_t *n_h)
 
 slw_status slw_batch_set_schedule(slw_batch *b, int schedule, int block)
 {
-    if (!b || (schedule != 0 && schedule != 1) || (block != 64 && block != 128 && block != 256 && block != 512))
-        return set_error(SLW_E_ARG, "slw_batch_set_schedule: schedule 0/1, block 64/128/256/512");
+    if (!b || (schedule < 0 || schedule > 2) || (block != 64 && block != 128 && block != 256 && block != 512))
+        return set_error(SLW_E_ARG, "slw_batch_set_schedule: schedule 0/1/2, block 64/128/256/512");
     b->schedule = schedule;
     b->block = block;
     DeviceGuard g(b->ctx->device);
@@ -946,7 +956,7 @@ bool cache_lookup(const char *path, const std::string &sig, int &schedule, int &
         return false;
     schedule = std::atoi(txt.c_str() + s1 + 11);
     block = std::atoi(txt.c_str() + b1 + 8);
-    return (schedule == 0 || schedule == 1) && (block == 64 || block == 128 || block == 256 || block == 512);
+    return (schedule >= 0 && schedule <= 2) && (block == 64 || block == 128 || block == 256 || block == 512);
 }
 
 void cache_store(const char *path, const std::string &sig, int schedule, int block, double ms)
@@ -1034,14 +1044,14 @@ extern "C" slw_status slw_batch_autotune(slw_batch *b, int scheme, const char *c
     int best_s = saved_schedule, best_b = saved_block;
     bool have_ref = false;
     std::vector<char> ref_h, out_h;
-    const int schedules[2] = {0, 1};
+    const int schedules[3] = {0, 1, 2};
     const int blocks[4] = {64, 128, 256, 512};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (st == SLW_OK)
         st = hip_check(hipEventCreate(&e0), "hipEventCreate");
     if (st == SLW_OK)
         st = hip_check(hipEventCreate(&e1), "hipEventCreate");
-    for (int si = 0; si < 2 && st == SLW_OK; ++si)
+    for (int si = 0; si < 3 && st == SLW_OK; ++si)
         for (int bi = 0; bi < 4 && st == SLW_OK; ++bi) {
             b->schedule = schedules[si];
             b->block = blocks[bi];
@@ -1184,6 +1194,9 @@ const char *knob_name(int mode)
     return "feet_per_lane";
 }
 
+// XCD chunks the step autotuner tries (slw_mesh_set_xcd_chunk)
+constexpr int kXcdChunks[] = {0, 16, 32, 64, 128};
+
 std::vector<double> knob_values(int mode, bool bc)
 {
     if (mode == SLW_START_HYBRID)
@@ -1219,7 +1232,7 @@ void knob_set(DevMesh &m, int mode, double v)
 extern "C" slw_status slw_step_autotune(slw_mesh *mesh, const slw_field *field, double t_n, double dt, int scheme,
                                         int order, int start_mode, const int32_t *start, const void *v_in,
                                         int vdtype, int k, const char *cache_path, double *value_out,
-                                        double *ms_out)
+                                        int32_t *xcd_chunk_out, double *ms_out)
 {
     if (!mesh || !v_in)
         return set_error(SLW_E_ARG, "slw_step_autotune: mesh or v_in is NULL");
@@ -1230,6 +1243,7 @@ extern "C" slw_status slw_step_autotune(slw_mesh *mesh, const slw_field *field, 
     const size_t vsz = vdtype == SLW_F64 ? 8 : 4;
     const size_t bytes = (size_t)rows * (size_t)(k > 0 ? k : 1) * vsz;
     const double saved = knob_get(m, start_mode);
+    const int saved_chunk = m.xcd_chunk;
     const bool keeps_prev = start_mode == SLW_START_PREV || start_mode == SLW_START_HYBRID;
     void *vout = nullptr;
     int32_t *prev0 = nullptr;
@@ -1310,21 +1324,23 @@ extern "C" slw_status slw_step_autotune(slw_mesh *mesh, const slw_field *field, 
                 if (st != SLW_OK)
                     return st;
                 knob_set(m, start_mode, cached);
+                double cc = 0.0;
+                if (cache_lookup_num(cache_path, sig, "xcd_chunk", cc) && cc >= 0.0 && cc <= 4096.0)
+                    m.xcd_chunk = (int)cc;
                 if (value_out)
                     *value_out = cached;
+                if (xcd_chunk_out)
+                    *xcd_chunk_out = m.xcd_chunk;
                 if (ms_out)
                     *ms_out = cms;
                 return SLW_OK;
             }
         }
     }
-    double best_v = saved, best_ms = 1e300;
-    for (double v : knob_values(start_mode, m.bc_kind != 0 || m.nonconvex != 0)) {
-        if (st != SLW_OK)
-            break;
-        knob_set(m, start_mode, v);
-        // parity guard: the candidate's step from the same state must give
-        // the reference's bits
+    // one candidate (the knobs as set on the mesh): its step from the same
+    // state must give the reference's bits (else it is never chosen); then
+    // five launches, each from the caller's previous elements; the median
+    auto time_candidate = [&](float &median) -> bool {
         st = restore_prev();
         if (st == SLW_OK)
             st = step_impl(mesh, field, t_n, dt, scheme, order, start_mode, start, v_in, vdtype, k, vout, 0.0,
@@ -1333,11 +1349,8 @@ extern "C" slw_status slw_step_autotune(slw_mesh *mesh, const slw_field *field, 
             out_h.resize(bytes);
             st = hip_check(hipMemcpy(out_h.data(), vout, bytes, hipMemcpyDeviceToHost), "copy candidate");
         }
-        if (st != SLW_OK)
-            break;
-        if (std::memcmp(out_h.data(), ref_h.data(), bytes) != 0)
-            continue;  // never chosen
-        // timing: five launches, each from the caller's previous elements; the median
+        if (st != SLW_OK || std::memcmp(out_h.data(), ref_h.data(), bytes) != 0)
+            return false;
         std::vector<float> ts;
         for (int r = 0; r < 5 && st == SLW_OK; ++r) {
             st = restore_prev();
@@ -1356,11 +1369,38 @@ extern "C" slw_status slw_step_autotune(slw_mesh *mesh, const slw_field *field, 
             ts.push_back(ms);
         }
         if (st != SLW_OK)
-            break;
+            return false;
         std::sort(ts.begin(), ts.end());
-        if (ts[2] < best_ms) {
-            best_ms = ts[2];
+        median = ts[2];
+        return true;
+    };
+    // first the mode's own knob (at the mesh's XCD chunk), then the XCD chunk
+    // for the chosen value
+    double best_v = saved, best_ms = 1e300;
+    int best_c = saved_chunk;
+    for (double v : knob_values(start_mode, m.bc_kind != 0 || m.nonconvex != 0)) {
+        if (st != SLW_OK)
+            break;
+        knob_set(m, start_mode, v);
+        float ms = 0.f;
+        if (time_candidate(ms) && ms < best_ms) {
+            best_ms = ms;
             best_v = v;
+        }
+    }
+    if (st == SLW_OK && best_ms < 1e300) {
+        knob_set(m, start_mode, best_v);
+        for (int c : kXcdChunks) {
+            if (st != SLW_OK)
+                break;
+            if (c == saved_chunk)
+                continue;  // timed above
+            m.xcd_chunk = c;
+            float ms = 0.f;
+            if (time_candidate(ms) && ms < best_ms) {
+                best_ms = ms;
+                best_c = c;
+            }
         }
     }
     // the caller's previous elements are left as they were
@@ -1369,17 +1409,21 @@ extern "C" slw_status slw_step_autotune(slw_mesh *mesh, const slw_field *field, 
         st2 = hip_check(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
     release();
     knob_set(m, start_mode, st == SLW_OK ? best_v : saved);
+    m.xcd_chunk = st == SLW_OK ? best_c : saved_chunk;
     if (st != SLW_OK)
         return st;
     if (st2 != SLW_OK)
         return st2;
     if (cache_path) {
         std::ostringstream body;
-        body << "\"" << knob_name(start_mode) << "\": " << best_v << ", \"ms\": " << best_ms;
+        body << "\"" << knob_name(start_mode) << "\": " << best_v << ", \"xcd_chunk\": " << best_c
+             << ", \"ms\": " << best_ms;
         cache_store_entry(cache_path, sig, body.str());
     }
     if (value_out)
         *value_out = best_v;
+    if (xcd_chunk_out)
+        *xcd_chunk_out = best_c;
     if (ms_out)
         *ms_out = best_ms;
     return SLW_OK;

@@ -109,6 +109,7 @@ struct DevMesh {
     float hybrid_far = 8.0f;  // SLW_START_HYBRID: feet farther than this many heights of their previous element use the chart
     int repack = 0;  // step kernel: 0 one foot per lane; 2, 4, 8: chunks of 64 x repack feet per wavefront
     int chain = 0;   // strategy (c): 0 the mesh forest below; 2, 4, 8, 16 Morton chains of that length per lane
+    int xcd_chunk = 64;  // tiles per XCD turn: 0 one contiguous range of tiles per XCD; C > 0 chunks of C tiles dealt round-robin
     // strategy (c)'s forest (depth one): roots = a maximal independent set of
     // the nodes (greedy in internal order), every other DOF a child of an
     // adjacent root.  List = roots then children, each part in internal
@@ -258,6 +259,7 @@ struct MeshView {
     FilterConst fc;
     int32_t step_cap, hard_limit;
     float hybrid_far;
+    int xcd_chunk;
     // variable step at the boundary (bc_kind 0: off)
     const int32_t *bnext, *bprev;
     int64_t n_boundary;

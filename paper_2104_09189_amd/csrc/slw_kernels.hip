@@ -150,6 +150,7 @@ MeshView view_of(const DevMesh &m)
     v.step_cap = m.step_cap;
     v.hard_limit = m.hard_limit;
     v.hybrid_far = m.hybrid_far;
+    v.xcd_chunk = m.xcd_chunk;
     v.bnext = m.bnext;
     v.bprev = m.bprev;
     v.n_boundary = m.n_boundary;
@@ -841,12 +842,29 @@ __device__ inline bool in_box(R qx, R qy, const double bb[4])
 }
 
 // Workgroups are dispatched to the 8 XCDs round-robin (block b runs on XCD
-// b mod 8).  Give each XCD one contiguous range of tiles instead, so that the
-// Morton-ordered tiles one XCD processes are spatially compact and the
-// triangle records and value rows they share stay in that XCD's L2.
-__device__ inline int64_t xcd_tile(int64_t b, int64_t nb)
+// b mod 8).  Tiles are consecutive in the Morton order.  chunk = 0 gives each
+// XCD one contiguous range of tiles, so the records and value rows its tiles
+// share stay in its L2; but the walk lengths of a graded mesh differ between
+// regions, and the XCD whose range holds the refined part finishes last.
+// chunk = C > 0 deals chunks of C consecutive tiles to the XCDs in turn, so
+// every XCD gets the same mix of regions; the last, incomplete round of
+// chunks falls back to contiguous ranges.  Both are bijections of
+// [0, nb) onto the tiles.
+__device__ inline int64_t xcd_tile(int64_t b, int64_t nb, int64_t chunk = 0)
 {
     constexpr int64_t kXcd = 8;
+    if (chunk > 0) {
+        const int64_t full = nb / (kXcd * chunk) * (kXcd * chunk);
+        if (b < full) {
+            const int64_t x = b % kXcd, local = b / kXcd;
+            return ((local / chunk) * kXcd + x) * chunk + local % chunk;
+        }
+        b -= full;  // a multiple of 8 was taken off: b keeps its XCD
+        nb -= full;
+        const int64_t q = nb / kXcd, r = nb % kXcd;
+        const int64_t x = b % kXcd, local = b / kXcd;
+        return full + (x < r ? x * (q + 1) + local : r * (q + 1) + (x - r) * q + local);
+    }
     const int64_t q = nb / kXcd, r = nb % kXcd;
     const int64_t x = b % kXcd, local = b / kXcd;
     return x < r ? x * (q + 1) + local : r * (q + 1) + (x - r) * q + local;
@@ -876,7 +894,7 @@ __global__ void __launch_bounds__(kBlock) k_locate(MeshView mv, const typename C
 {
     using R = typename CT<F32>::R;
     LaneStats ls;
-    const int64_t i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const int64_t i = xcd_tile(blockIdx.x, gridDim.x, mv.xcd_chunk) * kBlock + threadIdx.x;
     if (i < m) {
         R qx = q[i].x, qy = q[i].y;
         WalkResult<R> w = outside_result<R>(0, 0);
@@ -929,7 +947,7 @@ __global__ void __launch_bounds__(kBlock)
 {
     using R = typename CT<F32>::R;
     LaneStats ls;
-    const int64_t i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const int64_t i = xcd_tile(blockIdx.x, gridDim.x, mv.xcd_chunk) * kBlock + threadIdx.x;
     if (i < m) {
         const R qx = q[i].x, qy = q[i].y;
         int32_t best = -1;
@@ -969,7 +987,7 @@ __global__ void __launch_bounds__(kBlock)
     using R = typename CT<F32>::R;
     using R2 = typename CT<F32>::R2;
     LaneStats ls;
-    const int64_t d = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const int64_t d = xcd_tile(blockIdx.x, gridDim.x, mv.xcd_chunk) * kBlock + threadIdx.x;
     if (d < mv.n_dofs) {
         const int64_t api = mv.internal_order ? d : mv.dof_user[d];
         const R2 x = ((const R2 *)mv.dof_xy)[d];
@@ -1197,7 +1215,7 @@ __global__ void __launch_bounds__(kBlock)
              const V *__restrict__ vin, int k, V *__restrict__ vout, double outside, int user_rows)
 {
     using R = typename CT<F32>::R;
-    const int64_t base = xcd_tile(blockIdx.x, gridDim.x) * kBlock + (threadIdx.x & ~(kWave - 1));
+    const int64_t base = xcd_tile(blockIdx.x, gridDim.x, mv.xcd_chunk) * kBlock + (threadIdx.x & ~(kWave - 1));
     const int64_t i = base + (threadIdx.x & (kWave - 1));
     int32_t row[NA];
     V wgt[NA];
@@ -1601,7 +1619,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(ste
            const int32_t *__restrict__ out_map, int32_t *__restrict__ elem_out, int64_t n_iter, DevStats *st,
            ForestView fv)
 {
-    const int64_t base = xcd_tile(blockIdx.x, gridDim.x) * kBlock + (threadIdx.x & ~(kWave - 1));
+    const int64_t base = xcd_tile(blockIdx.x, gridDim.x, mv.xcd_chunk) * kBlock + (threadIdx.x & ~(kWave - 1));
     step_wave<F32, V, NA, KIND>(mv, f, dt, t_np1, scheme, mode, start, vin, k, vout, outside, write_prev, out_map,
                                 elem_out, n_iter, base, st, fv);
 }
@@ -1643,7 +1661,7 @@ __global__ void __launch_bounds__(kWave)
     __shared__ int32_t srow[C * NA];
     __shared__ V swgt[C * NA];
     const int lane = threadIdx.x;
-    const int64_t base = xcd_tile(blockIdx.x, gridDim.x) * (int64_t)C;
+    const int64_t base = xcd_tile(blockIdx.x, gridDim.x, mv.xcd_chunk) * (int64_t)C;
     LaneStats ls;
     int32_t prev = -1;  // element of the previous foot of this lane's chain
 #pragma unroll 1
@@ -1748,7 +1766,9 @@ __device__ __forceinline__ void batch_tile(const BatchItem *__restrict__ items, 
 // schedule 0: one workgroup per tile, XCD-contiguous ranges of the
 // concatenated tile space; schedule 1: persistent workgroups pulling tiles
 // from 8 per-XCD queues (each queue covers one XCD's contiguous range) and
-// stealing from the other queues when their own is empty.
+// stealing from the other queues when their own is empty; schedule 2: one
+// workgroup per tile, chunks of 16,384 nodes' tiles dealt to the XCDs in
+// turn (even work per XCD when the meshes' walks differ).
 template <bool F32, typename V, int BS>
 __device__ inline void batch_persistent(const BatchItem *__restrict__ items, int n_items, int64_t total,
                                         int64_t step, int scheme, int k, double outside, unsigned *queues,
@@ -1764,6 +1784,9 @@ __global__ void __launch_bounds__(BS)
     const int64_t step = *counter;
     if constexpr (SCHEDULE == 0)
         batch_tile<F32, V, BS>(items, n_items, xcd_tile(blockIdx.x, gridDim.x), step, scheme, k, outside, st);
+    else if constexpr (SCHEDULE == 2)
+        batch_tile<F32, V, BS>(items, n_items, xcd_tile(blockIdx.x, gridDim.x, 16384 / BS), step, scheme, k, outside,
+                               st);
     else
         batch_persistent<F32, V, BS>(items, n_items, total, step, scheme, k, outside, queues, st);
 }
@@ -1840,7 +1863,7 @@ __global__ void __launch_bounds__(kBlock)
 {
     using R = typename CT<F32>::R;
     using R2 = typename CT<F32>::R2;
-    const int64_t d = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const int64_t d = xcd_tile(blockIdx.x, gridDim.x, mv.xcd_chunk) * kBlock + threadIdx.x;
     R2 x;
     x.x = (R)0;
     x.y = (R)0;
@@ -2024,7 +2047,7 @@ __global__ void __launch_bounds__(kBlock)
     __shared__ int32_t sj[W][C];
     __shared__ int8_t sz[W][C];
     const int w = threadIdx.x / kWave;
-    const int64_t base = xcd_tile(blockIdx.x, gridDim.x) * (int64_t)(kBlock * RP) + (int64_t)w * C;
+    const int64_t base = xcd_tile(blockIdx.x, gridDim.x, mv.xcd_chunk) * (int64_t)(kBlock * RP) + (int64_t)w * C;
     step_chunk<F32, V, NA, RP, NET>(mv, f, dt, t_np1, scheme, mode, start, vin, k, vout, outside, write_prev, out_map,
                                     elem_out, n_iter, base, sq[w], sj[w], sz[w], st);
 }
@@ -2409,6 +2432,9 @@ hipError_t launch_batch_step(hipStream_t st, int coords_f32, int vdtype, int blo
     do {                                                                                                           \
         if (schedule == 1)                                                                                         \
             hipLaunchKernelGGL((k_batch_step<F32, V, BS, 1>), dim3(g), dim3(BS), 0, st, items, n_items, total_tiles, \
+                               counter, scheme, k, outside, queues, stats);                                        \
+        else if (schedule == 2)                                                                                    \
+            hipLaunchKernelGGL((k_batch_step<F32, V, BS, 2>), dim3(g), dim3(BS), 0, st, items, n_items, total_tiles, \
                                counter, scheme, k, outside, queues, stats);                                        \
         else                                                                                                       \
             hipLaunchKernelGGL((k_batch_step<F32, V, BS, 0>), dim3(g), dim3(BS), 0, st, items, n_items, total_tiles, \

@@ -105,6 +105,7 @@ _sig("slw_mesh_set_repack", ctypes.c_int, [_vp, ctypes.c_int])
 _sig("slw_mesh_set_neighbour_codes", ctypes.c_int, [_vp, ctypes.c_int])
 _sig("slw_walk_codes_host", ctypes.c_int, [_vp, _i64, ctypes.c_int, _vp])
 _sig("slw_mesh_set_chain", ctypes.c_int, [_vp, ctypes.c_int])
+_sig("slw_mesh_set_xcd_chunk", ctypes.c_int, [_vp, ctypes.c_int])
 _sig("slw_mesh_set_hybrid", ctypes.c_int, [_vp, ctypes.c_float])
 _sig("slw_mesh_set_boundary", ctypes.c_int, [_vp, ctypes.c_int, _vp])
 _sig("slw_locate", ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, _vp, _vp])
@@ -120,7 +121,7 @@ _sig("slw_step_noalloc", ctypes.c_int, [_vp, ctypes.POINTER(slw_field), _dbl, _d
                                         ctypes.POINTER(slw_stats)])
 _sig("slw_step_autotune", ctypes.c_int, [_vp, ctypes.POINTER(slw_field), _dbl, _dbl, ctypes.c_int, ctypes.c_int,
                                          ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_char_p,
-                                         ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)])
+                                         ctypes.POINTER(_dbl), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_dbl)])
 _sig("slw_permute_rows", ctypes.c_int, [_vp, _vp, _vp, _i64, ctypes.c_int])
 _sig("slw_orient_sign_host", ctypes.c_int, [_vp, _i64, _vp, ctypes.c_int])
 _sig("slw_float_filter_host", ctypes.c_int, [_vp, _i64, _dbl, _dbl, _dbl, ctypes.c_int, _vp])
@@ -162,7 +163,7 @@ MLP_PARAMS = 5 * 64 + 64 + 64 * 64 + 64 + 64 * 2 + 2
 
 EXPORTED = ["slw_status_string", "slw_last_error", "slw_ctx_create", "slw_ctx_set_stream", "slw_ctx_destroy",
             "slw_mesh_upload", "slw_mesh_check", "slw_mesh_free", "slw_mesh_get_info", "slw_mesh_dof_coords", "slw_mesh_dof_order",
-            "slw_mesh_set_walk_limits", "slw_mesh_set_repack", "slw_mesh_set_neighbour_codes", "slw_walk_codes_host", "slw_mesh_set_chain", "slw_mesh_set_hybrid", "slw_mesh_set_boundary", "slw_locate", "slw_locate_feet", "slw_interpolate", "slw_step",
+            "slw_mesh_set_walk_limits", "slw_mesh_set_repack", "slw_mesh_set_neighbour_codes", "slw_walk_codes_host", "slw_mesh_set_chain", "slw_mesh_set_xcd_chunk", "slw_mesh_set_hybrid", "slw_mesh_set_boundary", "slw_locate", "slw_locate_feet", "slw_interpolate", "slw_step",
             "slw_step_noalloc", "slw_step_autotune", "slw_permute_rows", "slw_orient_sign_host",
             "slw_float_filter_host", "slw_batch_create", "slw_batch_free", "slw_batch_set_fields",
             "slw_batch_set_values", "slw_batch_set_elem_out", "slw_batch_set_step", "slw_batch_get_step", "slw_batch_set_schedule",
@@ -323,6 +324,9 @@ class Mesh:
 
     def set_chain(self, length: int):
         _check(_lib.slw_mesh_set_chain(self.h, int(length)), "slw_mesh_set_chain")
+
+    def set_xcd_chunk(self, chunk: int):
+        _check(_lib.slw_mesh_set_xcd_chunk(self.h, int(chunk)), "slw_mesh_set_xcd_chunk")
 
     def set_hybrid(self, far: float):
         _check(_lib.slw_mesh_set_hybrid(self.h, float(far)), "slw_mesh_set_hybrid")
@@ -492,17 +496,20 @@ class Mesh:
         return (v_out, st.as_dict()) if stats else v_out
 
     def autotune_step(self, field, t_n, dt, scheme, v_in, order=1, start_mode=START_STEERED, start=None,
-                      cache_path=None):
-        """slw_step_autotune: returns (value chosen, median ms per step)."""
+                      cache_path=None, with_chunk=False):
+        """slw_step_autotune: returns (value chosen, median ms per step), or
+        (value, XCD chunk, ms) with with_chunk=True."""
         torch = _torch()
         dev = self.ctx.device
         k = 1 if v_in.ndim == 1 else v_in.shape[1]
-        val, ms = ctypes.c_double(), ctypes.c_double()
+        val, ms, chunk = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
         _check(_lib.slw_step_autotune(self.h, ctypes.byref(make_field(field)), float(t_n), float(dt), int(scheme),
                                       int(order), int(start_mode), _ptr(start, torch.int32, dev, "start", True),
                                       _ptr(v_in, v_in.dtype, dev, "v_in"), _vdtype(v_in), k,
                                       None if cache_path is None else str(cache_path).encode(),
-                                      ctypes.byref(val), ctypes.byref(ms)), "slw_step_autotune")
+                                      ctypes.byref(val), ctypes.byref(chunk), ctypes.byref(ms)), "slw_step_autotune")
+        if with_chunk:
+            return float(val.value), int(chunk.value), float(ms.value)
         return float(val.value), float(ms.value)
 
     def permute_rows(self, src, dst=None, to_internal=True):

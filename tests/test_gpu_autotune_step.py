@@ -1,7 +1,7 @@
 """slw_step_autotune: the knob of each start mode (lane schedule, hybrid
-threshold, strategy (c) forest or chain) chosen among bit-identical
-candidates, applied to the mesh, cached; the caller's values and previous
-elements untouched."""
+threshold, strategy (c) forest or chain) and then the XCD chunk chosen among
+bit-identical candidates, applied to the mesh, cached; the caller's values
+and previous elements untouched."""
 import json
 
 import numpy as np
@@ -42,22 +42,28 @@ def test_step_autotune_modes_cache_and_state(S, C, tmp_path):
             # previous elements from an earlier step, on both meshes
             mesh.step(w.field, 0.1, w.dt, w.scheme, vin, start_mode=mode)
             twin.step(w.field, 0.1, w.dt, w.scheme, vin, start_mode=mode)
-        val, ms = mesh.autotune_step(w.field, 0.3, w.dt, w.scheme, vin, start_mode=mode, cache_path=cache)
-        assert val in allowed and ms > 0
-        choices[mode] = val
+        val, chunk, ms = mesh.autotune_step(w.field, 0.3, w.dt, w.scheme, vin, start_mode=mode, cache_path=cache,
+                                            with_chunk=True)
+        assert val in allowed and chunk in (0, 16, 32, 64, 128) and ms > 0
+        choices[mode] = (val, chunk)
         v, st = mesh.step(w.field, 0.3, w.dt, w.scheme, vin, start_mode=mode, stats=True)
         assert np.array_equal(host(v), ref), mode
         if mode == S.START_HYBRID:
             # the previous elements were restored: the twin (same history, same threshold) walks the same
             twin.set_hybrid(val)
+            twin.set_xcd_chunk(chunk)
             _, st2 = twin.step(w.field, 0.3, w.dt, w.scheme, vin, start_mode=mode, stats=True)
             assert st == st2
     assert np.array_equal(host(vin), before)
     data = json.loads(cache.read_text())
     assert len(data) == 3
-    # a second call answers from the cache, with the same choice
-    for mode, val in choices.items():
+    assert all("xcd_chunk" in e for e in data.values())
+    # a second call answers from the cache, with the same choice, on a
+    # mesh whose XCD chunk was changed meanwhile
+    for mode, (val, chunk) in choices.items():
         if mode == S.START_HYBRID:
             mesh.step(w.field, 0.1, w.dt, w.scheme, vin, start_mode=mode)
-        assert mesh.autotune_step(w.field, 0.3, w.dt, w.scheme, vin, start_mode=mode, cache_path=cache)[0] == val
+        mesh.set_xcd_chunk(3)
+        got = mesh.autotune_step(w.field, 0.3, w.dt, w.scheme, vin, start_mode=mode, cache_path=cache, with_chunk=True)
+        assert got[:2] == (val, chunk)
     assert len(json.loads(cache.read_text())) == 3

@@ -256,7 +256,7 @@ def test_batch_elements_and_values_small(S, C, orc, f32):
     float-rounded mesh), values to 1e-5 of the same oracle step."""
     wl = _small_batch()
     meshes, perms, va, vb, el, b = _batch(S, C, wl, S.COORDS_F32 if f32 else 0)
-    for schedule, block in ((0, 256), (1, 128), (0, 64), (1, 512)):
+    for schedule, block in ((0, 256), (1, 128), (0, 64), (1, 512), (2, 256), (2, 64)):
         b.set_schedule(schedule, block)
         b.set_step(2)                                   # even: va -> vb, from 2 dt to 3 dt
         b.step(S.SLW_EULER)
