@@ -436,26 +436,32 @@ def wave_walks(mesh, w, t_n, mode) -> dict:
     return _walk_histogram(st)
 
 
-def measure_courant_range(mesh, w, v0, steps=20, warmup=3, alphas=(1.0, 5.0, 20.0, 50.0, 100.0), chart_g=2048):
+def measure_courant_range(mesh, w, v0, steps=20, warmup=3, alphas=(1.0, 5.0, 20.0, 50.0, 100.0), chart_g=2048,
+                          grid_g=16384):
     """The graded mesh across its Courant range: strategy (a) (steered
-    incident start), strategy (b) (previous element) and the exact chart
-    start, each with ms per step, kernel time, HBM-roofline fraction and the
-    walk lengths (mean, and the mean over wavefronts of each wavefront's
-    longest walk, which sets its time)."""
+    incident start), strategy (b) (previous element), strategy (c) (the
+    forest), the exact chart start, the jump-and-walk grid start and the
+    hybrid (previous element, else the grid cell), each with ms per step,
+    kernel time, HBM-roofline fraction and the walk lengths (mean, and the
+    mean over wavefronts of each wavefront's longest walk, which sets its
+    time)."""
     import dataclasses
     from paper_2104_09189_amd import inputs as I
     from paper_2104_09189_amd import slwalk as S
     if mesh.chart_g != chart_g:
         mesh.chart_build(chart_g)
+    t0 = time.perf_counter()
+    mesh.build_grid(grid_g)
+    grid_build_s = time.perf_counter() - t0
     abytes = algorithmic_bytes(mesh.n_nodes, mesh.n_tris, 16, 4, v0.shape[1])
-    out = {}
+    out = {"grid": {"g": grid_g, "bytes": 4 * grid_g * grid_g, "build_s": grid_build_s}}
     for alpha in alphas:
         dt, _ = I.courant_dt(alpha, w.h)
         wa = dataclasses.replace(w, dt=dt)
         line = {"dt": dt}
         for name, mode in (("a_steered", S.START_STEERED), ("b_previous", S.START_PREV),
                            ("c_forest", S.START_NEIGHBOR), ("chart_exact", S.START_CHART),
-                           ("hybrid", S.START_HYBRID)):
+                           ("grid", S.START_GRID), ("hybrid", S.START_HYBRID)):
             # the library's defaults: one foot per lane, the forest, hybrid
             # threshold 8, chunks of 64 tiles per XCD turn
             mesh.set_repack(0)
@@ -472,11 +478,13 @@ def measure_courant_range(mesh, w, v0, steps=20, warmup=3, alphas=(1.0, 5.0, 20.
                           "mean_walk_steps": ww["mean"], "mean_wavefront_max": ww["mean_wavefront_max"],
                           "p99": ww["p99"], "max": ww["max"]}
             # the same after slw_step_autotune (the mode's knob, then the XCD
-            # chunk), timed on the step from 7 dt (previous elements from the
-            # step before)
+            # chunk), tuned on the step ending near t = 1/4 (previous
+            # elements from the step before; near t = 1/2 the field vanishes
+            # and no foot moves)
+            t_tune = max(round(0.25 / dt) - 1, 1) * dt
             if mode in (S.START_PREV, S.START_HYBRID):
-                mesh.step(wa.field, 6 * dt, dt, wa.scheme, v0, start_mode=mode)
-            knob, chunk, _ = mesh.autotune_step(wa.field, 7 * dt, dt, wa.scheme, v0, start_mode=mode,
+                mesh.step(wa.field, t_tune - dt, dt, wa.scheme, v0, start_mode=mode)
+            knob, chunk, _ = mesh.autotune_step(wa.field, t_tune, dt, wa.scheme, v0, start_mode=mode,
                                                 with_chunk=True)
             rt = measure(mesh, wa, v0, steps, warmup, mode)
             line[name]["tuned"] = {"knob": knob, "xcd_chunk": chunk, "ms_per_step": rt["ms_per_step"],
@@ -485,7 +493,40 @@ def measure_courant_range(mesh, w, v0, steps=20, warmup=3, alphas=(1.0, 5.0, 20.
         mesh.set_chain(0)
         mesh.set_hybrid(8.0)
         mesh.set_xcd_chunk(64)
+        best = min((v["kernel_ms"], k) for k, v in line.items() if k != "dt")
+        line["fastest"] = best[1]
         out[f"alpha_{alpha:g}"] = line
+    mesh.build_grid(0)
+    return out
+
+
+def measure_cpu_walk(w, gpu_walk_ms=None):
+    """The paper's own walk on the host cores (Algorithm 1 in plain FP64,
+    strategy (a)'s start: a random incident triangle as in the paper, and the
+    incident triangle whose angle contains the foot direction), on one
+    thread and on all cores, for the feet of the locators line (t = 8 dt).
+    Walk only, as the GPU's walk-only locator beside it."""
+    from oracle import oracle as O
+    from oracle import walk as W
+    q = O.feet(w.xy, w.field, 8 * w.dt, w.dt, w.scheme)
+    M = W.Mesh(w.xy, w.tri)
+    n = int(w.xy.shape[0])
+    cores = W.max_threads()
+    out = {"points": n, "cores": cores, "cpu_model": cpu_model(), "kind": "paper walk (Algorithm 1, FP64)"}
+    for name, rule in (("sector_start", W.RULE_SECTOR), ("random_incident_start", W.RULE_RANDOM)):
+        line = {}
+        for threads in (1, cores):
+            t0 = time.perf_counter()
+            e, st = M.locate_nodes(q, rule, seed=11, threads=threads)
+            el = time.perf_counter() - t0
+            line[f"threads_{threads}_feet_per_s"] = n / el
+            line[f"threads_{threads}_s"] = el
+        line["mean_walk_steps"] = float(st[e >= 0].mean())
+        line["outside"] = int((e == -1).sum())
+        out[name] = line
+    if gpu_walk_ms:
+        out["gpu_walk_only_feet_per_s"] = n / (gpu_walk_ms * 1e-3)
+        out["gpu_vs_all_cores"] = out["gpu_walk_only_feet_per_s"] / out["sector_start"][f"threads_{cores}_feet_per_s"]
     return out
 
 
@@ -548,6 +589,8 @@ def main():
     ap.add_argument("--only-learned", action="store_true",
                     help="measure the learned start on the graded mesh only (training included; for traces)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-start measurement")
+    ap.add_argument("--only-courant", action="store_true",
+                    help="measure the Courant-range lines of the graded mesh only")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times (to scale HBM counters)")
@@ -587,6 +630,9 @@ def main():
     v0 = torch.from_numpy(np.ascontiguousarray(w.v0[perm])).to("cuda:0")
     n_feet = mesh.n_nodes
 
+    if args.only_courant:
+        print(json.dumps({"courant_range": measure_courant_range(mesh, w, v0), "workload": w.name}), flush=True)
+        return
     if args.only_b:
         rb = measure(mesh, w, v0, args.steps, args.warmup, S.START_PREV)
         print(json.dumps({"strategy_b": {"ms_per_step": rb["ms_per_step"], "kernel_ms": rb["kernel_ms"],
@@ -653,6 +699,8 @@ def main():
         out["courant_range"] = measure_courant_range(mesh, w, v0)
         out["k_field_reuse"] = measure_k_reuse(mesh, w, v0)
         out["locators"] = measure_locators(mesh, w)
+        if not args.no_cpu:
+            out["cpu_walk"] = measure_cpu_walk(w, out["locators"].get("walk_steered_ms"))
         out["precision"] = measure_precision()
     if not args.no_batch and not args.only_a:
         out["batch"] = measure_batch()

@@ -123,11 +123,14 @@ enum {
     SLW_START_LEARNED_INDEX = 7, /* a learned index: the network's chart cell as the guess of
                               galloping searches in the chart's quantile tables, which end
                               in the foot's own cell (the start of SLW_START_CHART) */
-    SLW_START_HYBRID = 8   /* chosen per foot from how far it moved (slw_step only; see
+    SLW_START_HYBRID = 8,  /* chosen per foot from how far it moved (slw_step only; see
                               slw_mesh_set_hybrid): the previous element (as SLW_START_PREV)
-                              when the foot is in it or near it, else the foot's chart cell
-                              (as SLW_START_CHART) when the mesh has a chart, else the
-                              steered start; keeps the previous elements as SLW_START_PREV */
+                              when the foot is in it or near it, else the foot's cell of the
+                              start grid (as SLW_START_GRID) when the mesh has one, else its
+                              chart cell (as SLW_START_CHART) when the mesh has a chart, else
+                              the steered start; keeps the previous elements as SLW_START_PREV */
+    SLW_START_GRID = 9     /* the triangle recorded for the foot's cell of the uniform start
+                              grid (jump-and-walk; needs slw_mesh_build_grid) */
 };
 /* slw_mesh_upload flags */
 #define SLW_COORDS_F32 0x1u     /* store coordinates as float (FP32 walk, FP64/exact fallback) */
@@ -280,6 +283,16 @@ slw_status slw_mesh_set_chain(slw_mesh *mesh, int length);
  * this mesh, not to batches.  Results never depend on it;
  * SLW_E_ARG outside 0 ... 4096. */
 slw_status slw_mesh_set_xcd_chunk(slw_mesh *mesh, int chunk);
+
+/* Jump-and-walk start grid (a bucketing start, Section 2.1's prior art;
+ * Muecke, Saias and Zhu 1996): g x g square cells over the mesh's bounding
+ * box (side = the box's longer side / g), each recording a triangle that
+ * holds its centre, found by the library's own walk at build time (a centre
+ * outside the mesh records a nearby triangle).  Starts of SLW_START_GRID and
+ * the far feet of SLW_START_HYBRID read one cell.  g in 16 ... 16384 (4 g^2
+ * bytes of device memory, replacing an earlier grid); g = 0 removes it.
+ * Synchronous.  Results never depend on it. */
+slw_status slw_mesh_build_grid(slw_mesh *mesh, int g);
 /* The per-foot choice of SLW_START_HYBRID, after the hybrid idea that closes
  * the numerical section (Section 4) of the paper: the start is chosen from
  * the local dynamics, i.e. from how far the foot moved since the previous

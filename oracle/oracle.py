@@ -36,11 +36,12 @@ _lib = None
 
 
 def build(force: bool = True) -> Path:
-    """Compile liborc.so with gcc (no FP contraction, OpenMP)."""
+    """Compile liborc.so with gcc (no FP contraction, OpenMP): the oracle
+    (orc.c) and the paper's walk on the host (walk.c)."""
     if force or not _LIB_PATH.exists():
         cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
                "-fPIC", "-shared", "-Wall", "-Wextra", "-o", str(_LIB_PATH) + ".tmp",
-               str(_HERE / "orc.c"), "-lm"]
+               str(_HERE / "orc.c"), str(_HERE / "walk.c"), "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(str(_LIB_PATH) + ".tmp", _LIB_PATH)
     return _LIB_PATH

@@ -131,8 +131,10 @@ slw_status step_impl(slw_mesh *mesh, const slw_field *field, double t_n, double 
         return set_error(SLW_E_ARG, w + ": unknown scheme");
     if (vdtype != SLW_F64 && vdtype != SLW_F32)
         return set_error(SLW_E_ARG, w + ": unknown vdtype");
-    if (start_mode < SLW_START_STEERED || start_mode > SLW_START_HYBRID)
+    if (start_mode < SLW_START_STEERED || start_mode > SLW_START_GRID)
         return set_error(SLW_E_ARG, w + ": unknown start mode");
+    if (start_mode == SLW_START_GRID && !mesh->m.grid)
+        return set_error(SLW_E_ARG, w + ": SLW_START_GRID needs a start grid (slw_mesh_build_grid)");
     if ((start_mode == SLW_START_GIVEN || start_mode == SLW_START_FIXED) && !start)
         return set_error(SLW_E_ARG, w + ": start array required for this start mode");
     if ((start_mode == SLW_START_LEARNED || start_mode == SLW_START_LEARNED_INDEX) && !mesh->m.mlp)
@@ -454,6 +456,53 @@ slw_status slw_mesh_set_hybrid(slw_mesh *mesh, float far)
     return SLW_OK;
 }
 
+slw_status slw_mesh_build_grid(slw_mesh *mesh, int g)
+{
+    if (!mesh)
+        return set_error(SLW_E_ARG, "mesh is NULL");
+    DevMesh &m = mesh->m;
+    if (g == 0) {
+        if (m.grid) {
+            DeviceGuard dg(mesh->ctx->device);
+            (void)hipStreamSynchronize(mesh->ctx->stream);
+            (void)hipFree(m.grid);
+            m.device_bytes -= (int64_t)m.grid_g * m.grid_g * 4;
+        }
+        m.grid = nullptr;
+        m.grid_g = 0;
+        return SLW_OK;
+    }
+    if (g < 16 || g > 16384)
+        return set_error(SLW_E_ARG, "slw_mesh_build_grid: g must be 0 (remove) or 16 ... 16384");
+    DeviceGuard dg(mesh->ctx->device);
+    const double wx = m.bbox[2] - m.bbox[0], wy = m.bbox[3] - m.bbox[1];
+    const double span = wx > wy ? wx : wy;
+    const double cell = span > 0 ? span / g : 1.0;
+    int32_t *grid = nullptr;
+    const size_t bytes = (size_t)g * (size_t)g * sizeof(int32_t);
+    if (hipMalloc((void **)&grid, bytes) != hipSuccess)
+        return set_error(SLW_E_NOMEM, "slw_mesh_build_grid: device memory");
+    slw_status st = hip_check(launch_grid_build(m, mesh->ctx->stream, grid, g, m.bbox[0], m.bbox[1], cell),
+                              "grid build");
+    if (st == SLW_OK)
+        st = hip_check(hipStreamSynchronize(mesh->ctx->stream), "hipStreamSynchronize");
+    if (st != SLW_OK) {
+        (void)hipFree(grid);
+        return st;
+    }
+    if (m.grid) {
+        (void)hipFree(m.grid);
+        m.device_bytes -= (int64_t)m.grid_g * m.grid_g * 4;
+    }
+    m.grid = grid;
+    m.grid_g = g;
+    m.grid_x0 = m.bbox[0];
+    m.grid_y0 = m.bbox[1];
+    m.grid_inv = 1.0 / cell;
+    m.device_bytes += (int64_t)bytes;
+    return SLW_OK;
+}
+
 slw_status slw_mesh_set_xcd_chunk(slw_mesh *mesh, int chunk)
 {
     if (!mesh)
@@ -520,8 +569,11 @@ slw_status slw_locate_feet(slw_mesh *mesh, const slw_field *field, double t_np1,
         return set_error(SLW_E_ARG, "feet (SLW_FEET_IN) or a valid field is required");
     if (scheme != SLW_EULER && scheme != SLW_RK2)
         return set_error(SLW_E_ARG, "unknown scheme");
-    if (start_mode < SLW_START_STEERED || start_mode > SLW_START_LEARNED_INDEX || start_mode == SLW_START_NEIGHBOR)
-        return set_error(SLW_E_ARG, "unknown start mode (SLW_START_NEIGHBOR is for slw_step)");
+    if (start_mode < SLW_START_STEERED || start_mode == SLW_START_NEIGHBOR || start_mode == SLW_START_HYBRID ||
+        start_mode > SLW_START_GRID)
+        return set_error(SLW_E_ARG, "unknown start mode (SLW_START_NEIGHBOR and SLW_START_HYBRID are for slw_step)");
+    if (start_mode == SLW_START_GRID && !mesh->m.grid)
+        return set_error(SLW_E_ARG, "SLW_START_GRID needs a start grid (slw_mesh_build_grid)");
     if ((start_mode == SLW_START_GIVEN || start_mode == SLW_START_FIXED) && !start)
         return set_error(SLW_E_ARG, "start array required for this start mode");
     if ((start_mode == SLW_START_LEARNED || start_mode == SLW_START_LEARNED_INDEX) && !mesh->m.mlp)

@@ -98,6 +98,12 @@ struct DevMesh {
     float *chart_qx = nullptr;        // [chart_g] smallest centroid x of each u slab
     float *chart_qy = nullptr;        // [chart_g * chart_g] smallest centroid y of each cell of a slab
     int chart_g = 0;
+    // jump-and-walk start grid (slw_mesh_build_grid): grid_g x grid_g square
+    // cells from (grid_x0, grid_y0), internal id of a triangle holding each
+    // cell's centre (or near it)
+    int32_t *grid = nullptr;
+    int grid_g = 0;
+    double grid_x0 = 0.0, grid_y0 = 0.0, grid_inv = 0.0;  // cells per unit length
     int32_t *learned_start = nullptr; // [n_dofs]
     struct slw_mlp *mlp = nullptr;    // borrowed
     // host copies kept for queries about the mesh
@@ -278,6 +284,9 @@ struct MeshView {
     const float *chart_qx, *chart_qy;
     const int32_t *chart_table;
     int chart_g;
+    const int32_t *grid;
+    int grid_g;
+    double grid_x0, grid_y0, grid_inv;
     const uint16_t *mlp_wpack;
     const float *mlp_bias, *mlp_norm;
 };
@@ -298,6 +307,8 @@ hipError_t launch_locate(const DevMesh &m, hipStream_t st, const void *q, int64_
                          int32_t *elem, void *bary, int32_t *steps, DevStats *stats);
 hipError_t launch_qt_locate(const DevMesh &m, hipStream_t st, const void *q, int64_t m_pts, int32_t *elem, void *bary,
                             DevStats *stats);
+hipError_t launch_grid_build(const DevMesh &m, hipStream_t st, int32_t *grid, int g, double x0, double y0,
+                             double cell);
 hipError_t launch_locate_feet(const DevMesh &m, hipStream_t st, const FieldDev *f, double t_np1, double dt,
                               int scheme, int start_mode, const int32_t *start, bool feet_in, void *feet,
                               int32_t *elem, void *bary, int32_t *steps, DevStats *stats);

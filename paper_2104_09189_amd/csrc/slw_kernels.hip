@@ -169,6 +169,11 @@ MeshView view_of(const DevMesh &m)
     v.chart_qy = m.chart_qy;
     v.chart_table = m.chart_table;
     v.chart_g = m.chart_g;
+    v.grid = m.grid;
+    v.grid_g = m.grid_g;
+    v.grid_x0 = m.grid_x0;
+    v.grid_y0 = m.grid_y0;
+    v.grid_inv = m.grid_inv;
     v.mlp_wpack = m.mlp ? m.mlp->wpack : nullptr;
     v.mlp_bias = m.mlp ? m.mlp->bias : nullptr;
     v.mlp_norm = m.mlp ? m.mlp->norm : nullptr;
@@ -220,7 +225,24 @@ __device__ inline int32_t start_id(const MeshView &mv, int64_t d, int64_t api, i
     return -1;
 }
 
-__device__ inline int32_t start_pick(const MeshView &mv, int64_t d, int32_t id, int mode, float dx, float dy)
+// Jump-and-walk start (Muecke, Saias and Zhu 1996): the triangle recorded for
+// the cell of the uniform start grid that holds the foot (the grid must
+// exist; the foot lies in the mesh's bounding box)
+template <typename R>
+__device__ inline int32_t grid_start(const MeshView &mv, R qx, R qy)
+{
+    const int g = mv.grid_g;
+    int cx = (int)((float)(((double)qx - mv.grid_x0) * mv.grid_inv));
+    int cy = (int)((float)(((double)qy - mv.grid_y0) * mv.grid_inv));
+    cx = cx < 0 ? 0 : (cx >= g ? g - 1 : cx);
+    cy = cy < 0 ? 0 : (cy >= g ? g - 1 : cy);
+    return mv.grid[(int64_t)cy * g + cx];
+}
+
+// GRID: whether the grid rule is compiled in (the plain step kernel leaves it
+// out; SLW_START_GRID has an instantiation of its own)
+template <bool GRID, typename R, typename R2>
+__device__ inline int32_t start_pick(const MeshView &mv, int64_t d, int32_t id, int mode, R2 x, R qx, R qy)
 {
     // caller-given ids outside [0, n_tris) fall back to the steered start
     if (mode == SLW_START_GIVEN || mode == SLW_START_FIXED) {
@@ -232,15 +254,18 @@ __device__ inline int32_t start_pick(const MeshView &mv, int64_t d, int32_t id, 
     } else if (mode == SLW_START_LEARNED || mode == SLW_START_CHART || mode == SLW_START_LEARNED_INDEX) {
         if (id >= 0 && id < mv.n_tris)
             return id;
+    } else if (GRID && mode == SLW_START_GRID) {
+        return grid_start(mv, qx, qy);
     }
-    return quadrant_start(mv.qstart[d], dx, dy);
+    return quadrant_start(mv.qstart[d], (float)(qx - x.x), (float)(qy - x.y));
 }
 
 template <bool F32>
 __device__ inline int32_t start_for(const MeshView &mv, int64_t d, int64_t api, int mode,
-                                    const int32_t *__restrict__ start, float dx, float dy)
+                                    const int32_t *__restrict__ start, typename CT<F32>::R2 x,
+                                    typename CT<F32>::R qx, typename CT<F32>::R qy)
 {
-    return start_pick(mv, d, start_id(mv, d, api, mode, start), mode, dx, dy);
+    return start_pick<true>(mv, d, start_id(mv, d, api, mode, start), mode, x, qx, qy);
 }
 
 // ---------------------------------------------------------------------------
@@ -978,6 +1003,38 @@ __global__ void __launch_bounds__(kBlock)
         flush_stats(ls, st);
 }
 
+// The jump-and-walk start grid: cell c of a g x g grid of square cells from
+// (x0, y0) records the triangle that holds its centre, located by the walk
+// from the upload's coarse bucket grid; a centre outside the mesh keeps the
+// coarse grid's triangle (any start gives the same results).
+template <bool F32>
+__global__ void __launch_bounds__(kBlock) k_grid_build(MeshView mv, int32_t *__restrict__ grid, int g, double x0,
+                                                       double y0, double cell)
+{
+    using R = typename CT<F32>::R;
+    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= (int64_t)g * g)
+        return;
+    const int cx = (int)(c % g), cy = (int)(c / g);
+    const double px = x0 + ((double)cx + 0.5) * cell, py = y0 + ((double)cy + 0.5) * cell;
+    const double wx = mv.bb[2] - mv.bb[0], wy = mv.bb[3] - mv.bb[1];
+    const double span = wx > wy ? wx : wy;
+    const double cw = span > 0 ? span / mv.jump_g : 1.0;
+    int jx = (int)floor((px - mv.bb[0]) / cw), jy = (int)floor((py - mv.bb[1]) / cw);
+    jx = jx < 0 ? 0 : (jx >= mv.jump_g ? mv.jump_g - 1 : jx);
+    jy = jy < 0 ? 0 : (jy >= mv.jump_g ? mv.jump_g - 1 : jy);
+    const int32_t j0 = mv.jump[(int64_t)jy * mv.jump_g + jx];
+    int32_t j = j0;
+    const R qx = (R)px, qy = (R)py;
+    if (in_box<R>(qx, qy, mv.bb)) {
+        LaneStats ls;
+        const WalkResult<R> w = walk<F32>(mv, j0, qx, qy, (uint32_t)c * 2654435761u, ls.c);
+        if (w.elem >= 0)
+            j = w.elem;
+    }
+    grid[c] = j;
+}
+
 template <bool F32>
 __global__ void __launch_bounds__(kBlock)
     k_locate_feet(MeshView mv, FieldDev f, double dt, int scheme, int mode, const int32_t *__restrict__ start,
@@ -1006,7 +1063,7 @@ __global__ void __launch_bounds__(kBlock)
         }
         WalkResult<R> w = outside_result<R>(0, 0);
         if (in_box<R>(qx, qy, mv.bb)) {
-            const int32_t j0 = start_for<F32>(mv, d, api, mode, start, (float)(qx - x.x), (float)(qy - x.y));
+            const int32_t j0 = start_for<F32>(mv, d, api, mode, start, x, qx, qy);
             w = walk<F32>(mv, j0, qx, qy, (uint32_t)d * 2654435761u, ls.c);
         }
         if (mode == SLW_START_PREV)
@@ -1542,12 +1599,16 @@ __device__ inline void step_wave(const MeshView &mv, const FieldDev &f, double d
             // previous element first (strategy (b)); a foot inside it is
             // located at once.  A foot less than hybrid_far heights of that
             // element beyond it walks on from there; a farther one, or one
-            // without a previous element, starts from its chart cell when the
+            // without a previous element, starts from its cell of the start
+            // grid when the mesh has one, else from its chart cell when the
             // mesh has a chart (the nearer of that cell's triangle and the
             // steered start), else from the steered start (strategy (a)).
             if (run) {
                 bool done = false;
                 int32_t j0 = -1;
+                // (the grid cell is read only for feet that need it: read
+                // beside the previous element's record for every foot, it
+                // measured slower at low Courant numbers)
                 if (sid >= 0) {
                     float tmin = 0.f;
                     done = first_test<F32>(mv, sid, qx, qy, tmin, w, ls.c) != 0;
@@ -1556,8 +1617,10 @@ __device__ inline void step_wave(const MeshView &mv, const FieldDev &f, double d
                 }
                 if (!done) {
                     if (j0 < 0)
-                        j0 = mv.chart_table ? chart_start<F32, 0>(mv, true, d, x, qx, qy, t_np1)
-                                            : quadrant_start(mv.qstart[d], (float)(qx - x.x), (float)(qy - x.y));
+                        j0 = mv.grid ? grid_start(mv, qx, qy)
+                                     : (mv.chart_table ? chart_start<F32, 0>(mv, true, d, x, qx, qy, t_np1)
+                                                       : quadrant_start(mv.qstart[d], (float)(qx - x.x),
+                                                                        (float)(qy - x.y)));
                     w = walk<F32>(mv, j0, qx, qy, (uint32_t)d * 2654435761u, ls.c);
                 }
             }
@@ -1567,7 +1630,7 @@ __device__ inline void step_wave(const MeshView &mv, const FieldDev &f, double d
             if constexpr (KIND == -3 || KIND == -4)
                 j0 = sid >= 0 ? sid : quadrant_start(mv.qstart[d], (float)(qx - x.x), (float)(qy - x.y));
             else if constexpr (KIND < 0)
-                j0 = start_pick(mv, d, sid, mode, (float)(qx - x.x), (float)(qy - x.y));
+                j0 = start_pick<KIND == -6>(mv, d, sid, mode, x, qx, qy);
             w = walk<F32>(mv, j0, qx, qy, (uint32_t)d * 2654435761u, ls.c, KIND == -2);
         }
         if constexpr (KIND == -3)
@@ -1935,7 +1998,7 @@ __device__ inline void step_chunk(const MeshView &mv, const FieldDev &f, double 
             j0 = valid ? jc : j0;
         } else if (valid) {
             const int64_t api = (mode == SLW_START_GIVEN && !mv.internal_order) ? mv.dof_user[d] : d;
-            j0 = start_for<F32>(mv, d, api, mode, start, (float)(q.x - x.x), (float)(q.y - x.y));
+            j0 = start_for<F32>(mv, d, api, mode, start, x, q.x, q.y);
         }
         sq[slot] = q;
         sj[slot] = j0;
@@ -2166,6 +2229,24 @@ hipError_t launch_qt_locate(const DevMesh &m, hipStream_t st, const void *q, int
     return hipGetLastError();
 }
 
+hipError_t launch_grid_build(const DevMesh &m, hipStream_t st, int32_t *grid, int g, double x0, double y0,
+                             double cell)
+{
+    const int64_t cells = (int64_t)g * g;
+    if (cells <= 0 || !m.jump)
+        return hipErrorInvalidValue;
+    const int64_t blocks = (cells + kBlock - 1) / kBlock;
+    if (blocks > (int64_t)INT32_MAX)
+        return hipErrorInvalidValue;
+    MeshView mv = view_of(m);
+    if (m.coords_f32)
+        hipLaunchKernelGGL(k_grid_build<true>, dim3((unsigned)blocks), dim3(kBlock), 0, st, mv, grid, g, x0, y0, cell);
+    else
+        hipLaunchKernelGGL(k_grid_build<false>, dim3((unsigned)blocks), dim3(kBlock), 0, st, mv, grid, g, x0, y0,
+                           cell);
+    return hipGetLastError();
+}
+
 hipError_t launch_locate_feet(const DevMesh &m, hipStream_t st, const FieldDev *f, double t_np1, double dt,
                               int scheme, int mode, const int32_t *start, bool feet_in, void *feet, int32_t *elem,
                               void *bary, int32_t *steps, DevStats *stats)
@@ -2387,6 +2468,10 @@ hipError_t launch_step(const DevMesh &m, hipStream_t st, const FieldDev &f0, dou
     default:                                                                                                   \
         if (mode == SLW_START_PREV)                                                                            \
             hipLaunchKernelGGL((k_step<F32, V, NA, -2>), dim3(g), dim3(kBlock), 0, st, mv, f, dt, t_n + dt, scheme, \
+                               mode, start, (const V *)v_in, k, (V *)v_out, outside, (int)write_prev, out_map,   \
+                               elem_out, n_iter, stats, ForestView());                                         \
+        else if (mode == SLW_START_GRID)                                                                       \
+            hipLaunchKernelGGL((k_step<F32, V, NA, -6>), dim3(g), dim3(kBlock), 0, st, mv, f, dt, t_n + dt, scheme, \
                                mode, start, (const V *)v_in, k, (V *)v_out, outside, (int)write_prev, out_map,   \
                                elem_out, n_iter, stats, ForestView());                                         \
         else                                                                                                   \

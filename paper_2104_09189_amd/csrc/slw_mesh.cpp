@@ -189,7 +189,7 @@ void free_mesh(DevMesh &m)
                     m.dof_int, m.tri_int, m.prev_elem, m.jump, m.chart_uv, m.chart_node, m.chart_table,
                     m.chart_qx, m.chart_qy, m.learned_start, m.bnext, m.bprev, m.qt_nodes, m.qt_lists,
                     m.forest_list1, m.forest_out1, m.forest_parent1, m.forest_list2, m.forest_out2,
-                    m.forest_parent2, m.forest_elem, m.bedge};
+                    m.forest_parent2, m.forest_elem, m.bedge, m.grid};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);

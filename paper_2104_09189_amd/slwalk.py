@@ -35,6 +35,7 @@ SLW_EULER, SLW_RK2 = 0, 1
 START_STEERED, START_GIVEN, START_PREV, START_FIXED, START_LEARNED, START_CHART, START_NEIGHBOR = 0, 1, 2, 3, 4, 5, 6
 START_LEARNED_INDEX = 7
 START_HYBRID = 8
+START_GRID = 9
 BC_NONE, BC_CONSTANT, BC_AFFINE = 0, 1, 2
 COORDS_F32, P2, NO_REORDER, INTERNAL_ORDER, HILBERT = 0x1, 0x2, 0x4, 0x8, 0x10
 FEET_IN = 0x1
@@ -106,6 +107,7 @@ _sig("slw_mesh_set_neighbour_codes", ctypes.c_int, [_vp, ctypes.c_int])
 _sig("slw_walk_codes_host", ctypes.c_int, [_vp, _i64, ctypes.c_int, _vp])
 _sig("slw_mesh_set_chain", ctypes.c_int, [_vp, ctypes.c_int])
 _sig("slw_mesh_set_xcd_chunk", ctypes.c_int, [_vp, ctypes.c_int])
+_sig("slw_mesh_build_grid", ctypes.c_int, [_vp, ctypes.c_int])
 _sig("slw_mesh_set_hybrid", ctypes.c_int, [_vp, ctypes.c_float])
 _sig("slw_mesh_set_boundary", ctypes.c_int, [_vp, ctypes.c_int, _vp])
 _sig("slw_locate", ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, _vp, _vp])
@@ -163,7 +165,7 @@ MLP_PARAMS = 5 * 64 + 64 + 64 * 64 + 64 + 64 * 2 + 2
 
 EXPORTED = ["slw_status_string", "slw_last_error", "slw_ctx_create", "slw_ctx_set_stream", "slw_ctx_destroy",
             "slw_mesh_upload", "slw_mesh_check", "slw_mesh_free", "slw_mesh_get_info", "slw_mesh_dof_coords", "slw_mesh_dof_order",
-            "slw_mesh_set_walk_limits", "slw_mesh_set_repack", "slw_mesh_set_neighbour_codes", "slw_walk_codes_host", "slw_mesh_set_chain", "slw_mesh_set_xcd_chunk", "slw_mesh_set_hybrid", "slw_mesh_set_boundary", "slw_locate", "slw_locate_feet", "slw_interpolate", "slw_step",
+            "slw_mesh_set_walk_limits", "slw_mesh_set_repack", "slw_mesh_set_neighbour_codes", "slw_walk_codes_host", "slw_mesh_set_chain", "slw_mesh_set_xcd_chunk", "slw_mesh_build_grid", "slw_mesh_set_hybrid", "slw_mesh_set_boundary", "slw_locate", "slw_locate_feet", "slw_interpolate", "slw_step",
             "slw_step_noalloc", "slw_step_autotune", "slw_permute_rows", "slw_orient_sign_host",
             "slw_float_filter_host", "slw_batch_create", "slw_batch_free", "slw_batch_set_fields",
             "slw_batch_set_values", "slw_batch_set_elem_out", "slw_batch_set_step", "slw_batch_get_step", "slw_batch_set_schedule",
@@ -301,6 +303,7 @@ class Mesh:
         self.bbox = tuple(info.bbox)
         self.cdtype = _torch().float32 if self.coords_f32 else _torch().float64
         self.chart_g = 0
+        self.grid_g = 0
 
     # -- mesh queries
     def dof_coords(self) -> np.ndarray:
@@ -327,6 +330,11 @@ class Mesh:
 
     def set_xcd_chunk(self, chunk: int):
         _check(_lib.slw_mesh_set_xcd_chunk(self.h, int(chunk)), "slw_mesh_set_xcd_chunk")
+
+    def build_grid(self, g: int):
+        """slw_mesh_build_grid: the jump-and-walk start grid (g x g cells; 0 removes it)."""
+        _check(_lib.slw_mesh_build_grid(self.h, int(g)), "slw_mesh_build_grid")
+        self.grid_g = int(g)
 
     def set_hybrid(self, far: float):
         _check(_lib.slw_mesh_set_hybrid(self.h, float(far)), "slw_mesh_set_hybrid")

@@ -1,0 +1,116 @@
+"""Jump-and-walk start grid (slw_mesh_build_grid, SLW_START_GRID, and the
+far feet of SLW_START_HYBRID): a start never changes a result, so every
+start gives the steered start's bits and the oracle's elements -- P1 and P2,
+float meshes, feet outside the domain, lane schedules, a non-convex domain,
+the graded mesh at a high Courant number -- and the grid start shortens the
+walks there."""
+import numpy as np
+import pytest
+
+from paper_2104_09189_amd import inputs as I
+from gpu_util import check_elements_near, ctx as _ctx, dev, host, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2104_09189_amd import slwalk
+    return slwalk
+
+
+@pytest.fixture(scope="module")
+def C(S):
+    return _ctx()
+
+
+@pytest.mark.parametrize("flags,order", [(0, 1), (0x2, 2), (0x1, 1)])
+def test_grid_start_same_bits_as_steered(S, C, flags, order):
+    xy, tri = I.permute_mesh(*I.jittered_grid(61, 1501), 6)
+    mesh = S.Mesh(C, xy, tri, flags)
+    fld = I.Field(I.FIELD_AFFINE, (0.4, -1.1, 0.9, 0.2, 0.5, 0.5, 0.35, -0.3))  # some feet leave
+    rows = mesh.n_nodes if order == 1 else mesh.n_dofs
+    v0 = np.random.default_rng(2).normal(size=(rows, 3)).astype(np.float32 if flags & 0x1 else np.float64)
+    e_ref = dev(np.zeros(rows, np.int32))
+    ref, st_ref = mesh.step(fld, 0.3, 0.2, S.SLW_RK2, dev(v0), order=order, elem=e_ref, stats=True)
+    assert st_ref["outside"] > 20
+    for g in (16, 100, 1024):
+        mesh.build_grid(g)
+        e = dev(np.zeros(rows, np.int32))
+        v, st = mesh.step(fld, 0.3, 0.2, S.SLW_RK2, dev(v0), order=order, start_mode=S.START_GRID, elem=e,
+                          stats=True)
+        assert np.array_equal(host(v), host(ref)) and np.array_equal(host(e), host(e_ref)), g
+        assert st["outside"] == st_ref["outside"]
+        # hybrid: far feet from the grid; first step (no previous elements) and the next
+        for _ in range(2):
+            e = dev(np.zeros(rows, np.int32))
+            v = mesh.step(fld, 0.3, 0.2, S.SLW_RK2, dev(v0), order=order, start_mode=S.START_HYBRID, elem=e)
+            assert np.array_equal(host(v), host(ref)) and np.array_equal(host(e), host(e_ref)), g
+    # repacked lanes and slw_locate_feet with the grid start
+    mesh.set_repack(4)
+    v = mesh.step(fld, 0.3, 0.2, S.SLW_RK2, dev(v0), order=order, start_mode=S.START_GRID)
+    assert np.array_equal(host(v), host(ref))
+    mesh.set_repack(0)
+    a = mesh.locate_feet(fld, 0.5, 0.2, S.SLW_RK2)
+    b = mesh.locate_feet(fld, 0.5, 0.2, S.SLW_RK2, start_mode=S.START_GRID)
+    assert np.array_equal(host(a["elem"]), host(b["elem"]))
+    assert np.array_equal(host(a["bary"]), host(b["bary"]), equal_nan=True)
+
+
+def test_grid_start_graded_high_courant_against_oracle(S, C, orc):
+    """The graded mesh (2,002,225 nodes) at Courant 50, RK2, 16 FP32 fields:
+    every element of grid-start and hybrid steps against the oracle, values
+    on a sample, and far shorter walks than strategy (a)."""
+    w = I.graded_swirl(alpha=50.0)
+    mesh = S.Mesh(C, w.xy, w.tri, S.INTERNAL_ORDER)
+    mesh.build_grid(4096)
+    perm = mesh.dof_order()
+    v0 = w.v0.astype(np.float32)
+    vin = dev(v0[perm])
+    t_n = 2 * w.dt
+    q = orc.feet(w.xy, w.field, t_n + w.dt, w.dt, w.scheme)
+    r, b = orc.locate(w.xy, w.tri, q)
+    _, st_a = mesh.step(w.field, t_n, w.dt, w.scheme, vin, stats=True)
+    mesh.step(w.field, t_n - w.dt, w.dt, w.scheme, vin, start_mode=S.START_HYBRID)   # previous elements
+    for mode in (S.START_GRID, S.START_HYBRID):
+        e = dev(np.zeros(mesh.n_nodes, np.int32))
+        v, st = mesh.step(w.field, t_n, w.dt, w.scheme, vin, start_mode=mode, elem=e, stats=True)
+        assert st["walk_steps"] < 0.2 * st_a["walk_steps"], mode
+        e_user = np.empty(mesh.n_nodes, np.int32)
+        e_user[perm] = host(e)
+        check_elements_near(w.xy, w.tri, q, r, e_user, 64 * 2.0 ** -52)
+        sample = np.random.default_rng(92).choice(mesh.n_nodes, 20000, replace=False)
+        ref = orc.interp(1, w.tri, r[perm[sample]], b[perm[sample]], v0.astype(np.float64), w.xy.shape[0])
+        assert rel_err(host(v)[sample], ref, np.abs(v0).max()) < 1e-5
+
+
+def test_grid_start_nonconvex_domain(S, C, orc):
+    """Cell centres in the notch lie outside the mesh (their cells keep a
+    nearby triangle); feet across the notch are located as the oracle does."""
+    xy, tri = I.l_shaped(65, 1601)
+    mesh = S.Mesh(C, xy, tri)
+    mesh.build_grid(200)
+    fld = I.constant(-0.4, 0.4)
+    q = orc.feet(xy, fld, 0.25, 0.25, I.SCHEME_EULER)
+    r, _ = orc.locate(xy, tri, q)
+    out = mesh.locate_feet(fld, 0.25, 0.25, S.SLW_EULER, start_mode=S.START_GRID)
+    assert np.array_equal(host(out["elem"]), r)
+    assert (r < 0).sum() > 50
+
+
+def test_grid_errors_and_removal(S, C):
+    xy, tri = I.jittered_grid(17, 1701)
+    mesh = S.Mesh(C, xy, tri)
+    v0 = dev(np.ones((xy.shape[0], 1)))
+    with pytest.raises(S.SlwError):
+        mesh.step(I.constant(0.1, 0.0), 0.0, 0.1, S.SLW_EULER, v0, start_mode=S.START_GRID)
+    for bad in (-1, 1, 15, 16385):
+        with pytest.raises(S.SlwError):
+            mesh.build_grid(bad)
+    mesh.build_grid(16)
+    mesh.step(I.constant(0.1, 0.0), 0.0, 0.1, S.SLW_EULER, v0, start_mode=S.START_GRID)
+    mesh.build_grid(0)
+    with pytest.raises(S.SlwError):
+        mesh.step(I.constant(0.1, 0.0), 0.0, 0.1, S.SLW_EULER, v0, start_mode=S.START_GRID)
+    # the hybrid falls back to the steered start without grid or chart
+    mesh.step(I.constant(0.1, 0.0), 0.0, 0.1, S.SLW_EULER, v0, start_mode=S.START_HYBRID)
