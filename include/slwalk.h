@@ -262,7 +262,8 @@ slw_status slw_mesh_set_boundary(slw_mesh *mesh, int kind, const double *p_h);
  *     roots are a maximal independent set of the mesh's nodes (greedy in
  *     internal order: about a quarter of them); every other DOF is a child of
  *     the nearest root among the vertices of its incident triangles.  The
- *     roots are stepped first (strategy (a) start), then the children, each
+ *     roots are stepped first (from their cell of the start grid when the mesh
+ *     has one, slw_mesh_build_grid, else strategy (a)), then the children, each
  *     from its parent's element unless its own node lies nearer its foot than
  *     the parent node (then strategy (a)): two kernel launches per step.
  *     Boundary data (slw_mesh_set_boundary) apply.

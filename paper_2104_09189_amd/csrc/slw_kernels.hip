@@ -1627,7 +1627,12 @@ __device__ inline void step_wave(const MeshView &mv, const FieldDev &f, double d
             store_stream(mv.prev + d, w.elem);
         } else if (run) {
             int32_t j0 = jc;
-            if constexpr (KIND == -3 || KIND == -4)
+            if constexpr (KIND == -3)
+                // a root of the forest: from its cell of the start grid when
+                // the mesh has one, else strategy (a)
+                j0 = mv.grid ? grid_start(mv, qx, qy)
+                             : quadrant_start(mv.qstart[d], (float)(qx - x.x), (float)(qy - x.y));
+            else if constexpr (KIND == -4)
                 j0 = sid >= 0 ? sid : quadrant_start(mv.qstart[d], (float)(qx - x.x), (float)(qy - x.y));
             else if constexpr (KIND < 0)
                 j0 = start_pick<KIND == -6>(mv, d, sid, mode, x, qx, qy);

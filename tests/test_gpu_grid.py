@@ -1,9 +1,9 @@
-"""Jump-and-walk start grid (slw_mesh_build_grid, SLW_START_GRID, and the
-far feet of SLW_START_HYBRID): a start never changes a result, so every
-start gives the steered start's bits and the oracle's elements -- P1 and P2,
-float meshes, feet outside the domain, lane schedules, a non-convex domain,
-the graded mesh at a high Courant number -- and the grid start shortens the
-walks there."""
+"""Jump-and-walk start grid (slw_mesh_build_grid, SLW_START_GRID, the far
+feet of SLW_START_HYBRID and the forest's roots): a start never changes a
+result, so every start gives the steered start's bits and the oracle's
+elements -- P1 and P2, float meshes, feet outside the domain, lane
+schedules, a non-convex domain, the graded mesh at a high Courant number --
+and the grid start shortens the walks there."""
 import numpy as np
 import pytest
 
@@ -46,6 +46,10 @@ def test_grid_start_same_bits_as_steered(S, C, flags, order):
             e = dev(np.zeros(rows, np.int32))
             v = mesh.step(fld, 0.3, 0.2, S.SLW_RK2, dev(v0), order=order, start_mode=S.START_HYBRID, elem=e)
             assert np.array_equal(host(v), host(ref)) and np.array_equal(host(e), host(e_ref)), g
+        # strategy (c) on the forest: roots from the grid
+        e = dev(np.zeros(rows, np.int32))
+        v = mesh.step(fld, 0.3, 0.2, S.SLW_RK2, dev(v0), order=order, start_mode=S.START_NEIGHBOR, elem=e)
+        assert np.array_equal(host(v), host(ref)) and np.array_equal(host(e), host(e_ref)), g
     # repacked lanes and slw_locate_feet with the grid start
     mesh.set_repack(4)
     v = mesh.step(fld, 0.3, 0.2, S.SLW_RK2, dev(v0), order=order, start_mode=S.START_GRID)
@@ -59,8 +63,9 @@ def test_grid_start_same_bits_as_steered(S, C, flags, order):
 
 def test_grid_start_graded_high_courant_against_oracle(S, C, orc):
     """The graded mesh (2,002,225 nodes) at Courant 50, RK2, 16 FP32 fields:
-    every element of grid-start and hybrid steps against the oracle, values
-    on a sample, and far shorter walks than strategy (a)."""
+    every element of grid-start, hybrid and forest steps (roots from the
+    grid) against the oracle, values on a sample, and far shorter walks than
+    strategy (a)."""
     w = I.graded_swirl(alpha=50.0)
     mesh = S.Mesh(C, w.xy, w.tri, S.INTERNAL_ORDER)
     mesh.build_grid(4096)
@@ -72,7 +77,7 @@ def test_grid_start_graded_high_courant_against_oracle(S, C, orc):
     r, b = orc.locate(w.xy, w.tri, q)
     _, st_a = mesh.step(w.field, t_n, w.dt, w.scheme, vin, stats=True)
     mesh.step(w.field, t_n - w.dt, w.dt, w.scheme, vin, start_mode=S.START_HYBRID)   # previous elements
-    for mode in (S.START_GRID, S.START_HYBRID):
+    for mode in (S.START_GRID, S.START_HYBRID, S.START_NEIGHBOR):
         e = dev(np.zeros(mesh.n_nodes, np.int32))
         v, st = mesh.step(w.field, t_n, w.dt, w.scheme, vin, start_mode=mode, elem=e, stats=True)
         assert st["walk_steps"] < 0.2 * st_a["walk_steps"], mode
