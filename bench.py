@@ -463,10 +463,10 @@ def measure_courant_range(mesh, w, v0, steps=20, warmup=3, alphas=(1.0, 5.0, 20.
                            ("c_forest", S.START_NEIGHBOR), ("chart_exact", S.START_CHART),
                            ("grid", S.START_GRID), ("hybrid", S.START_HYBRID)):
             # the library's defaults: one foot per lane, the forest, hybrid
-            # threshold 8, chunks of 64 tiles per XCD turn
+            # threshold automatic (0), chunks of 64 tiles per XCD turn
             mesh.set_repack(0)
             mesh.set_chain(0)
-            mesh.set_hybrid(8.0)
+            mesh.set_hybrid(0.0)
             mesh.set_xcd_chunk(64)
             r = measure(mesh, wa, v0, steps, warmup, mode)
             # walk lengths of the step ending near t = 1/4 (the swirl's time
@@ -491,7 +491,7 @@ def measure_courant_range(mesh, w, v0, steps=20, warmup=3, alphas=(1.0, 5.0, 20.
                                    "kernel_ms": rt["kernel_ms"]}
         mesh.set_repack(0)
         mesh.set_chain(0)
-        mesh.set_hybrid(8.0)
+        mesh.set_hybrid(0.0)
         mesh.set_xcd_chunk(64)
         best = min((v["kernel_ms"], k) for k, v in line.items() if k != "dt")
         line["fastest"] = best[1]

@@ -110,7 +110,8 @@ enum {
     SLW_START_STEERED = 0, /* strategy (a): the DOF's incident triangle facing the foot */
     SLW_START_GIVEN = 1,   /* start[dof] = user triangle id */
     SLW_START_PREV = 2,    /* strategy (b): the element found for this DOF by the previous
-                              SLW_START_PREV call on this mesh (steered when there is none) */
+                              SLW_START_PREV call on this mesh (steered when there is none);
+                              meshes of fewer than 2^29 triangles (SLW_E_UNSUPPORTED) */
     SLW_START_FIXED = 3,   /* every walk starts at user triangle start[0] (the paper's
                               fixed-start baseline, Section 2.2 complexity) */
     SLW_START_LEARNED = 4, /* the triangle proposed by the network attached with
@@ -128,7 +129,10 @@ enum {
                               when the foot is in it or near it, else the foot's cell of the
                               start grid (as SLW_START_GRID) when the mesh has one, else its
                               chart cell (as SLW_START_CHART) when the mesh has a chart, else
-                              the steered start; keeps the previous elements as SLW_START_PREV */
+                              the steered start; keeps the previous elements as SLW_START_PREV.
+                              With a grid or a chart, a foot found far from its previous
+                              element goes straight to the grid or chart for the next three
+                              steps, then is tested again */
     SLW_START_GRID = 9     /* the triangle recorded for the foot's cell of the uniform start
                               grid (jump-and-walk; needs slw_mesh_build_grid) */
 };
@@ -302,9 +306,12 @@ slw_status slw_mesh_build_grid(slw_mesh *mesh, int g);
  * theta_min, its smallest barycentric coordinate there, measures how far
  * (about -theta_min heights of that element beyond its nearest side).  With
  * theta_min > -far the walk continues from the previous element; otherwise
- * (and without a previous element) it starts from the foot's chart cell
- * when slw_chart_build was called, else from the steered start.  far > 0;
- * default 8.  Results never depend on it. */
+ * (and without a previous element) it starts from the foot's cell of the
+ * start grid when slw_mesh_build_grid was called, else from its chart cell
+ * when slw_chart_build was called, else from the steered start.  far > 0, or
+ * 0 (the default) for the measured best of each case: 1 with a grid, 16 with
+ * a chart alone, 64 with neither.  Negative or non-finite: SLW_E_ARG.
+ * Results never depend on it. */
 slw_status slw_mesh_set_hybrid(slw_mesh *mesh, float far);
 
 /* General point location, the analogue of the paper's [I, B] =
@@ -349,11 +356,13 @@ slw_status slw_step(slw_mesh *mesh, const slw_field *field, double t_n, double d
  * slw_step) it times every candidate value of the knob that matters for
  * start_mode -- the lane schedule of slw_mesh_set_repack (1, 2, 4, 8 feet
  * per lane) for the steered, given, fixed, previous, chart and learned
- * starts; the threshold of slw_mesh_set_hybrid (2 ... 64) for
+ * starts; the threshold of slw_mesh_set_hybrid (0.5 ... 64) for
  * SLW_START_HYBRID; the forest or chain length of slw_mesh_set_chain (0, 2,
  * 4, 8, 16) for SLW_START_NEIGHBOR -- then, for the value chosen, the XCD
- * chunk of slw_mesh_set_xcd_chunk (0, 16, 32, 64, 128); each candidate over
- * five launches (the median).  It keeps only candidates whose step is
+ * chunk of slw_mesh_set_xcd_chunk (0, 16, 32, 64, 128); each candidate
+ * timed over five consecutive steps from t_n (the median), after one untimed
+ * step from t_n - dt that starts from the mesh's previous elements (the
+ * hybrid's skip counts cleared).  It keeps only candidates whose step is
  * bit-identical to the one of the mesh's current setting, applies the
  * fastest to the mesh and records it in
  * the JSON file cache_path (nullable) under a signature of the step (size,

@@ -135,6 +135,8 @@ slw_status step_impl(slw_mesh *mesh, const slw_field *field, double t_n, double 
         return set_error(SLW_E_ARG, w + ": unknown start mode");
     if (start_mode == SLW_START_GRID && !mesh->m.grid)
         return set_error(SLW_E_ARG, w + ": SLW_START_GRID needs a start grid (slw_mesh_build_grid)");
+    if ((start_mode == SLW_START_PREV || start_mode == SLW_START_HYBRID) && mesh->m.n_tris >= ((int64_t)1 << 29))
+        return set_error(SLW_E_UNSUPPORTED, w + ": previous elements need fewer than 2^29 triangles");
     if ((start_mode == SLW_START_GIVEN || start_mode == SLW_START_FIXED) && !start)
         return set_error(SLW_E_ARG, w + ": start array required for this start mode");
     if ((start_mode == SLW_START_LEARNED || start_mode == SLW_START_LEARNED_INDEX) && !mesh->m.mlp)
@@ -450,8 +452,8 @@ slw_status slw_mesh_set_hybrid(slw_mesh *mesh, float far)
 {
     if (!mesh)
         return set_error(SLW_E_ARG, "mesh is NULL");
-    if (!(far > 0.0f) || !std::isfinite(far))
-        return set_error(SLW_E_ARG, "slw_mesh_set_hybrid: far must be a positive finite number");
+    if (!(far >= 0.0f) || !std::isfinite(far))
+        return set_error(SLW_E_ARG, "slw_mesh_set_hybrid: far must be 0 (automatic) or a positive finite number");
     mesh->m.hybrid_far = far;
     return SLW_OK;
 }
@@ -574,6 +576,8 @@ slw_status slw_locate_feet(slw_mesh *mesh, const slw_field *field, double t_np1,
         return set_error(SLW_E_ARG, "unknown start mode (SLW_START_NEIGHBOR and SLW_START_HYBRID are for slw_step)");
     if (start_mode == SLW_START_GRID && !mesh->m.grid)
         return set_error(SLW_E_ARG, "SLW_START_GRID needs a start grid (slw_mesh_build_grid)");
+    if (start_mode == SLW_START_PREV && mesh->m.n_tris >= ((int64_t)1 << 29))
+        return set_error(SLW_E_UNSUPPORTED, "previous elements need fewer than 2^29 triangles");
     if ((start_mode == SLW_START_GIVEN || start_mode == SLW_START_FIXED) && !start)
         return set_error(SLW_E_ARG, "start array required for this start mode");
     if ((start_mode == SLW_START_LEARNED || start_mode == SLW_START_LEARNED_INDEX) && !mesh->m.mlp)
@@ -1252,7 +1256,7 @@ constexpr int kXcdChunks[] = {0, 16, 32, 64, 128};
 std::vector<double> knob_values(int mode, bool bc)
 {
     if (mode == SLW_START_HYBRID)
-        return {2, 4, 8, 16, 32, 64};
+        return {0.5, 1, 2, 4, 8, 16, 32, 64};
     if (mode == SLW_START_NEIGHBOR)
         return bc ? std::vector<double>{0} : std::vector<double>{0, 2, 4, 8, 16};
     if (mode == SLW_START_LEARNED_INDEX || bc)
@@ -1390,8 +1394,10 @@ extern "C" slw_status slw_step_autotune(slw_mesh *mesh, const slw_field *field, 
         }
     }
     // one candidate (the knobs as set on the mesh): its step from the same
-    // state must give the reference's bits (else it is never chosen); then
-    // five launches, each from the caller's previous elements; the median
+    // state must give the reference's bits (else it is never chosen); then,
+    // from the caller's previous elements (the hybrid's skip counts
+    // cleared, so that each candidate sets its own), one untimed step from
+    // t_n - dt and five timed consecutive steps from t_n; the median
     auto time_candidate = [&](float &median) -> bool {
         st = restore_prev();
         if (st == SLW_OK)
@@ -1404,13 +1410,17 @@ extern "C" slw_status slw_step_autotune(slw_mesh *mesh, const slw_field *field, 
         if (st != SLW_OK || std::memcmp(out_h.data(), ref_h.data(), bytes) != 0)
             return false;
         std::vector<float> ts;
+        st = restore_prev();
+        if (st == SLW_OK && keeps_prev)
+            st = hip_check(launch_prev_clear_skip(ctx->stream, m.prev_elem, m.n_dofs), "clear skip counts");
+        if (st == SLW_OK)
+            st = step_impl(mesh, field, t_n - dt, dt, scheme, order, start_mode, start, v_in, vdtype, k, vout, 0.0,
+                           nullptr, nullptr, StepScratch(), "slw_step_autotune");
         for (int r = 0; r < 5 && st == SLW_OK; ++r) {
-            st = restore_prev();
+            st = hip_check(hipEventRecord(e0, ctx->stream), "event");
             if (st == SLW_OK)
-                st = hip_check(hipEventRecord(e0, ctx->stream), "event");
-            if (st == SLW_OK)
-                st = step_impl(mesh, field, t_n, dt, scheme, order, start_mode, start, v_in, vdtype, k, vout, 0.0,
-                               nullptr, nullptr, StepScratch(), "slw_step_autotune");
+                st = step_impl(mesh, field, t_n + r * dt, dt, scheme, order, start_mode, start, v_in, vdtype, k, vout,
+                               0.0, nullptr, nullptr, StepScratch(), "slw_step_autotune");
             if (st == SLW_OK)
                 st = hip_check(hipEventRecord(e1, ctx->stream), "event");
             if (st == SLW_OK)

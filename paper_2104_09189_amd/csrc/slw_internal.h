@@ -112,7 +112,7 @@ struct DevMesh {
     int64_t device_bytes = 0;
     int32_t step_cap = 4096;
     int32_t hard_limit = 1 << 22;
-    float hybrid_far = 8.0f;  // SLW_START_HYBRID: feet farther than this many heights of their previous element use the chart
+    float hybrid_far = 0.0f;  // SLW_START_HYBRID: feet farther than this many heights of their previous element start afresh (0: automatic)
     int repack = 0;  // step kernel: 0 one foot per lane; 2, 4, 8: chunks of 64 x repack feet per wavefront
     int chain = 0;   // strategy (c): 0 the mesh forest below; 2, 4, 8, 16 Morton chains of that length per lane
     int xcd_chunk = 64;  // tiles per XCD turn: 0 one contiguous range of tiles per XCD; C > 0 chunks of C tiles dealt round-robin
@@ -309,6 +309,7 @@ hipError_t launch_qt_locate(const DevMesh &m, hipStream_t st, const void *q, int
                             DevStats *stats);
 hipError_t launch_grid_build(const DevMesh &m, hipStream_t st, int32_t *grid, int g, double x0, double y0,
                              double cell);
+hipError_t launch_prev_clear_skip(hipStream_t st, int32_t *prev, int64_t n);
 hipError_t launch_locate_feet(const DevMesh &m, hipStream_t st, const FieldDev *f, double t_np1, double dt,
                               int scheme, int start_mode, const int32_t *start, bool feet_in, void *feet,
                               int32_t *elem, void *bary, int32_t *steps, DevStats *stats);

@@ -59,6 +59,13 @@ __device__ inline void store_stream(double *p, double v) { __builtin_nontemporal
 __device__ inline void store_stream(int32_t *p, int32_t v) { __builtin_nontemporal_store(v, p); }
 __device__ inline int32_t load_stream(const int32_t *p) { return __builtin_nontemporal_load(p); }
 
+// The previous element of a DOF (strategies (b) and the hybrid) is an
+// internal triangle id below 2^29; the hybrid keeps in bits 29-30 how many
+// more steps the DOF skips the test on it (its foot moved far lately).
+constexpr int32_t kPrevElemMask = (1 << 29) - 1;
+constexpr int kPrevSkipShift = 29;
+constexpr int kPrevSkipSteps = 3;
+
 // ---------------------------------------------------------------------------
 // advecting fields (kinds as in slw_field) and feet
 
@@ -149,7 +156,9 @@ MeshView view_of(const DevMesh &m)
     v.fc = m.fc;
     v.step_cap = m.step_cap;
     v.hard_limit = m.hard_limit;
-    v.hybrid_far = m.hybrid_far;
+    // the hybrid's threshold; 0 picks the best measured for the far-foot
+    // start the mesh has (one grid read; two binary searches; the steered start)
+    v.hybrid_far = m.hybrid_far > 0.0f ? m.hybrid_far : (m.grid ? 1.0f : (m.chart_table ? 16.0f : 64.0f));
     v.xcd_chunk = m.xcd_chunk;
     v.bnext = m.bnext;
     v.bprev = m.bprev;
@@ -218,8 +227,10 @@ __device__ inline int32_t start_id(const MeshView &mv, int64_t d, int64_t api, i
 {
     if (mode == SLW_START_GIVEN || mode == SLW_START_FIXED)
         return start[mode == SLW_START_GIVEN ? api : 0];  // user id
-    if (mode == SLW_START_PREV)
-        return load_stream(mv.prev + d);
+    if (mode == SLW_START_PREV) {
+        const int32_t v = load_stream(mv.prev + d);
+        return v >= 0 ? (v & kPrevElemMask) : v;  // without the hybrid's skip count
+    }
     if (mode == SLW_START_LEARNED || mode == SLW_START_CHART || mode == SLW_START_LEARNED_INDEX)
         return start[d];  // internal id from the chart
     return -1;
@@ -1566,7 +1577,7 @@ __device__ inline void step_wave(const MeshView &mv, const FieldDev &f, double d
             p = fv.parent[pos];
             sid = p >= 0 ? fv.elem[p] : -1;
         } else if constexpr (KIND == -5) {
-            sid = load_stream(mv.prev + d);  // the previous step's element (strategy (b))
+            sid = load_stream(mv.prev + d);  // the previous step's element (strategy (b)), with its skip count
         } else if constexpr (KIND < 0 && KIND != -3) {
             const int64_t api = (mode == SLW_START_GIVEN && !mv.internal_order) ? mv.dof_user[d] : d;
             sid = start_id(mv, d, api, mode, start);
@@ -1603,17 +1614,27 @@ __device__ inline void step_wave(const MeshView &mv, const FieldDev &f, double d
             // grid when the mesh has one, else from its chart cell when the
             // mesh has a chart (the nearer of that cell's triangle and the
             // steered start), else from the steered start (strategy (a)).
+            // A foot found far from its previous element skips that test for
+            // the next kPrevSkipSteps steps (feet of a fast flow stay fast).
+            // (Only with a grid or a chart: without them a far foot starts
+            // from the steered start, slower than walking on.)
+            const bool far_start = mv.grid || mv.chart_table;
+            const int skip = (sid >= 0 && far_start) ? (sid >> kPrevSkipShift) : 0;
+            const int32_t pe = sid >= 0 ? (sid & kPrevElemMask) : -1;
+            int next_skip = skip > 0 ? skip - 1 : 0;
             if (run) {
                 bool done = false;
                 int32_t j0 = -1;
                 // (the grid cell is read only for feet that need it: read
                 // beside the previous element's record for every foot, it
                 // measured slower at low Courant numbers)
-                if (sid >= 0) {
+                if (pe >= 0 && skip == 0) {
                     float tmin = 0.f;
-                    done = first_test<F32>(mv, sid, qx, qy, tmin, w, ls.c) != 0;
+                    done = first_test<F32>(mv, pe, qx, qy, tmin, w, ls.c) != 0;
                     if (!done && tmin > -mv.hybrid_far)
-                        j0 = sid;
+                        j0 = pe;
+                    else if (!done && far_start)
+                        next_skip = kPrevSkipSteps;
                 }
                 if (!done) {
                     if (j0 < 0)
@@ -1624,7 +1645,7 @@ __device__ inline void step_wave(const MeshView &mv, const FieldDev &f, double d
                     w = walk<F32>(mv, j0, qx, qy, (uint32_t)d * 2654435761u, ls.c);
                 }
             }
-            store_stream(mv.prev + d, w.elem);
+            store_stream(mv.prev + d, w.elem >= 0 ? (w.elem | (next_skip << kPrevSkipShift)) : w.elem);
         } else if (run) {
             int32_t j0 = jc;
             if constexpr (KIND == -3)
@@ -2231,6 +2252,28 @@ hipError_t launch_qt_locate(const DevMesh &m, hipStream_t st, const void *q, int
     else
         hipLaunchKernelGGL(k_qt_locate<false>, dim3(g), dim3(kBlock), 0, st, mv, (const double2 *)q, mp, elem,
                            (double *)bary, stats);
+    return hipGetLastError();
+}
+
+// previous elements without the hybrid's skip counts
+__global__ void k_prev_clear_skip(int32_t *__restrict__ prev, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) {
+        const int32_t v = prev[i];
+        if (v >= 0)
+            prev[i] = v & kPrevElemMask;
+    }
+}
+
+hipError_t launch_prev_clear_skip(hipStream_t st, int32_t *prev, int64_t n)
+{
+    if (n <= 0)
+        return hipSuccess;
+    const int64_t blocks = (n + kBlock - 1) / kBlock;
+    if (blocks > (int64_t)INT32_MAX)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_prev_clear_skip, dim3((unsigned)blocks), dim3(kBlock), 0, st, prev, n);
     return hipGetLastError();
 }
 

@@ -37,7 +37,7 @@ def test_step_autotune_modes_cache_and_state(S, C, tmp_path):
     ref = host(mesh.step(w.field, 0.3, w.dt, w.scheme, vin)).copy()
     choices = {}
     for mode, allowed in ((S.START_STEERED, (1, 2, 4, 8)), (S.START_NEIGHBOR, (0, 2, 4, 8, 16)),
-                          (S.START_HYBRID, (2, 4, 8, 16, 32, 64))):
+                          (S.START_HYBRID, (0.5, 1, 2, 4, 8, 16, 32, 64))):
         if mode == S.START_HYBRID:
             # previous elements from an earlier step, on both meshes
             mesh.step(w.field, 0.1, w.dt, w.scheme, vin, start_mode=mode)

@@ -59,13 +59,14 @@ def test_hybrid_threshold_and_no_chart_change_nothing(S, C, orc):
     for chart in (False, True):
         if chart:
             mesh.chart_build(512)
-        for far in (0.25, 8.0, 1e30):
+        for far in (0.25, 8.0, 1e30, 0.0):
             mesh.set_hybrid(far)
             _step(S, mesh, w, 0.2, vin, S.START_HYBRID)          # previous elements from another time
             v, e, st = _step(S, mesh, w, 0.3, vin, S.START_HYBRID)
             assert np.array_equal(v, ref_v) and np.array_equal(e, ref_e), (chart, far)
             assert rel_err(v, ref, np.abs(w.v0).max()) < 1e-12
-    with pytest.raises(S.SlwError):
-        mesh.set_hybrid(0.0)
+    for bad in (-1.0, float("inf"), float("nan")):
+        with pytest.raises(S.SlwError):
+            mesh.set_hybrid(bad)
     with pytest.raises(S.SlwError):
         mesh.locate_feet(w.field, 0.3, w.dt, w.scheme, start_mode=S.START_HYBRID)
