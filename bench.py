@@ -295,13 +295,34 @@ def measure_batch(steps=100):
     n_tris = sum(m.n_tris for m in meshes)
     abytes = n_nodes * (8 + 4 + 4 + 2 * 4) + 12 * n_tris
     g.free()
+    # the same batch with strategy (b)'s start (each mesh's previous
+    # elements), its own autotuned schedule, 100 steps in one graph
+    b.set_start(S.START_PREV)
+    b.set_step(0)
+    b.step(S.SLW_EULER)                                    # previous elements for the autotuner
+    schedule_b, block_b = b.autotune(S.SLW_EULER)
+    b.set_step(0)
+    gb = b.capture(steps, S.SLW_EULER)
+    gb.launch()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    gb.launch()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    prev_ms = e0.elapsed_time(e1) / steps
+    st_b = b.step(S.SLW_EULER, stats=True)
+    gb.free()
     b.free()
     return {"workload": f"{len(meshes)} jittered meshes, swirl, Courant 5, float coordinates, 1 field, Hilbert order",
             "n_nodes": n_nodes, "n_tris": n_tris, "steps_in_graph": steps, "schedule": schedule, "block": block,
             "ms_per_step": graph_ms, "feet_per_s": n_nodes / (graph_ms * 1e-3),
             "roofline_frac": abytes / (graph_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "mean_walk_steps": st["walk_steps"] / max(st["feet"], 1),
-            "plain_one_launch_per_mesh_ms_per_step": plain_ms, "speedup_vs_plain": plain_ms / graph_ms}
+            "plain_one_launch_per_mesh_ms_per_step": plain_ms, "speedup_vs_plain": plain_ms / graph_ms,
+            "previous_element_start": {"schedule": schedule_b, "block": block_b, "ms_per_step": prev_ms,
+                                       "feet_per_s": n_nodes / (prev_ms * 1e-3),
+                                       "roofline_frac": abytes / (prev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                       "mean_walk_steps": st_b["walk_steps"] / max(st_b["feet"], 1)}}
 
 
 def _walk_histogram(steps: np.ndarray) -> dict:

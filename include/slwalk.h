@@ -439,6 +439,16 @@ slw_status slw_batch_get_step(slw_batch *b, int64_t *n_h);
 /* schedule 0 (static, XCD-contiguous), 1 (persistent queues) or 2 (static, XCD chunks); workgroup size
  * 64, 128, 256 or 512 */
 slw_status slw_batch_set_schedule(slw_batch *b, int schedule, int block);
+/* The start of every mesh's walks: SLW_START_STEERED (the default, strategy
+ * (a)) or SLW_START_PREV (strategy (b), Section 3 (b): the element found for
+ * the node at the mesh's previous SLW_START_PREV step, batched or not; the
+ * steered start where there is none).  Graphs read the batch's item table
+ * at each replay, so graphs captured earlier follow the new mode (and the
+ * element outputs of slw_batch_set_elem_out); after slw_batch_set_schedule
+ * or slw_batch_autotune changes the workgroup size, capture again.  Results
+ * never depend on the mode.  SLW_E_ARG for other modes; SLW_E_UNSUPPORTED
+ * for meshes of 2^29 triangles or more. */
+slw_status slw_batch_set_start(slw_batch *b, int start_mode);
 /* one step of every mesh (asynchronous unless stats_h is given) */
 slw_status slw_batch_step(slw_batch *b, int scheme, double outside_value, slw_stats *stats_h);
 /* Capture n_steps batch steps into a HIP graph (on a private stream; no
@@ -451,9 +461,10 @@ slw_status slw_graph_free(slw_graph *g);
  * batch's current values, keeps only candidates whose first step is bit-
  * identical to the reference candidate's, selects the fastest and records it
  * in the JSON file cache_path (nullable) under a signature of the batch
- * (mesh count, DOF count bucket, types, k); a later call with a cached
- * signature applies the cached choice without timing.  Synchronous; the
- * caller's values and step index are left as they were. */
+ * (mesh count, DOF count bucket, types, k, start mode); a later call with a
+ * cached signature applies the cached choice without timing.  Synchronous;
+ * the caller's values, step index and (with SLW_START_PREV) the meshes'
+ * previous elements are left as they were. */
 slw_status slw_batch_autotune(slw_batch *b, int scheme, const char *cache_path, int *schedule_out, int *block_out);
 
 /* ------------------------------------------------------------------------

@@ -860,6 +860,19 @@ slw_status slw_batch_set_elem_out(slw_batch *b, int32_t *const *elem_h)
     return batch_upload_items(b);
 }
 
+slw_status slw_batch_set_start(slw_batch *b, int start_mode)
+{
+    if (!b || (start_mode != SLW_START_STEERED && start_mode != SLW_START_PREV))
+        return set_error(SLW_E_ARG, "slw_batch_set_start: SLW_START_STEERED or SLW_START_PREV");
+    for (slw_mesh *m : b->meshes)
+        if (start_mode == SLW_START_PREV && m->m.n_tris >= ((int64_t)1 << 29))
+            return set_error(SLW_E_UNSUPPORTED, "slw_batch_set_start: previous elements need fewer than 2^29 triangles");
+    for (auto &it : b->items_h)
+        it.start_mode = start_mode;
+    DeviceGuard g(b->ctx->device);
+    return batch_upload_items(b);
+}
+
 slw_status slw_batch_set_step(slw_batch *b, int64_t n)
 {
     if (!b || n < 0)
@@ -991,7 +1004,8 @@ std::string batch_signature(const slw_batch *b)
         ++bucket;
     std::ostringstream os;
     os << "meshes" << b->items_h.size() << "_dofs2^" << bucket << "_c" << (b->coords_f32 ? "f32" : "f64") << "_v"
-       << (b->vdtype == SLW_F32 ? "f32" : "f64") << "_k" << b->k;
+       << (b->vdtype == SLW_F32 ? "f32" : "f64") << "_k" << b->k
+       << (b->items_h.empty() || b->items_h[0].start_mode == SLW_START_STEERED ? "" : "_prev");
     return os.str();
 }
 
@@ -1084,6 +1098,32 @@ extern "C" slw_status slw_batch_autotune(slw_batch *b, int scheme, const char *c
     std::vector<slw::BatchItem> saved = b->items_h;
     int64_t saved_step = 0;
     slw_status st = hip_check(hipStreamSynchronize(b->ctx->stream), "hipStreamSynchronize");
+    // with the previous-element start every candidate starts from the
+    // meshes' previous elements as they are now, and they are left so
+    const bool keeps_prev = !b->items_h.empty() && b->items_h[0].start_mode == SLW_START_PREV;
+    size_t prev_total = 0;
+    if (keeps_prev)
+        for (slw_mesh *m : b->meshes)
+            prev_total += (size_t)m->m.n_dofs;
+    int32_t *prev_saved = nullptr;
+    if (st == SLW_OK && keeps_prev && hipMalloc((void **)&prev_saved, prev_total * sizeof(int32_t)) != hipSuccess)
+        st = set_error(SLW_E_NOMEM, "autotune workspace (previous elements)");
+    auto copy_prev = [&](bool save) -> slw_status {
+        size_t o = 0;
+        for (slw_mesh *m : b->meshes) {
+            const size_t nb = (size_t)m->m.n_dofs * sizeof(int32_t);
+            slw_status s2 = hip_check(hipMemcpy(save ? (void *)(prev_saved + o) : (void *)m->m.prev_elem,
+                                                save ? (const void *)m->m.prev_elem : (const void *)(prev_saved + o),
+                                                nb, hipMemcpyDeviceToDevice),
+                                      "copy previous elements");
+            if (s2 != SLW_OK)
+                return s2;
+            o += (size_t)m->m.n_dofs;
+        }
+        return SLW_OK;
+    };
+    if (st == SLW_OK && keeps_prev)
+        st = copy_prev(true);
     if (st == SLW_OK)
         st = hip_check(hipMemcpy(&saved_step, b->counter, sizeof saved_step, hipMemcpyDeviceToHost), "counter");
     const int saved_schedule = b->schedule, saved_block = b->block;
@@ -1115,7 +1155,10 @@ extern "C" slw_status slw_batch_autotune(slw_batch *b, int scheme, const char *c
             if (st != SLW_OK)
                 break;
             // parity guard: one step from the copy of the input (even step: A -> B)
-            st = slw_batch_set_step(b, even_step);
+            if (keeps_prev)
+                st = copy_prev(false);
+            if (st == SLW_OK)
+                st = slw_batch_set_step(b, even_step);
             if (st == SLW_OK)
                 st = batch_launch(b, scheme, 0.0, nullptr, b->ctx->stream);
             if (st == SLW_OK)
@@ -1169,6 +1212,12 @@ extern "C" slw_status slw_batch_autotune(slw_batch *b, int scheme, const char *c
     b->block = st == SLW_OK ? best_b : saved_block;
     slw_status st2 = batch_upload_items(b);
     slw_status st3 = slw_batch_set_step(b, saved_step);
+    if (prev_saved) {
+        const slw_status st4 = copy_prev(false);
+        if (st2 == SLW_OK)
+            st2 = st4;
+        (void)hipFree(prev_saved);
+    }
     (void)hipFree(work);
     if (st != SLW_OK)
         return st;

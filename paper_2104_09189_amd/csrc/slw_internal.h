@@ -339,6 +339,7 @@ struct BatchItem {
     int32_t *elem;   // nullable: user triangle id of each node's foot (-1 outside), internal node order
     int64_t n_iter;  // DOFs stepped (the nodes: P1)
     int64_t tile0;   // first tile of this mesh in the concatenated tile space
+    int start_mode;  // SLW_START_STEERED or SLW_START_PREV (the mesh's previous elements)
 };
 hipError_t launch_batch_step(hipStream_t st, int coords_f32, int vdtype, int block, int schedule,
                              const BatchItem *items, int n_items, int64_t total_tiles, int64_t *counter, int scheme,

@@ -1848,8 +1848,8 @@ __device__ __forceinline__ void batch_tile(const BatchItem *__restrict__ items, 
     const V *vin = (const V *)(even ? it.va : it.vb);
     V *vout = (V *)(even ? it.vb : it.va);
     const int64_t base = (tile - it.tile0) * BS + (threadIdx.x & ~(kWave - 1));
-    step_wave<F32, V, 3>(it.mv, f, it.dt, it.t0 + (double)(step + 1) * it.dt, scheme, SLW_START_STEERED, nullptr,
-                         vin, k, vout, outside, 0, nullptr, it.elem, it.n_iter, base, st);
+    step_wave<F32, V, 3>(it.mv, f, it.dt, it.t0 + (double)(step + 1) * it.dt, scheme, it.start_mode, nullptr, vin,
+                         k, vout, outside, it.start_mode == SLW_START_PREV, nullptr, it.elem, it.n_iter, base, st);
 }
 
 // schedule 0: one workgroup per tile, XCD-contiguous ranges of the

@@ -135,6 +135,7 @@ _sig("slw_batch_set_elem_out", ctypes.c_int, [_vp, _vp])
 _sig("slw_batch_set_step", ctypes.c_int, [_vp, _i64])
 _sig("slw_batch_get_step", ctypes.c_int, [_vp, ctypes.POINTER(_i64)])
 _sig("slw_batch_set_schedule", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int])
+_sig("slw_batch_set_start", ctypes.c_int, [_vp, ctypes.c_int])
 _sig("slw_batch_step", ctypes.c_int, [_vp, ctypes.c_int, _dbl, ctypes.POINTER(slw_stats)])
 _sig("slw_batch_graph_capture", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _dbl, ctypes.POINTER(_vp)])
 _sig("slw_graph_launch", ctypes.c_int, [_vp])
@@ -168,7 +169,7 @@ EXPORTED = ["slw_status_string", "slw_last_error", "slw_ctx_create", "slw_ctx_se
             "slw_mesh_set_walk_limits", "slw_mesh_set_repack", "slw_mesh_set_neighbour_codes", "slw_walk_codes_host", "slw_mesh_set_chain", "slw_mesh_set_xcd_chunk", "slw_mesh_build_grid", "slw_mesh_set_hybrid", "slw_mesh_set_boundary", "slw_locate", "slw_locate_feet", "slw_interpolate", "slw_step",
             "slw_step_noalloc", "slw_step_autotune", "slw_permute_rows", "slw_orient_sign_host",
             "slw_float_filter_host", "slw_batch_create", "slw_batch_free", "slw_batch_set_fields",
-            "slw_batch_set_values", "slw_batch_set_elem_out", "slw_batch_set_step", "slw_batch_get_step", "slw_batch_set_schedule",
+            "slw_batch_set_values", "slw_batch_set_elem_out", "slw_batch_set_step", "slw_batch_get_step", "slw_batch_set_start", "slw_batch_set_schedule",
             "slw_batch_step", "slw_batch_graph_capture", "slw_graph_launch", "slw_graph_free", "slw_batch_autotune",
             "slw_chart_build", "slw_chart_coords", "slw_mlp_create", "slw_mlp_free", "slw_mlp_set_params",
             "slw_mlp_get_params", "slw_mlp_set_normalization", "slw_mlp_get_normalization",
@@ -599,6 +600,10 @@ class Batch:
 
     def set_schedule(self, schedule: int, block: int = 256):
         _check(_lib.slw_batch_set_schedule(self.h, int(schedule), int(block)), "slw_batch_set_schedule")
+
+    def set_start(self, start_mode: int):
+        """slw_batch_set_start: START_STEERED or START_PREV."""
+        _check(_lib.slw_batch_set_start(self.h, int(start_mode)), "slw_batch_set_start")
 
     def step(self, scheme=SLW_EULER, outside_value=0.0, stats=False):
         st = slw_stats() if stats else None

@@ -125,3 +125,77 @@ def test_batch_rejects_mixed_meshes(S, C):
     m3 = S.Mesh(C, xy, tri, S.INTERNAL_ORDER | S.COORDS_F32)
     with pytest.raises(S.SlwError):
         S.Batch(C, [m1, m3])
+
+
+def test_batch_previous_element_start(S, C, orc):
+    """slw_batch_set_start(SLW_START_PREV): every step gives the steered
+    start's bits (values and elements) for every schedule, the walks after
+    the first step are far shorter, graph replays equal eager steps, and the
+    autotuner leaves the previous elements as they were (the next step walks
+    as a twin batch with the same history does)."""
+    import torch
+    wl, meshes, perms, v0, va, vb, b = _setup(S, C)
+    a0 = [t.clone() for t in va]
+    els = [torch.zeros(m.n_nodes, dtype=torch.int32, device="cuda") for m in meshes]
+    b.set_elem_out(els)
+
+    def run(mode, schedule, steps=3):
+        for t, s0 in zip(va, a0):
+            t.copy_(s0)
+        b.set_start(mode)
+        b.set_schedule(schedule, 128)
+        b.set_step(0)
+        out, walks = [], []
+        for _ in range(steps):
+            st = b.step(S.SLW_EULER, stats=True)
+            cur = va if b.get_step() % 2 == 0 else vb
+            out.append(([host(t).copy() for t in cur], [host(e).copy() for e in els]))
+            walks.append(st["walk_steps"])
+        return out, walks
+
+    ref, w_ref = run(S.START_STEERED, 0)
+    for schedule in (0, 1, 2):
+        got, w = run(S.START_PREV, schedule)
+        for (vr, er), (vg, eg) in zip(ref, got):
+            for x, y in zip(vr + er, vg + eg):
+                assert np.array_equal(x, y), schedule
+        if schedule == 0:
+            assert w[0] == w_ref[0]              # fresh meshes: no previous elements, steered
+        assert w[1] < 0.6 * w_ref[1] and w[2] < 0.6 * w_ref[2], (w, w_ref)
+    # the steps' elements are the oracle's (step 3 on each mesh, sampled)
+    for (xy, tri, fld, dt), p, e in zip(wl, perms, got[2][1]):
+        q = orc.feet(xy, fld, 3 * dt, dt, I.SCHEME_EULER)
+        r, _ = orc.locate(xy, tri, q)
+        assert (e == r[p]).mean() > 0.999
+    # graph replay with the previous-element start equals eager stepping
+    for t, s0 in zip(va, a0):
+        t.copy_(s0)
+    b.set_step(0)
+    for _ in range(4):
+        b.step(S.SLW_EULER)
+    stepped = [host(t).copy() for t in va]
+    for t, s0 in zip(va, a0):
+        t.copy_(s0)
+    b.set_step(0)
+    g = b.capture(2, S.SLW_EULER)
+    g.launch()
+    g.launch()
+    assert [np.array_equal(x, host(t)) for x, t in zip(stepped, va)] == [True] * len(va)
+    g.free()
+    # autotune keeps the previous elements: the next step walks as a twin's
+    wl2, meshes2, perms2, v02, va2, vb2, b2 = _setup(S, C)
+    b2.set_start(S.START_PREV)
+    for bb, vv, v0s in ((b, va, a0), (b2, va2, [t.clone() for t in va2])):
+        for t, s0 in zip(vv, v0s):
+            t.copy_(s0)
+        bb.set_schedule(0, 128)
+        bb.set_step(0)
+        bb.step(S.SLW_EULER)
+        bb.step(S.SLW_EULER)
+    b.autotune(S.SLW_EULER)
+    b.set_schedule(0, 128)
+    s1 = b.step(S.SLW_EULER, stats=True)
+    s2 = b2.step(S.SLW_EULER, stats=True)
+    assert s1["walk_steps"] == s2["walk_steps"] and s1["feet"] == s2["feet"]
+    with pytest.raises(S.SlwError):
+        b.set_start(S.START_GRID)
