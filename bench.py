@@ -551,6 +551,88 @@ def measure_cpu_walk(w, gpu_walk_ms=None):
     return out
 
 
+def _time_steps(mesh, fld, dt, scheme, v, steps=20, warmup=3, **kw):
+    """Kernel-inclusive ms per step (HIP events around `steps` steps on the
+    current stream) and the statistics of one more step."""
+    import torch
+    out = torch.empty_like(v)
+    for n in range(warmup):
+        mesh.step(fld, n * dt, dt, scheme, v, out, **kw)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for n in range(steps):
+        mesh.step(fld, n * dt, dt, scheme, v, out, **kw)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    _, st = mesh.step(fld, steps * dt, dt, scheme, v, out, stats=True, **kw)
+    return e0.elapsed_time(e1) / steps, st
+
+
+def measure_boundary(n=1001, alpha=5.0):
+    """The variable step at the boundary and non-convex domains (n x n
+    jittered grids, one FP64 field, Euler, Courant alpha, constant fields
+    that carry feet out of the domain): ms per step with affine Dirichlet
+    data (feet that leave take the datum at the first exit of their segment)
+    and without (the outside value), on the square (convex: the walk's exit
+    edge and the boundary loop decide), an L-shaped domain and a square with
+    a hole (a walk blocked by the boundary ends in the exact quadtree search;
+    exits are found by a scan of every boundary edge)."""
+    import torch
+    from paper_2104_09189_amd import inputs as I
+    from paper_2104_09189_amd import slwalk as S
+    ctx = S.Context(0)
+    h = 1.0 / (n - 1)
+    out = {"n": n, "alpha": alpha}
+    cases = (("square", I.jittered_grid(n, 9101), I.constant(0.6, 0.3)),
+             ("l_shaped", I.l_shaped(n, 9102), I.constant(-0.4, 0.4)),
+             ("hole", I.square_with_hole(n, 9103), I.constant(-0.4, 0.0)))
+    for name, (xy, tri), fld in cases:
+        mesh = S.Mesh(ctx, xy, tri, S.INTERNAL_ORDER)
+        v = torch.from_numpy(np.ascontiguousarray(I.gaussian_hill(xy)[mesh.dof_order()][:, None])).cuda()
+        speed = max(abs(fld.p[0]), abs(fld.p[1]))
+        dt = alpha * h / max(speed, 1e-9)
+        line = {"n_nodes": int(mesh.n_nodes), "n_tris": int(mesh.n_tris), "nonconvex": bool(mesh.nonconvex),
+                "boundary_loops": int(mesh.boundary_loops), "dt": dt}
+        for bc in ("none", "affine"):
+            if bc == "affine":
+                mesh.set_boundary(S.BC_AFFINE, (0.7, -1.3, 2.1, 0.5))
+            else:
+                mesh.set_boundary(S.BC_NONE)
+            ms, st = _time_steps(mesh, fld, dt, S.SLW_EULER, v)
+            line[bc] = {"ms_per_step": ms, "feet_per_s": mesh.n_nodes / (ms * 1e-3),
+                        "outside_share": st["outside"] / max(st["feet"], 1),
+                        "mean_walk_steps": st["walk_steps"] / max(st["feet"], 1),
+                        "exact_searches": st["boundary_searches"]}
+        mesh.free()
+        out[name] = line
+    return out
+
+
+def measure_p2(alpha=5.0):
+    """P1 against P2 (eq. barycoords' quadratic Lagrange basis, vertex and
+    edge-midpoint DOFs) on the 500 x 500 jittered mesh in Morton input order,
+    swirl, Euler, Courant alpha, one FP64 field: ms per step, DOFs per second
+    and the roofline fraction on each order's algorithmic bytes."""
+    import torch
+    from paper_2104_09189_amd import inputs as I
+    from paper_2104_09189_amd import slwalk as S
+    w = I.swirl_500(alpha=alpha, order="morton")
+    ctx = S.Context(0)
+    mesh = S.Mesh(ctx, w.xy, w.tri, S.INTERNAL_ORDER | S.P2)
+    out = {"workload": w.name, "n_nodes": int(mesh.n_nodes), "n_dofs": int(mesh.n_dofs), "n_tris": int(mesh.n_tris)}
+    for order, rows in ((1, mesh.n_nodes), (2, mesh.n_dofs)):
+        v = torch.from_numpy(np.random.default_rng(7).normal(size=(rows, 1))).cuda()
+        ms, st = _time_steps(mesh, w.field, w.dt, w.scheme, v, order=order)
+        ab = algorithmic_bytes(rows, mesh.n_tris, 16, 8, 1, order)
+        out[f"p{order}"] = {"ms_per_step": ms, "dofs_per_s": rows / (ms * 1e-3),
+                            "roofline_frac": ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                            "mean_walk_steps": st["walk_steps"] / max(st["feet"], 1)}
+    mesh.free()
+    return out
+
+
 def measure_locators(mesh, w, reps=10):
     """Point location alone on the feet of one step of the headline workload:
     the steered walk (strategy (a)), the walk from a bucket-grid start
@@ -610,6 +692,8 @@ def main():
     ap.add_argument("--only-learned", action="store_true",
                     help="measure the learned start on the graded mesh only (training included; for traces)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-start measurement")
+    ap.add_argument("--only-extra", action="store_true",
+                    help="measure the boundary and P2 lines only")
     ap.add_argument("--only-courant", action="store_true",
                     help="measure the Courant-range lines of the graded mesh only")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
@@ -651,6 +735,9 @@ def main():
     v0 = torch.from_numpy(np.ascontiguousarray(w.v0[perm])).to("cuda:0")
     n_feet = mesh.n_nodes
 
+    if args.only_extra:
+        print(json.dumps({"boundary": measure_boundary(), "p2": measure_p2()}), flush=True)
+        return
     if args.only_courant:
         print(json.dumps({"courant_range": measure_courant_range(mesh, w, v0), "workload": w.name}), flush=True)
         return
@@ -723,6 +810,8 @@ def main():
         if not args.no_cpu:
             out["cpu_walk"] = measure_cpu_walk(w, out["locators"].get("walk_steered_ms"))
         out["precision"] = measure_precision()
+        out["boundary"] = measure_boundary()
+        out["p2"] = measure_p2()
     if not args.no_batch and not args.only_a:
         out["batch"] = measure_batch()
     if not args.no_learned and not args.only_a:

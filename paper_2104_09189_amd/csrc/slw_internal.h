@@ -86,6 +86,13 @@ struct DevMesh {
     int nonconvex = 0;
     int n_loops = 0;               // boundary loops
     int32_t *bedge = nullptr;      // [n_boundary] internal node a of every boundary edge a -> bnext[a]
+    // non-convex domains: uniform grid over the boundary edges (bg_g x bg_g
+    // square cells of side bg_cell from (bg_x0, bg_y0)); cell c lists the
+    // indices into bedge of the edges whose padded bounding box meets it
+    int32_t *bg_ptr = nullptr;   // [bg_g^2 + 1]
+    int32_t *bg_list = nullptr;
+    int bg_g = 0;
+    double bg_x0 = 0.0, bg_y0 = 0.0, bg_cell = 1.0;
     // boundary data for feet outside the domain (variable step); kind 0: none
     int bc_kind = 0;
     double bc_p[4] = {0, 0, 0, 0};
@@ -277,6 +284,9 @@ struct MeshView {
     double qt_box[3];
     int qt_depth;
     const int32_t *bedge;
+    const int32_t *bg_ptr, *bg_list;
+    int bg_g;
+    double bg_x0, bg_y0, bg_cell;
     int bc_kind;
     double bc_p[4];
     // chart starts (null without a chart / network)

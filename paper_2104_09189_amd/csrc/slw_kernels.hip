@@ -173,6 +173,12 @@ MeshView view_of(const DevMesh &m)
         v.qt_box[i] = m.qt_box[i];
     v.qt_depth = m.qt_depth;
     v.bedge = m.bedge;
+    v.bg_ptr = m.bg_ptr;
+    v.bg_list = m.bg_list;
+    v.bg_g = m.bg_g;
+    v.bg_x0 = m.bg_x0;
+    v.bg_y0 = m.bg_y0;
+    v.bg_cell = m.bg_cell;
     v.chart_node = m.chart_node;
     v.chart_qx = m.chart_qx;
     v.chart_qy = m.chart_qy;
@@ -1501,7 +1507,8 @@ __device__ inline bool boundary_value_scan(const MeshView &mv, bool f32, double 
 {
     const double wx = qx - xx, wy = qy - xy;
     double best = INFINITY;
-    for (int64_t i = 0; i < mv.n_boundary; ++i) {
+    // outward crossing parameter of boundary edge i (the smaller into best)
+    auto test_edge = [&](int64_t i) {
         const int32_t a = mv.bedge[i], b = mv.bnext[a];
         double ax, ay, bx, by;
         if (f32) {
@@ -1514,10 +1521,49 @@ __device__ inline bool boundary_value_scan(const MeshView &mv, bool f32, double 
         const double ex = bx - ax, ey = by - ay, rx = ax - xx, ry = ay - xy;
         const double den = wx * ey - wy * ex;  // > 0: the segment crosses this edge's line outwards
         if (!(den > 0.0))
-            continue;
+            return;
         const double la = (rx * wy - ry * wx) / den, th = (rx * ey - ry * ex) / den;
         if (la >= 0.0 && la <= 1.0 && th >= -1e-12 && th <= 1.0 + 1e-12)
             best = fmin(best, th < 0.0 ? 0.0 : (th > 1.0 ? 1.0 : th));
+    };
+    if (!mv.bg_ptr) {
+        for (int64_t i = 0; i < mv.n_boundary; ++i)
+            test_edge(i);
+    } else {
+        // the cells of the edge grid in the order the segment meets them
+        // (Amanatides and Woo 1987); a crossing at theta lies in a cell the
+        // segment enters at or before theta, so once the best crossing
+        // precedes the current cell's exit no later cell can improve it
+        // (the margins absorb the rounding of the cell parameters; the
+        // edges' boxes are padded for the same reason)
+        const int G = mv.bg_g;
+        const double cell = mv.bg_cell;
+        int cx = (int)floor((xx - mv.bg_x0) / cell), cy = (int)floor((xy - mv.bg_y0) / cell);
+        cx = cx < 0 ? 0 : (cx >= G ? G - 1 : cx);
+        cy = cy < 0 ? 0 : (cy >= G ? G - 1 : cy);
+        const int sx = wx > 0.0 ? 1 : (wx < 0.0 ? -1 : 0), sy = wy > 0.0 ? 1 : (wy < 0.0 ? -1 : 0);
+        double tmx = sx > 0 ? (mv.bg_x0 + (cx + 1) * cell - xx) / wx
+                            : (sx < 0 ? (mv.bg_x0 + cx * cell - xx) / wx : INFINITY);
+        double tmy = sy > 0 ? (mv.bg_y0 + (cy + 1) * cell - xy) / wy
+                            : (sy < 0 ? (mv.bg_y0 + cy * cell - xy) / wy : INFINITY);
+        const double tdx = sx ? cell / fabs(wx) : INFINITY, tdy = sy ? cell / fabs(wy) : INFINITY;
+        for (int it = 0; it < 4 * G + 4; ++it) {  // a segment meets at most 2 G cells
+            const int c = cy * G + cx;
+            for (int32_t e = mv.bg_ptr[c]; e < mv.bg_ptr[c + 1]; ++e)
+                test_edge(mv.bg_list[e]);
+            const double texit = fmin(tmx, tmy);
+            if (best < texit - 1e-9 || texit >= 1.0)
+                break;
+            if (tmx < tmy) {
+                cx += sx;
+                tmx += tdx;
+            } else {
+                cy += sy;
+                tmy += tdy;
+            }
+            if (cx < 0 || cy < 0 || cx >= G || cy >= G)
+                break;
+        }
     }
     if (!(best <= 1.0))
         return false;

@@ -189,7 +189,7 @@ void free_mesh(DevMesh &m)
                     m.dof_int, m.tri_int, m.prev_elem, m.jump, m.chart_uv, m.chart_node, m.chart_table,
                     m.chart_qx, m.chart_qy, m.learned_start, m.bnext, m.bprev, m.qt_nodes, m.qt_lists,
                     m.forest_list1, m.forest_out1, m.forest_parent1, m.forest_list2, m.forest_out2,
-                    m.forest_parent2, m.forest_elem, m.bedge, m.grid};
+                    m.forest_parent2, m.forest_elem, m.bedge, m.grid, m.bg_ptr, m.bg_list};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -654,6 +654,45 @@ slw_status build_mesh(slw_ctx *ctx, const double *xy, int64_t n, const int32_t *
             if (bn[a] >= 0)
                 be.push_back((int32_t)a);
         UP(be, m.bedge);
+        if (nonconvex && !be.empty()) {
+            // uniform grid over the boundary edges, for the first exit of a
+            // segment from a non-convex domain (about one edge per cell)
+            const int gb = (int)std::min(1024.0, std::max(1.0, std::ceil(std::sqrt((double)be.size()))));
+            const double cell = span > 0 ? span / gb : 1.0;
+            const double pad = 1e-6 * (span > 0 ? span : 1.0);
+            auto cell_of = [&](double v, double o) {
+                return (int)std::min<double>(gb - 1, std::max(0.0, std::floor((v - o) / cell)));
+            };
+            std::vector<int32_t> ptr((size_t)gb * gb + 1, 0), list;
+            for (int pass = 0; pass < 2; ++pass) {
+                std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+                for (size_t i = 0; i < be.size(); ++i) {
+                    const int64_t ua = dof_u[be[i]], ub = dof_u[bn[be[i]]];
+                    const double x0 = std::min(X[2 * ua], X[2 * ub]) - pad, x1 = std::max(X[2 * ua], X[2 * ub]) + pad;
+                    const double y0 = std::min(X[2 * ua + 1], X[2 * ub + 1]) - pad,
+                                 y1 = std::max(X[2 * ua + 1], X[2 * ub + 1]) + pad;
+                    for (int cy = cell_of(y0, bb[1]); cy <= cell_of(y1, bb[1]); ++cy)
+                        for (int cx = cell_of(x0, bb[0]); cx <= cell_of(x1, bb[0]); ++cx) {
+                            const size_t c = (size_t)cy * gb + cx;
+                            if (pass == 0)
+                                ++ptr[c + 1];
+                            else
+                                list[fill[c]++] = (int32_t)i;
+                        }
+                }
+                if (pass == 0) {
+                    for (size_t c = 0; c + 1 < ptr.size(); ++c)
+                        ptr[c + 1] += ptr[c];
+                    list.resize((size_t)ptr.back());
+                }
+            }
+            UP(ptr, m.bg_ptr);
+            UP(list, m.bg_list);
+            m.bg_g = gb;
+            m.bg_x0 = bb[0];
+            m.bg_y0 = bb[1];
+            m.bg_cell = cell;
+        }
     }
     {
         // strategy (c)'s forest: roots = a maximal independent set of the

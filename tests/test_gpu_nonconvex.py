@@ -88,12 +88,15 @@ def test_nonconvex_p2_and_float_mesh(S, C, orc):
     assert (host(out["elem"]) == e_ref).all()
 
 
+@pytest.mark.parametrize("n", [65, 129])
 @pytest.mark.parametrize("name", ["L", "hole"])
-def test_nonconvex_boundary_data_first_exit(S, C, orc, name):
+def test_nonconvex_boundary_data_first_exit(S, C, orc, name, n):
     """The variable step: a foot outside gets the Dirichlet datum where the
     segment from its node first leaves the domain (it may re-enter across
-    the notch or the hole)."""
-    xy, tri = MESHES[name]()
+    the notch or the hole).  The first exit is found through the grid of
+    boundary edges (16 and 32 cells a side here), cell by cell along long
+    segments."""
+    xy, tri = MESHES[name]() if n == 65 else (I.l_shaped(n, 903) if name == "L" else I.square_with_hole(n, 904))
     mesh = S.Mesh(C, xy, tri)
     bc = (0.25, 1.5, -0.5, 0.75)
     mesh.set_boundary(S.BC_AFFINE, bc)
