@@ -289,6 +289,14 @@ slw_status slw_mesh_set_chain(slw_mesh *mesh, int length);
  * SLW_E_ARG outside 0 ... 4096. */
 slw_status slw_mesh_set_xcd_chunk(slw_mesh *mesh, int chunk);
 
+/* Schedule knob of the plain step (one foot per lane; starts steered, given
+ * or fixed; P1): each workgroup first copies `records` walk records around
+ * its tile (triangles and DOFs share the Morton order) into LDS, and its
+ * walks read the records of that window from LDS instead of memory.  0
+ * turns it off; default 512 (16 KB per workgroup); 64 ... 2048, else
+ * SLW_E_ARG.  Results never depend on it. */
+slw_status slw_mesh_set_lds_window(slw_mesh *mesh, int records);
+
 /* Jump-and-walk start grid (a bucketing start, Section 2.1's prior art;
  * Muecke, Saias and Zhu 1996): g x g square cells over the mesh's bounding
  * box (side = the box's longer side / g), each recording a triangle that
@@ -359,7 +367,9 @@ slw_status slw_step(slw_mesh *mesh, const slw_field *field, double t_n, double d
  * starts; the threshold of slw_mesh_set_hybrid (0.5 ... 64) for
  * SLW_START_HYBRID; the forest or chain length of slw_mesh_set_chain (0, 2,
  * 4, 8, 16) for SLW_START_NEIGHBOR -- then, for the value chosen, the XCD
- * chunk of slw_mesh_set_xcd_chunk (0, 16, 32, 64, 128); each candidate
+ * chunk of slw_mesh_set_xcd_chunk (0, 16, 32, 64, 128), then for the plain
+ * step (one foot per lane; steered, given or fixed starts; P1) the LDS
+ * window of slw_mesh_set_lds_window (0, 256, 512, 768); each candidate
  * timed over five consecutive steps from t_n (the median), after one untimed
  * step from t_n - dt that starts from the mesh's previous elements (the
  * hybrid's skip counts cleared).  It keeps only candidates whose step is
@@ -374,7 +384,8 @@ slw_status slw_step(slw_mesh *mesh, const slw_field *field, double t_n, double d
  * restored afterwards; the caller's v_in is only read.  Allocates a private
  * output buffer; synchronous.  value_out / xcd_chunk_out / ms_out
  * (nullable): the knob value and XCD chunk chosen and their median time per
- * step (ms; the cached time when the cache answered). */
+ * step (ms; the cached time when the cache answered); the LDS window chosen
+ * is applied to the mesh (and cached) too. */
 slw_status slw_step_autotune(slw_mesh *mesh, const slw_field *field, double t_n, double dt, int scheme, int order,
                              int start_mode, const int32_t *start, const void *v_in, int vdtype, int k,
                              const char *cache_path, double *value_out, int32_t *xcd_chunk_out, double *ms_out);

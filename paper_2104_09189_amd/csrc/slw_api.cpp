@@ -458,6 +458,16 @@ slw_status slw_mesh_set_hybrid(slw_mesh *mesh, float far)
     return SLW_OK;
 }
 
+slw_status slw_mesh_set_lds_window(slw_mesh *mesh, int records)
+{
+    if (!mesh)
+        return set_error(SLW_E_ARG, "mesh is NULL");
+    if (records != 0 && (records < 64 || records > 2048))
+        return set_error(SLW_E_ARG, "slw_mesh_set_lds_window: records must be 0 or 64 ... 2048");
+    mesh->m.lds_w = records;
+    return SLW_OK;
+}
+
 slw_status slw_mesh_build_grid(slw_mesh *mesh, int g)
 {
     if (!mesh)
@@ -1301,6 +1311,12 @@ const char *knob_name(int mode)
 
 // XCD chunks the step autotuner tries (slw_mesh_set_xcd_chunk)
 constexpr int kXcdChunks[] = {0, 16, 32, 64, 128};
+// LDS windows it tries (slw_mesh_set_lds_window) for the plain step's modes
+constexpr int kLdsWindows[] = {0, 256, 512, 768};
+bool plain_step_mode(int mode)
+{
+    return mode == SLW_START_STEERED || mode == SLW_START_GIVEN || mode == SLW_START_FIXED;
+}
 
 std::vector<double> knob_values(int mode, bool bc)
 {
@@ -1349,6 +1365,7 @@ extern "C" slw_status slw_step_autotune(slw_mesh *mesh, const slw_field *field, 
     const size_t bytes = (size_t)rows * (size_t)(k > 0 ? k : 1) * vsz;
     const double saved = knob_get(m, start_mode);
     const int saved_chunk = m.xcd_chunk;
+    const int saved_lds = m.lds_w;
     const bool keeps_prev = start_mode == SLW_START_PREV || start_mode == SLW_START_HYBRID;
     void *vout = nullptr;
     int32_t *prev0 = nullptr;
@@ -1432,6 +1449,8 @@ extern "C" slw_status slw_step_autotune(slw_mesh *mesh, const slw_field *field, 
                 double cc = 0.0;
                 if (cache_lookup_num(cache_path, sig, "xcd_chunk", cc) && cc >= 0.0 && cc <= 4096.0)
                     m.xcd_chunk = (int)cc;
+                if (cache_lookup_num(cache_path, sig, "lds_window", cc) && (cc == 0.0 || (cc >= 64.0 && cc <= 2048.0)))
+                    m.lds_w = (int)cc;
                 if (value_out)
                     *value_out = cached;
                 if (xcd_chunk_out)
@@ -1488,7 +1507,7 @@ extern "C" slw_status slw_step_autotune(slw_mesh *mesh, const slw_field *field, 
     // first the mode's own knob (at the mesh's XCD chunk), then the XCD chunk
     // for the chosen value
     double best_v = saved, best_ms = 1e300;
-    int best_c = saved_chunk;
+    int best_c = saved_chunk, best_l = saved_lds;
     for (double v : knob_values(start_mode, m.bc_kind != 0 || m.nonconvex != 0)) {
         if (st != SLW_OK)
             break;
@@ -1513,6 +1532,21 @@ extern "C" slw_status slw_step_autotune(slw_mesh *mesh, const slw_field *field, 
                 best_c = c;
             }
         }
+        // then the LDS window of the plain step (one foot per lane)
+        m.xcd_chunk = best_c;
+        if (plain_step_mode(start_mode) && best_v <= 1.0 && order == 1)
+            for (int lw : kLdsWindows) {
+                if (st != SLW_OK)
+                    break;
+                if (lw == saved_lds)
+                    continue;  // timed above
+                m.lds_w = lw;
+                float ms = 0.f;
+                if (time_candidate(ms) && ms < best_ms) {
+                    best_ms = ms;
+                    best_l = lw;
+                }
+            }
     }
     // the caller's previous elements are left as they were
     slw_status st2 = restore_prev();
@@ -1521,6 +1555,7 @@ extern "C" slw_status slw_step_autotune(slw_mesh *mesh, const slw_field *field, 
     release();
     knob_set(m, start_mode, st == SLW_OK ? best_v : saved);
     m.xcd_chunk = st == SLW_OK ? best_c : saved_chunk;
+    m.lds_w = st == SLW_OK ? best_l : saved_lds;
     if (st != SLW_OK)
         return st;
     if (st2 != SLW_OK)
@@ -1528,7 +1563,7 @@ extern "C" slw_status slw_step_autotune(slw_mesh *mesh, const slw_field *field, 
     if (cache_path) {
         std::ostringstream body;
         body << "\"" << knob_name(start_mode) << "\": " << best_v << ", \"xcd_chunk\": " << best_c
-             << ", \"ms\": " << best_ms;
+             << ", \"lds_window\": " << best_l << ", \"ms\": " << best_ms;
         cache_store_entry(cache_path, sig, body.str());
     }
     if (value_out)

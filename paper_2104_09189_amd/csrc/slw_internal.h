@@ -123,6 +123,7 @@ struct DevMesh {
     int repack = 0;  // step kernel: 0 one foot per lane; 2, 4, 8: chunks of 64 x repack feet per wavefront
     int chain = 0;   // strategy (c): 0 the mesh forest below; 2, 4, 8, 16 Morton chains of that length per lane
     int xcd_chunk = 64;  // tiles per XCD turn: 0 one contiguous range of tiles per XCD; C > 0 chunks of C tiles dealt round-robin
+    int lds_w = 512;     // walk records staged in LDS per workgroup by the plain step (0: none)
     // strategy (c)'s forest (depth one): roots = a maximal independent set of
     // the nodes (greedy in internal order), every other DOF a child of an
     // adjacent root.  List = roots then children, each part in internal
@@ -273,6 +274,7 @@ struct MeshView {
     int32_t step_cap, hard_limit;
     float hybrid_far;
     int xcd_chunk;
+    int lds_w;
     // variable step at the boundary (bc_kind 0: off)
     const int32_t *bnext, *bprev;
     int64_t n_boundary;

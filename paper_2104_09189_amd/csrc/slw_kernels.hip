@@ -160,6 +160,7 @@ MeshView view_of(const DevMesh &m)
     // start the mesh has (one grid read; two binary searches; the steered start)
     v.hybrid_far = m.hybrid_far > 0.0f ? m.hybrid_far : (m.grid ? 1.0f : (m.chart_table ? 16.0f : 64.0f));
     v.xcd_chunk = m.xcd_chunk;
+    v.lds_w = m.lds_w;
     v.bnext = m.bnext;
     v.bprev = m.bprev;
     v.n_boundary = m.n_boundary;
@@ -733,11 +734,12 @@ __device__ inline int first_test(const MeshView &mv, int32_t j, typename CT<F32>
 }
 
 // Barycentric walk of Section 2.2 from triangle j to the foot q, then the tie
-// rule, then the weights.
-template <bool F32>
-__device__ WalkResult<typename CT<F32>::R> walk(const MeshView &mv, int32_t j, typename CT<F32>::R qx,
-                                                 typename CT<F32>::R qy, uint32_t seed, Counters &c,
-                                                 bool likely_stop = false)
+// rule, then the weights; fetch(t) gives triangle t's walk record.
+template <bool F32, typename Fetch>
+__device__ __forceinline__ WalkResult<typename CT<F32>::R> walk_with(const MeshView &mv, int32_t j,
+                                                                     typename CT<F32>::R qx, typename CT<F32>::R qy,
+                                                                     uint32_t seed, Counters &c, bool likely_stop,
+                                                                     Fetch fetch)
 {
     const float qfx = F32 ? (float)qx : (float)((double)qx - mv.fc.cx);
     const float qfy = F32 ? (float)qy : (float)((double)qy - mv.fc.cy);
@@ -770,12 +772,32 @@ __device__ WalkResult<typename CT<F32>::R> walk(const MeshView &mv, int32_t j, t
     // stay out of the hot loop
     const int32_t fast_lim = mv.step_cap < mv.hard_limit ? mv.step_cap : mv.hard_limit;
     while (steps < fast_lim) {
-        r = mv.wrec[j];
+        r = fetch(j);
         st = det_move<F32>(mv, j, r, zmask, qfx, qfy, qx, qy, steps, c);
         if (st != 0)
             break;
     }
     return walk_end<F32>(mv, j, r, zmask, qfx, qfy, qx, qy, seed, steps, flags, st, c);
+}
+
+template <bool F32>
+__device__ WalkResult<typename CT<F32>::R> walk(const MeshView &mv, int32_t j, typename CT<F32>::R qx,
+                                                 typename CT<F32>::R qy, uint32_t seed, Counters &c,
+                                                 bool likely_stop = false)
+{
+    return walk_with<F32>(mv, j, qx, qy, seed, c, likely_stop, [&](int32_t t) { return mv.wrec[t]; });
+}
+
+// The walk of the staged-window step: the records of triangles
+// [lbase, lbase + lcount) come from the workgroup's copy in LDS.
+template <bool F32>
+__device__ WalkResult<typename CT<F32>::R> walk_win(const MeshView &mv, int32_t j, typename CT<F32>::R qx,
+                                                     typename CT<F32>::R qy, uint32_t seed, Counters &c,
+                                                     const WalkRec *lw, int32_t lbase, int32_t lcount)
+{
+    return walk_with<F32>(mv, j, qx, qy, seed, c, false, [&](int32_t t) {
+        return (uint32_t)(t - lbase) < (uint32_t)lcount ? lw[t - lbase] : mv.wrec[t];
+    });
 }
 
 __device__ inline unsigned long long wave_sum(unsigned long long v)
@@ -1537,30 +1559,29 @@ __device__ inline bool boundary_value_scan(const MeshView &mv, bool f32, double 
         // (the margins absorb the rounding of the cell parameters; the
         // edges' boxes are padded for the same reason)
         const int G = mv.bg_g;
-        const double cell = mv.bg_cell;
-        int cx = (int)floor((xx - mv.bg_x0) / cell), cy = (int)floor((xy - mv.bg_y0) / cell);
+        // in units of cells from the grid's corner, in float: the order of
+        // the cells needs no more (the margins and the padding absorb it)
+        const float ux = (float)((xx - mv.bg_x0) / mv.bg_cell), uy = (float)((xy - mv.bg_y0) / mv.bg_cell);
+        const float vx = (float)(wx / mv.bg_cell), vy = (float)(wy / mv.bg_cell);
+        int cx = (int)floorf(ux), cy = (int)floorf(uy);
         cx = cx < 0 ? 0 : (cx >= G ? G - 1 : cx);
         cy = cy < 0 ? 0 : (cy >= G ? G - 1 : cy);
-        const int sx = wx > 0.0 ? 1 : (wx < 0.0 ? -1 : 0), sy = wy > 0.0 ? 1 : (wy < 0.0 ? -1 : 0);
-        double tmx = sx > 0 ? (mv.bg_x0 + (cx + 1) * cell - xx) / wx
-                            : (sx < 0 ? (mv.bg_x0 + cx * cell - xx) / wx : INFINITY);
-        double tmy = sy > 0 ? (mv.bg_y0 + (cy + 1) * cell - xy) / wy
-                            : (sy < 0 ? (mv.bg_y0 + cy * cell - xy) / wy : INFINITY);
-        const double tdx = sx ? cell / fabs(wx) : INFINITY, tdy = sy ? cell / fabs(wy) : INFINITY;
+        const int sx = vx > 0.f ? 1 : (vx < 0.f ? -1 : 0), sy = vy > 0.f ? 1 : (vy < 0.f ? -1 : 0);
         for (int it = 0; it < 4 * G + 4; ++it) {  // a segment meets at most 2 G cells
             const int c = cy * G + cx;
             for (int32_t e = mv.bg_ptr[c]; e < mv.bg_ptr[c + 1]; ++e)
                 test_edge(mv.bg_list[e]);
-            const double texit = fmin(tmx, tmy);
-            if (best < texit - 1e-9 || texit >= 1.0)
+            // where the segment leaves this cell, from the cell's own lines
+            // (no accumulated increments: a few ulps of error)
+            const float tmx = sx > 0 ? ((float)(cx + 1) - ux) / vx : (sx < 0 ? ((float)cx - ux) / vx : INFINITY);
+            const float tmy = sy > 0 ? ((float)(cy + 1) - uy) / vy : (sy < 0 ? ((float)cy - uy) / vy : INFINITY);
+            const float texit = fminf(tmx, tmy);
+            if (best < (double)texit - 1e-5 || texit >= 1.f)
                 break;
-            if (tmx < tmy) {
+            if (tmx < tmy)
                 cx += sx;
-                tmx += tdx;
-            } else {
+            else
                 cy += sy;
-                tmy += tdy;
-            }
             if (cx < 0 || cy < 0 || cx >= G || cy >= G)
                 break;
         }
@@ -1586,7 +1607,8 @@ __device__ inline void step_wave(const MeshView &mv, const FieldDev &f, double d
                                  const int32_t *__restrict__ start, const V *__restrict__ vin, int k,
                                  V *__restrict__ vout, double outside, int write_prev,
                                  const int32_t *__restrict__ out_map, int32_t *__restrict__ elem_out,
-                                 int64_t n_iter, int64_t base, DevStats *st, ForestView fv = ForestView())
+                                 int64_t n_iter, int64_t base, DevStats *st, ForestView fv = ForestView(),
+                                 const WalkRec *lw = nullptr, int32_t lbase = 0, int32_t lcount = 0)
 {
     using R = typename CT<F32>::R;
     using R2 = typename CT<F32>::R2;
@@ -1703,7 +1725,10 @@ __device__ inline void step_wave(const MeshView &mv, const FieldDev &f, double d
                 j0 = sid >= 0 ? sid : quadrant_start(mv.qstart[d], (float)(qx - x.x), (float)(qy - x.y));
             else if constexpr (KIND < 0)
                 j0 = start_pick<KIND == -6>(mv, d, sid, mode, x, qx, qy);
-            w = walk<F32>(mv, j0, qx, qy, (uint32_t)d * 2654435761u, ls.c, KIND == -2);
+            if constexpr (KIND == -7)
+                w = walk_win<F32>(mv, j0, qx, qy, (uint32_t)d * 2654435761u, ls.c, lw, lbase, lcount);
+            else
+                w = walk<F32>(mv, j0, qx, qy, (uint32_t)d * 2654435761u, ls.c, KIND == -2);
         }
         if constexpr (KIND == -3)
             fv.elem[d] = w.elem;
@@ -1745,7 +1770,7 @@ __device__ inline void step_wave(const MeshView &mv, const FieldDev &f, double d
 // slower).  The others keep the compiler's choice (the plain step takes 66
 // registers, seven wavefronts; forcing eight spills one value and measured
 // slower).
-constexpr int step_waves_per_eu(int kind) { return kind == -2 ? 7 : (kind == 2 ? 4 : 1); }
+constexpr int step_waves_per_eu(int kind) { return kind == -2 || kind == -7 ? 7 : (kind == 2 ? 4 : 1); }
 
 template <bool F32, typename V, int NA, int KIND = -1>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(step_waves_per_eu(KIND))))
@@ -1754,9 +1779,29 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(ste
            const int32_t *__restrict__ out_map, int32_t *__restrict__ elem_out, int64_t n_iter, DevStats *st,
            ForestView fv)
 {
-    const int64_t base = xcd_tile(blockIdx.x, gridDim.x, mv.xcd_chunk) * kBlock + (threadIdx.x & ~(kWave - 1));
-    step_wave<F32, V, NA, KIND>(mv, f, dt, t_np1, scheme, mode, start, vin, k, vout, outside, write_prev, out_map,
-                                elem_out, n_iter, base, st, fv);
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x, mv.xcd_chunk);
+    const int64_t base = tile * kBlock + (threadIdx.x & ~(kWave - 1));
+    if constexpr (KIND == -7) {
+        // The staged-window step: the workgroup first copies the lds_w walk
+        // records around its tile (centred on an incident triangle of the
+        // tile's middle DOF; triangles and DOFs share the Morton order) into
+        // LDS, and its walks read the records of that window from there.
+        extern __shared__ WalkRec win[];
+        int64_t mid = tile * kBlock + kBlock / 2;
+        mid = mid < n_iter ? mid : n_iter - 1;
+        const int32_t lc = mv.n_tris < (int64_t)mv.lds_w ? (int32_t)mv.n_tris : mv.lds_w;
+        int32_t lb = mv.qstart[mid].x - lc / 2;
+        lb = lb < 0 ? 0 : lb;
+        lb = lb > (int32_t)mv.n_tris - lc ? (int32_t)mv.n_tris - lc : lb;
+        for (int i = threadIdx.x; i < lc; i += kBlock)
+            win[i] = mv.wrec[lb + i];
+        __syncthreads();
+        step_wave<F32, V, NA, KIND>(mv, f, dt, t_np1, scheme, mode, start, vin, k, vout, outside, write_prev,
+                                    out_map, elem_out, n_iter, base, st, fv, win, lb, lc);
+    } else {
+        step_wave<F32, V, NA, KIND>(mv, f, dt, t_np1, scheme, mode, start, vin, k, vout, outside, write_prev,
+                                    out_map, elem_out, n_iter, base, st, fv);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -2568,6 +2613,10 @@ hipError_t launch_step(const DevMesh &m, hipStream_t st, const FieldDev &f0, dou
             hipLaunchKernelGGL((k_step<F32, V, NA, -6>), dim3(g), dim3(kBlock), 0, st, mv, f, dt, t_n + dt, scheme, \
                                mode, start, (const V *)v_in, k, (V *)v_out, outside, (int)write_prev, out_map,   \
                                elem_out, n_iter, stats, ForestView());                                         \
+        else if (NA == 3 && m.lds_w > 0)                                                                       \
+            hipLaunchKernelGGL((k_step<F32, V, NA, -7>), dim3(g), dim3(kBlock), (size_t)m.lds_w * sizeof(WalkRec),  \
+                               st, mv, f, dt, t_n + dt, scheme, mode, start, (const V *)v_in, k, (V *)v_out,    \
+                               outside, (int)write_prev, out_map, elem_out, n_iter, stats, ForestView());       \
         else                                                                                                   \
             hipLaunchKernelGGL((k_step<F32, V, NA>), dim3(g), dim3(kBlock), 0, st, mv, f, dt, t_n + dt, scheme, mode, \
                                start, (const V *)v_in, k, (V *)v_out, outside, (int)write_prev, out_map, elem_out, \

@@ -108,6 +108,7 @@ _sig("slw_walk_codes_host", ctypes.c_int, [_vp, _i64, ctypes.c_int, _vp])
 _sig("slw_mesh_set_chain", ctypes.c_int, [_vp, ctypes.c_int])
 _sig("slw_mesh_set_xcd_chunk", ctypes.c_int, [_vp, ctypes.c_int])
 _sig("slw_mesh_build_grid", ctypes.c_int, [_vp, ctypes.c_int])
+_sig("slw_mesh_set_lds_window", ctypes.c_int, [_vp, ctypes.c_int])
 _sig("slw_mesh_set_hybrid", ctypes.c_int, [_vp, ctypes.c_float])
 _sig("slw_mesh_set_boundary", ctypes.c_int, [_vp, ctypes.c_int, _vp])
 _sig("slw_locate", ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, _vp, _vp])
@@ -166,7 +167,7 @@ MLP_PARAMS = 5 * 64 + 64 + 64 * 64 + 64 + 64 * 2 + 2
 
 EXPORTED = ["slw_status_string", "slw_last_error", "slw_ctx_create", "slw_ctx_set_stream", "slw_ctx_destroy",
             "slw_mesh_upload", "slw_mesh_check", "slw_mesh_free", "slw_mesh_get_info", "slw_mesh_dof_coords", "slw_mesh_dof_order",
-            "slw_mesh_set_walk_limits", "slw_mesh_set_repack", "slw_mesh_set_neighbour_codes", "slw_walk_codes_host", "slw_mesh_set_chain", "slw_mesh_set_xcd_chunk", "slw_mesh_build_grid", "slw_mesh_set_hybrid", "slw_mesh_set_boundary", "slw_locate", "slw_locate_feet", "slw_interpolate", "slw_step",
+            "slw_mesh_set_walk_limits", "slw_mesh_set_repack", "slw_mesh_set_neighbour_codes", "slw_walk_codes_host", "slw_mesh_set_chain", "slw_mesh_set_xcd_chunk", "slw_mesh_build_grid", "slw_mesh_set_lds_window", "slw_mesh_set_hybrid", "slw_mesh_set_boundary", "slw_locate", "slw_locate_feet", "slw_interpolate", "slw_step",
             "slw_step_noalloc", "slw_step_autotune", "slw_permute_rows", "slw_orient_sign_host",
             "slw_float_filter_host", "slw_batch_create", "slw_batch_free", "slw_batch_set_fields",
             "slw_batch_set_values", "slw_batch_set_elem_out", "slw_batch_set_step", "slw_batch_get_step", "slw_batch_set_start", "slw_batch_set_schedule",
@@ -331,6 +332,10 @@ class Mesh:
 
     def set_xcd_chunk(self, chunk: int):
         _check(_lib.slw_mesh_set_xcd_chunk(self.h, int(chunk)), "slw_mesh_set_xcd_chunk")
+
+    def set_lds_window(self, records: int):
+        """slw_mesh_set_lds_window: walk records staged in LDS per workgroup (0: none)."""
+        _check(_lib.slw_mesh_set_lds_window(self.h, int(records)), "slw_mesh_set_lds_window")
 
     def build_grid(self, g: int):
         """slw_mesh_build_grid: the jump-and-walk start grid (g x g cells; 0 removes it)."""

@@ -57,7 +57,8 @@ def test_step_autotune_modes_cache_and_state(S, C, tmp_path):
     assert np.array_equal(host(vin), before)
     data = json.loads(cache.read_text())
     assert len(data) == 3
-    assert all("xcd_chunk" in e for e in data.values())
+    assert all("xcd_chunk" in e and "lds_window" in e for e in data.values())
+    assert all(e["lds_window"] in (0, 256, 512, 768) for e in data.values())
     # a second call answers from the cache, with the same choice, on a
     # mesh whose XCD chunk was changed meanwhile
     for mode, (val, chunk) in choices.items():
