@@ -769,16 +769,16 @@ def main():
         "config": {"workload": w.name, "n_nodes": int(n_feet), "n_tris": int(mesh.n_tris), "alpha": args.alpha,
                    "k_fields": args.k, "coords": "f64", "values": "f32", "order": 1, "scheme": "rk2",
                    "start": "strategy (a): incident triangle facing the foot", "parallelism": "none (1 GPU)"},
-        "schedule": {"feet_per_lane": 1, "xcd_chunk": 64,
+        "schedule": {"feet_per_lane": 1, "xcd_chunk": 64, "lds_window": 512,
                      "note": "library defaults: one foot per lane; chunks of 64 tiles of 256 nodes dealt to the "
-                             "8 XCDs in turn"},
+                             "8 XCDs in turn; 512 walk records around each tile staged in LDS"},
         "field_values_per_s": value * args.k,
         "mean_walk_steps": st["walk_steps"] / max(st["feet"], 1),
         "walk": {**{k: st[k] for k in ("max_steps", "outside", "exact_tests", "fp64_tests", "fallback_walks",
                                        "edge_ties", "vertex_ties")},
                  "step_hist": hist_dict(st["step_hist"])},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_step<false, float, 3, -1>",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_step<false, float, 3, -7>",
                      "kernel_ms": ra["kernel_ms"], "algorithmic_bytes_per_launch": abytes},
         "upload_s": upload_s,
         "wall_s": ra["wall_s"],
