@@ -263,9 +263,9 @@ slw_status slw_mesh_set_boundary(slw_mesh *mesh, int kind, const double *p_h);
  * tree).  The paper's breadth-first tree has about sqrt(N) sequential levels;
  * the spanning forests used here are shallow:
  *   length 0 (the default): a forest of depth one built at upload.  Its
- *     roots are a maximal independent set of the mesh's nodes (greedy in
- *     internal order: about a quarter of them); every other DOF is a child of
- *     the nearest root among the vertices of its incident triangles.  The
+ *     roots are nodes no two of which lie within three hops (mesh edges) of
+ *     each other (greedy in internal order, a maximal such set); every other
+ *     DOF is a child of the nearest root within three hops.  The
  *     roots are stepped first (from their cell of the start grid when the mesh
  *     has one, slw_mesh_build_grid, else strategy (a)), then the children, each
  *     from its parent's element unless its own node lies nearer its foot than

@@ -1641,7 +1641,7 @@ __device__ inline void step_wave(const MeshView &mv, const FieldDev &f, double d
         int32_t p = -1;
         if constexpr (KIND == -4) {
             // strategy (c): the element found for this DOF's parent (a root
-            // adjacent to it in the mesh) by the roots' launch
+            // within three hops of it in the mesh) by the roots' launch
             p = fv.parent[pos];
             sid = p >= 0 ? fv.elem[p] : -1;
         } else if constexpr (KIND == -5) {
