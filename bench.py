@@ -246,6 +246,31 @@ def measure_k_reuse(mesh, w, v0, reps=20):
     return {"k_fields": k, "one_location_ms": t_k, "separate_locations_ms": t_1, "speedup": t_1 / t_k}
 
 
+def measure_decomposition(mesh, w, v0, steps=20, warmup=3):
+    """Where a step's time goes: strategy (a) and strategy (b) (almost no
+    moves: the previous step's element), each with all K fields and with
+    the first field alone, on the same mesh, feet and launch configuration.
+    (a) minus (b) with one field is the cost of the walk's moves; (a) with K
+    fields minus (a) with one is the cost of the other K - 1 fields; (b)
+    with one field is the rest (coordinates, starts, feet, vertex ids, one
+    field).  ms per step, HIP events around `steps` steps, after one
+    untimed run of the first configuration."""
+    from paper_2104_09189_amd import slwalk as S
+    k = v0.shape[1]
+    v1 = v0[:, :1].contiguous()
+    out = {"k_fields": k}
+    _time_steps(mesh, w.field, w.dt, w.scheme, v0, steps, warmup)  # clocks up before the first timed run
+    for name, mode in (("a", S.START_STEERED), ("b", S.START_PREV)):
+        for tag, v in ((f"k{k}", v0), ("k1", v1)):
+            ms, st = _time_steps(mesh, w.field, w.dt, w.scheme, v, steps, warmup, start_mode=mode)
+            out[f"{name}_{tag}_ms"] = ms
+        out[f"{name}_mean_walk_steps"] = st["walk_steps"] / max(st["feet"], 1)
+    out["walk_moves_ms"] = out["a_k1_ms"] - out["b_k1_ms"]
+    out["other_fields_ms"] = out[f"a_k{k}_ms"] - out["a_k1_ms"]
+    out["rest_ms"] = out["b_k1_ms"]
+    return out
+
+
 def measure_batch(steps=100):
     """64 jittered meshes, triangle counts log-uniform in [1e4, 5e5], own swirl
     period each, Courant 5, Euler, float coordinates (float filter, FP64 and
@@ -694,6 +719,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-start measurement")
     ap.add_argument("--only-extra", action="store_true",
                     help="measure the boundary and P2 lines only")
+    ap.add_argument("--only-decomp", action="store_true",
+                    help="only the decomposition of the step's time (strategies (a) and (b), K fields and one)")
     ap.add_argument("--only-courant", action="store_true",
                     help="measure the Courant-range lines of the graded mesh only")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
@@ -740,6 +767,9 @@ def main():
         return
     if args.only_courant:
         print(json.dumps({"courant_range": measure_courant_range(mesh, w, v0), "workload": w.name}), flush=True)
+        return
+    if args.only_decomp:
+        print(json.dumps({"decomposition": measure_decomposition(mesh, w, v0), "workload": w.name}), flush=True)
         return
     if args.only_b:
         rb = measure(mesh, w, v0, args.steps, args.warmup, S.START_PREV)
@@ -806,6 +836,7 @@ def main():
         mesh.set_chain(0)
         out["courant_range"] = measure_courant_range(mesh, w, v0)
         out["k_field_reuse"] = measure_k_reuse(mesh, w, v0)
+        out["decomposition"] = measure_decomposition(mesh, w, v0)
         out["locators"] = measure_locators(mesh, w)
         if not args.no_cpu:
             out["cpu_walk"] = measure_cpu_walk(w, out["locators"].get("walk_steered_ms"))
