@@ -27,6 +27,7 @@ import json
 import os
 import re
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -482,6 +483,17 @@ def wave_walks(mesh, w, t_n, mode) -> dict:
     return _walk_histogram(st)
 
 
+def _library_defaults(mesh):
+    """The step's settings as a fresh mesh has them (one foot per lane, the
+    forest, the automatic hybrid threshold, chunks of 64 tiles per XCD turn,
+    512 walk records in LDS)."""
+    mesh.set_repack(0)
+    mesh.set_chain(0)
+    mesh.set_hybrid(0.0)
+    mesh.set_xcd_chunk(64)
+    mesh.set_lds_window(512)
+
+
 def measure_courant_range(mesh, w, v0, steps=20, warmup=3, alphas=(1.0, 5.0, 20.0, 50.0, 100.0), chart_g=2048,
                           grid_g=16384):
     """The graded mesh across its Courant range: strategy (a) (steered
@@ -509,11 +521,10 @@ def measure_courant_range(mesh, w, v0, steps=20, warmup=3, alphas=(1.0, 5.0, 20.
                            ("c_forest", S.START_NEIGHBOR), ("chart_exact", S.START_CHART),
                            ("grid", S.START_GRID), ("hybrid", S.START_HYBRID)):
             # the library's defaults: one foot per lane, the forest, hybrid
-            # threshold automatic (0), chunks of 64 tiles per XCD turn
-            mesh.set_repack(0)
-            mesh.set_chain(0)
-            mesh.set_hybrid(0.0)
-            mesh.set_xcd_chunk(64)
+            # threshold automatic (0), chunks of 64 tiles per XCD turn, 512
+            # walk records staged in LDS (the autotuner below leaves its
+            # choices set on the mesh)
+            _library_defaults(mesh)
             r = measure(mesh, wa, v0, steps, warmup, mode)
             # walk lengths of the step ending near t = 1/4 (the swirl's time
             # factor cos(pi t) is 0.7 there; it vanishes at t = 1/2)
@@ -530,15 +541,15 @@ def measure_courant_range(mesh, w, v0, steps=20, warmup=3, alphas=(1.0, 5.0, 20.
             t_tune = max(round(0.25 / dt) - 1, 1) * dt
             if mode in (S.START_PREV, S.START_HYBRID):
                 mesh.step(wa.field, t_tune - dt, dt, wa.scheme, v0, start_mode=mode)
-            knob, chunk, _ = mesh.autotune_step(wa.field, t_tune, dt, wa.scheme, v0, start_mode=mode,
-                                                with_chunk=True)
+            with tempfile.TemporaryDirectory() as tmp:
+                cache = os.path.join(tmp, "tune.json")
+                knob, chunk, _ = mesh.autotune_step(wa.field, t_tune, dt, wa.scheme, v0, start_mode=mode,
+                                                    cache_path=cache, with_chunk=True)
+                m = re.search(r'"lds_window":\s*(\d+)', open(cache).read())
             rt = measure(mesh, wa, v0, steps, warmup, mode)
-            line[name]["tuned"] = {"knob": knob, "xcd_chunk": chunk, "ms_per_step": rt["ms_per_step"],
-                                   "kernel_ms": rt["kernel_ms"]}
-        mesh.set_repack(0)
-        mesh.set_chain(0)
-        mesh.set_hybrid(0.0)
-        mesh.set_xcd_chunk(64)
+            line[name]["tuned"] = {"knob": knob, "xcd_chunk": chunk, "lds_window": int(m.group(1)) if m else None,
+                                   "ms_per_step": rt["ms_per_step"], "kernel_ms": rt["kernel_ms"]}
+        _library_defaults(mesh)
         best = min((v["kernel_ms"], k) for k, v in line.items() if k != "dt")
         line["fastest"] = best[1]
         out[f"alpha_{alpha:g}"] = line
